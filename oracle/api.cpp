@@ -1,0 +1,166 @@
+// Oracle: C entry points.  Test infrastructure only.
+#include <cstring>
+#include <vector>
+
+#include "oracle.h"
+#include "procs.hpp"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+using namespace orc;
+
+namespace {
+int gluon_count(int proc) {
+  switch (proc) {
+    case OR_GG_GG: return 4;
+    case OR_GG_GGG: return 5;
+    case OR_GG_4G: return 6;
+    default: return 0;
+  }
+}
+void load(const double* mom, int nl, Vec4* p) {
+  for (int k = 0; k < nl; ++k)
+    for (int m = 0; m < 4; ++m) p[k][m] = mom[4 * k + m];
+}
+}  // namespace
+
+extern "C" int or_nlegs(int proc) {
+  if (int n = gluon_count(proc)) return n;
+  const ProcDef* P = find_proc(proc);
+  return P ? P->nlegs : -1;
+}
+
+extern "C" int or_eval(int proc, const or_params* prm, int64_t n_events, const double* mom, double* me2,
+                       int n_threads) {
+  const SM sm(*prm);
+  const int ng = gluon_count(proc);
+  const ProcDef* P = ng ? nullptr : find_proc(proc);
+  if (!ng && !P) return -1;
+  const int nl = ng ? ng : P->nlegs;
+  if (ng) gluon_colour_matrix(ng);
+  const std::vector<std::vector<cd>>* C = P ? &colour_assignments(proc, *P) : nullptr;
+  const auto hels = P ? helicity_table(*P) : std::vector<std::vector<int>>{};
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_events; ++i) {
+    Vec4 p[16];
+    load(mom + i * nl * 4, nl, p);
+    if (ng) {
+      me2[i] = gluon_me2(ng, sm, p);
+    } else {
+      double s = 0.0;
+      for (const auto& h : hels) s += me2_one_helicity(*P, *C, sm, p, h.data());
+      me2[i] = s;
+    }
+  }
+  return 0;
+}
+
+extern "C" int or_amp_colour(int proc, const or_params* prm, const double* mom, const int* hel, const int* col,
+                             double* out) {
+  const ProcDef* P = find_proc(proc);
+  if (!P) return -1;
+  const SM sm(*prm);
+  Vec4 p[16];
+  load(mom, P->nlegs, p);
+  std::vector<cd> M(P->ndiag), c(P->ndiag);
+  P->amp(sm, p, hel, M.data());
+  P->colf(col, c.data());
+  cd s = 0;
+  for (int d = 0; d < P->ndiag; ++d) s += c[d] * M[d];
+  out[0] = s.real();
+  out[1] = s.imag();
+  return 0;
+}
+
+extern "C" int or_helicities(int proc, int* table) {
+  const ProcDef* P = find_proc(proc);
+  if (!P) return -1;
+  const auto hels = helicity_table(*P);
+  if (table)
+    for (size_t k = 0; k < hels.size(); ++k)
+      for (int l = 0; l < P->nlegs; ++l) table[k * P->nlegs + l] = hels[k][l];
+  return int(hels.size());
+}
+
+extern "C" int or_me2_per_helicity(int proc, const or_params* prm, const double* mom, double* out) {
+  const ProcDef* P = find_proc(proc);
+  if (!P) return -1;
+  const SM sm(*prm);
+  Vec4 p[16];
+  load(mom, P->nlegs, p);
+  const auto& C = colour_assignments(proc, *P);
+  const auto hels = helicity_table(*P);
+  for (size_t k = 0; k < hels.size(); ++k) out[k] = me2_one_helicity(*P, C, sm, p, hels[k].data());
+  return int(hels.size());
+}
+
+extern "C" int or_me2_hel(int proc, const or_params* prm, const double* mom, const int* hel, double* out) {
+  const ProcDef* P = find_proc(proc);
+  if (!P) return -1;
+  const SM sm(*prm);
+  Vec4 p[16];
+  load(mom, P->nlegs, p);
+  out[0] = me2_one_helicity(*P, colour_assignments(proc, *P), sm, p, hel);
+  return 0;
+}
+
+extern "C" int or_gluon_partial(int n, const or_params* prm, const double* mom, const int* hel, const int* order,
+                                double* out) {
+  if (n < 4 || n > 7) return -1;
+  const SM sm(*prm);
+  Vec4 p[16];
+  load(mom, n, p);
+  const cd a = gluon_partial(n, sm, p, hel, order);
+  out[0] = a.real();
+  out[1] = a.imag();
+  return 0;
+}
+
+extern "C" int or_gluon_colour_matrix(int n, double* C) {
+  if (n < 3 || n > 6) return -1;
+  const std::vector<double>& M = gluon_colour_matrix(n);
+  std::memcpy(C, M.data(), M.size() * sizeof(double));
+  return int(M.size());
+}
+
+extern "C" int or_trace_me2(int proc, const or_params* prm, const double* mom, double* out) {
+  const SM sm(*prm);
+  Vec4 p[4];
+  load(mom, 4, p);
+  out[0] = trace_me2(proc, sm, p);
+  return out[0] < 0 ? -1 : 0;
+}
+
+extern "C" double or_selfcheck_spinors(const double* pin, double m) {
+  // Dirac equation, completeness and helicity eigenvalue checks for one momentum
+  Vec4 p = {pin[0], pin[1], pin[2], pin[3]};
+  const Mat4 ps = slash(p);
+  const Mat4 mm = mscale(m, ident4());
+  double worst = 0.0;
+  const double scale = p[0] + 1.0;
+  Mat4 su = zero4(), sv = zero4();
+  for (int lam : {-1, 1}) {
+    const Spinor u = u_spinor(p, m, lam), v = v_spinor(p, m, lam);
+    const Spinor du = mv(madd(ps, mscale(-1.0, mm)), u);   // (pslash - m) u = 0
+    const Spinor dv = mv(madd(ps, mm), v);                  // (pslash + m) v = 0
+    for (int i = 0; i < 4; ++i) worst = std::max(worst, std::max(std::abs(du[i]), std::abs(dv[i])) / scale);
+    const Spinor ub = dbar(u), vb = dbar(v);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        su.m[i][j] += u[i] * ub[j];
+        sv.m[i][j] += v[i] * vb[j];
+      }
+  }
+  const Mat4 eu = madd(su, mscale(-1.0, madd(ps, mm)));   // sum u ubar - (pslash + m)
+  const Mat4 ev = madd(sv, mscale(-1.0, madd(ps, mscale(-1.0, mm))));
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) worst = std::max(worst, std::max(std::abs(eu.m[i][j]), std::abs(ev.m[i][j])) / scale);
+  return worst;
+}
