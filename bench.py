@@ -1,0 +1,143 @@
+"""Benchmark: helicity- and colour-summed |M|^2 events/s on one GPU.
+
+Workload: g g -> t tbar -> (b e+ nu_e)(bbar mu- nu_mu~) at sqrt(s_hat) = 1 TeV,
+2^20 RAMBO events per step from a Philox seed, all 256 helicity combinations,
+two colour flows.  One step = the whole hot path over one batch: Philox ->
+RAMBO -> external wavefunctions -> vertex/propagator chain -> jamps ->
+colour form -> helicity sum -> weights -> deterministic cross-section
+reduction (heget_integrate).  The FP64 path is the headline; the mixed
+path, and both with exactly-vanishing helicities filtered out, are reported
+beside it.
+
+Prints ONE JSON line (rank 0).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "helicity+colour-summed |M|^2 events/s, FP64 vs mixed; p50/p99 serve latency"
+N_EVENTS = 1 << 20
+SQRT_S = 1000.0
+SEED = 0x48454746
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
+
+
+def time_path(torch, proc, steps, warmup, n=N_EVENTS):
+    """Per step: one heget_integrate (amplitude kernel + reduction).  Also
+    times the amplitude kernel alone with HIP events on the launch stream."""
+    for _ in range(warmup):
+        proc.integrate(n, seed=SEED, sqrt_s=SQRT_S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        r = proc.integrate(n, seed=SEED + k, sqrt_s=SQRT_S)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # amplitude kernel alone: eval with |M|^2 written, timed with events on the stream it runs on
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    proc.eval(n=n, seed=SEED, sqrt_s=SQRT_S, me2_out=out)
+    ev0.record(stream)
+    for k in range(steps):
+        proc.eval(n=n, seed=SEED + k, sqrt_s=SQRT_S, me2_out=out)
+    ev1.record(stream)
+    ev1.synchronize()
+    kern = ev0.elapsed_time(ev1) / 1e3 / steps
+    return wall, kern, r
+
+
+def cpu_baseline(oracle, target_seconds=12.0):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    mom = oracle.generate(SEED, 256, 6, SQRT_S)
+    t0 = time.perf_counter()
+    oracle.me2(oracle.GG_TT_6F, mom, oracle.params(), threads=cores)
+    rate = 256 / (time.perf_counter() - t0)
+    n = int(min(max(rate * target_seconds, 512), 200000))
+    mom = oracle.generate(SEED, n, 6, SQRT_S)
+    t0 = time.perf_counter()
+    f = oracle.me2(oracle.GG_TT_6F, mom, oracle.params(), threads=cores)
+    dt = time.perf_counter() - t0
+    assert np.all(f > 0)
+    return {"value": n / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} events of the same workload (first {n} Philox counters), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the path shards by Philox counter ranges, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes, flops
+
+    proc_ir = processes.gg_ttbar_6f()
+    fp64 = H.Process(proc_ir, precision="fp64")
+    mixed = H.Process(proc_ir, precision="mixed")
+
+    wall64, kern64, r64 = time_path(torch, fp64, args.steps, args.warmup)
+    wallmx, kernmx, rmx = time_path(torch, mixed, args.steps, args.warmup)
+
+    # with the exactly-vanishing helicity combinations dropped (4 of 256 survive)
+    fp64f = H.Process(proc_ir, precision="fp64")
+    nk = fp64f.filter_helicities(n_probe=64, seed=99, sqrt_s=SQRT_S, rel_threshold=1e-20)
+    mixedf = H.Process(proc_ir, precision="mixed")
+    mixedf.filter_helicities(n_probe=64, seed=99, sqrt_s=SQRT_S, rel_threshold=1e-20)
+    wall64f, kern64f, _ = time_path(torch, fp64f, args.steps, args.warmup)
+    wallmxf, kernmxf, _ = time_path(torch, mixedf, args.steps, args.warmup)
+
+    flop_event = flops.per_event(proc_ir)
+    achieved = flop_event * N_EVENTS / kern64 / 1e12
+    value = N_EVENTS / wall64
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gg->ttbar->(b e+ nu_e)(bbar mu- nu_mu~), sqrt_s_hat=1 TeV, 2^20 RAMBO events "
+                               "per step, 256 helicity combinations, 2 colour flows",
+                   "events_per_step": N_EVENTS, "helicities": 256},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "amp_gg_ttbar_6f<double>", "kernel_ms": kern64 * 1e3,
+                     "flop_per_event": flop_event},
+        "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,
+                  "achieved_tflops": flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
+                  "sigma_pb": rmx["sigma_pb"]},
+        "helicity_filtered": {"helicities": nk, "fp64_value": N_EVENTS / wall64f,
+                              "mixed_value": N_EVENTS / wallmxf, "fp64_kernel_ms": kern64f * 1e3,
+                              "mixed_kernel_ms": kernmxf * 1e3},
+        "sigma_pb": r64["sigma_pb"], "sigma_err_pb": r64["err_pb"],
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        line["cpu_baseline"] = cpu_baseline(oracle)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

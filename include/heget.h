@@ -1,0 +1,205 @@
+/* heget: per-event tree-level Standard Model helicity amplitudes on gfx950.
+ *
+ * C ABI of the library libheget.so.  The calls follow the paper's statement of
+ * the problem (Sec. 2): for a partonic process a b -> 1 ... n, the squared
+ * matrix element summed over helicities and colours,
+ *     F = sum_lambda sum_c |M_lambda^c|^2,   M = sum over Feynman diagrams,
+ * evaluated per phase-space point, and the cross section
+ *     sigma = 1/(2 s) * 1/4 * 1/(n_a n_b) * 1/S * integral F dPhi_n
+ * (the paper's LO partonic cross section and invariant phase space, Sec. 2;
+ * S is the identical-particle symmetry factor).  A process is described by a
+ * process IR: external legs, SM inputs, the list of HEGET-style vertex and
+ * propagator calls (Sec. 4, Tables of external-line and vertex functions), the
+ * decomposition of the amplitudes into colour flows and the colour matrix
+ * (Sec. 5.4).
+ *
+ * Memory: every pointer argument of heget_eval / heget_integrate that is
+ * documented as "device" must point to device memory of the current HIP device
+ * and stay valid until the work enqueued on `stream` completes; the caller owns
+ * it.  The IR passed to heget_process_create is host memory, read during the
+ * call only (the library copies what it keeps).  A process handle owns its
+ * device-resident tables and releases them in heget_process_destroy.
+ *
+ * Errors: every call returns a heget_status; no call aborts or throws.  On a
+ * non-OK status, heget_last_error() returns a thread-local message.
+ * Threading: a handle is immutable after creation; concurrent heget_eval calls
+ * on one handle are allowed on different streams.
+ */
+#ifndef HEGET_H
+#define HEGET_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HEGET_OK = 0,
+  HEGET_E_INVALID = -1,      /* bad argument (null pointer, n < 0, size mismatch) */
+  HEGET_E_IR = -2,           /* the IR is malformed (slot, arity, kind or symmetry error) */
+  HEGET_E_OOM = -3,          /* device allocation failed */
+  HEGET_E_HIP = -4,          /* a HIP runtime call failed */
+  HEGET_E_UNSUPPORTED = -5   /* no compiled kernel for this IR structure */
+} heget_status;
+
+typedef enum { HEGET_FP64 = 0, HEGET_MIXED = 1 } heget_precision;
+
+/* leg kinds and particle ids (masses / widths) */
+enum { HEGET_LEG_F = 0, HEGET_LEG_V = 1, HEGET_LEG_S = 2 };
+enum { HEGET_P_ZERO = 0, HEGET_P_W = 1, HEGET_P_Z = 2, HEGET_P_TOP = 3, HEGET_P_H = 4, HEGET_N_PARTICLES = 5 };
+
+/* call opcodes: HEGET function equivalents (paper Sec. 4, App. C) */
+enum {
+  HEGET_OP_IOV = 0, HEGET_OP_FVI, HEGET_OP_FVO, HEGET_OP_JIO,   /* FFV */
+  HEGET_OP_IOS, HEGET_OP_FSI, HEGET_OP_FSO, HEGET_OP_HIO,       /* FFS */
+  HEGET_OP_VVV, HEGET_OP_JVV,                                   /* VVV */
+  HEGET_OP_GGGG, HEGET_OP_JGGG, HEGET_OP_WWWW, HEGET_OP_JWWW,   /* VVVV */
+  HEGET_OP_VVS, HEGET_OP_JVS, HEGET_OP_HVV,                     /* VVS */
+  HEGET_OP_VVSS, HEGET_OP_JVSS, HEGET_OP_HVVS,                  /* VVSS */
+  HEGET_OP_SSS, HEGET_OP_HSS, HEGET_OP_SSSS, HEGET_OP_HSSS,     /* SSS, SSSS */
+  HEGET_N_OPS
+};
+
+/* coupling kinds; values are derived by the library from heget_sm */
+enum {
+  HEGET_CPL_GAMMA_FF = 0, /* photon-fermion, charge Q:      gc0 = gc1 = -e Q */
+  HEGET_CPL_Z_FF,         /* Z-fermion, Q and T3:           gc0 = -g_Z (T3 - Q s_W^2), gc1 = g_Z Q s_W^2 */
+  HEGET_CPL_W_FF,         /* W-fermion pair (CKM = 1):      gc0 = -g_W / sqrt2, gc1 = 0 */
+  HEGET_CPL_G_QQ,         /* quark-gluon, colour -T^a:      gc0 = gc1 = g_s */
+  HEGET_CPL_GGG,          /* triple gluon, colour i f^abc:  g_s */
+  HEGET_CPL_GGGG,         /* four gluon, colour f f:        g_s^2 */
+  HEGET_CPL_WWZ,          /* g_W cos theta_W */
+  HEGET_CPL_WWA,          /* e */
+  HEGET_CPL_WWH,          /* g_W m_W (complex mass in the complex-mass scheme) */
+  HEGET_CPL_ZZH,          /* g_Z m_Z */
+  HEGET_CPL_WWHH,         /* g_W^2 / 2 */
+  HEGET_CPL_ZZHH,         /* g_Z^2 / 2 */
+  HEGET_CPL_HHH,          /* -3 m_H^2 / v */
+  HEGET_CPL_HHHH,         /* -3 m_H^2 / v^2 */
+  HEGET_CPL_HBB,          /* gc0 = gc1 = -m_b / v  (Yukawa mass mb_yuk) */
+  HEGET_CPL_WWWW,         /* -g_W^2  (W-W+W-W+) */
+  HEGET_CPL_WWZZ,         /* g_W^2 cos^2 theta_W  (W-ZW+Z) */
+  HEGET_N_CPL
+};
+
+typedef struct {
+  double alpha;         /* QED coupling */
+  double sw2;           /* sin^2 theta_W */
+  double mz, wz;        /* Z mass, width (GeV) */
+  double mw, ww;        /* W mass, width; ignored when complex_mass != 0 */
+  double mt, wt;        /* top mass, width */
+  double mh, wh;        /* Higgs mass, width */
+  double alpha_s;       /* strong coupling */
+  double mb_yuk;        /* b mass entering the Yukawa coupling only */
+  int32_t complex_mass; /* 1: m_V^2 -> m_V^2 - i m_V Gamma_V in propagators and couplings,
+                           with mu_W^2 = c_W^2 mu_Z^2 (paper, complex-mass discussion of Sec. 6) */
+} heget_sm;
+
+typedef struct {
+  int32_t kind;      /* HEGET_LEG_F / _V / _S */
+  int32_t incoming;  /* 1 = initial state, 0 = final state */
+  int32_t flow;      /* fermions: +1 particle, -1 antiparticle (ignored otherwise) */
+  int32_t particle;  /* HEGET_P_* : mass and width of the external line */
+  int32_t colour;    /* 1, 3 or 8 */
+} heget_leg;
+
+typedef struct {
+  int32_t kind;      /* HEGET_CPL_* */
+  int32_t particle;  /* reserved (0) */
+  double charge;     /* Q for photon / Z couplings */
+  double t3;         /* T3 for Z couplings */
+} heget_coupling;
+
+typedef struct {
+  int32_t op;        /* HEGET_OP_* */
+  int32_t in[4];     /* input slots in argument order; -1 for unused */
+  int32_t out;       /* output slot (currents) or amplitude index (amplitude ops) */
+  int32_t coupling;  /* index into heget_process_ir.couplings */
+  int32_t prop;      /* HEGET_P_* of the propagator of a current (0 for amplitudes) */
+} heget_call;
+
+/* Slots 0 .. n_legs-1 hold the external wavefunctions; every current writes a
+ * new slot >= n_legs that is read only by later calls. */
+typedef struct {
+  int32_t n_legs;
+  const heget_leg* legs;              /* [n_legs]; legs 0 and 1 are the incoming partons */
+  heget_sm sm;
+  int32_t n_couplings;
+  const heget_coupling* couplings;
+  int32_t n_calls;
+  const heget_call* calls;
+  int32_t n_amps;
+  int32_t n_flows;
+  const double* jamp;                 /* [n_flows][n_amps][2]: J_f = sum_a jamp[f][a] * amp_a */
+  const double* colour_num;           /* [n_flows][n_flows] symmetric numerators */
+  double colour_den;                  /* colour matrix = colour_num / colour_den */
+  int32_t n_hel;
+  const int8_t* helicities;           /* [n_hel][n_legs]: -1, 0, +1 (4 = gauge vector k/k^0) */
+  int32_t n_a_n_b;                    /* initial-state colour degrees of freedom n_a n_b */
+  int32_t symmetry;                   /* identical-particle factor S */
+  int32_t cut_enabled;                /* every final leg pT > cut_pt and every pair Delta R > cut_dr */
+  double cut_pt, cut_dr;
+} heget_process_ir;
+
+typedef struct heget_process* heget_process_t;
+
+typedef struct {
+  double sigma_gev2, err_gev2;   /* cross section and its Monte Carlo error, GeV^-2 */
+  double sigma_pb, err_pb;       /* the same in pb ((hbar c)^2 = 0.3893793721e9 pb GeV^2) */
+  double sum_w, sum_w2;          /* sum of weights and of squared weights */
+  int64_t n_generated, n_accepted;
+} heget_result;
+
+/* Validate the IR, derive the couplings and propagator table from ir->sm,
+ * upload the helicity table and bind the compiled kernel whose structure
+ * (legs, calls, jamps, colour matrix) matches the IR.  prec selects FP64 or the
+ * mixed path (FP32 wavefunctions, vertex chain and colour sum; FP64 momenta,
+ * propagator denominators and reductions).  *out receives the handle.
+ * Errors: HEGET_E_INVALID (null pointers), HEGET_E_IR (malformed IR),
+ * HEGET_E_UNSUPPORTED (no kernel compiled for this structure), HEGET_E_OOM,
+ * HEGET_E_HIP.  heget_eval never allocates. */
+heget_status heget_process_create(const heget_process_ir* ir, heget_precision prec, heget_process_t* out);
+
+/* Release the handle and its device tables (synchronises the device first). */
+heget_status heget_process_destroy(heget_process_t p);
+
+/* Evaluate n events on `stream` (asynchronous; hipStream_t passed as void*).
+ * momenta_in: device FP64 SoA [n_legs][4][n] physical momenta (E, px, py, pz),
+ *   or NULL to generate them: incoming partons along +z / -z with energy
+ *   sqrt_s / 2 each, final state by RAMBO from Philox4x32-10 with key `seed`
+ *   and event counters counter_offset .. counter_offset + n - 1.
+ * me2_out: device FP64 [n]: helicity- and colour-summed |M|^2 (no averaging,
+ *   no symmetry factor); events failing the IR's cut get 0.  May be NULL.
+ * momenta_out: device FP64 SoA [n_legs][4][n] of the momenta used, or NULL.
+ * n = 0 is a no-op.  Errors: HEGET_E_INVALID, HEGET_E_HIP. */
+heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, uint64_t seed,
+                        uint64_t counter_offset, double sqrt_s, double* me2_out, double* momenta_out,
+                        void* stream);
+
+/* Monte Carlo cross section from n RAMBO events generated from `seed`
+ * (counters 0 .. n-1): sigma = (1/N) sum_i w_i with w_i = Phi_n * pass_i * F_i
+ * / (2 s 4 n_a n_b S), reduced on the device in a fixed order.  Synchronises
+ * `stream`; fills *out.  The handle keeps a small buffer of per-block partial
+ * sums (24 bytes per 256 events), allocated on the first call and grown when a
+ * larger n arrives; calls on one handle must not overlap.
+ * Errors: HEGET_E_INVALID, HEGET_E_OOM, HEGET_E_HIP. */
+heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
+                             void* stream);
+
+/* Number of helicity combinations the handle sums (after heget_filter_helicities). */
+int32_t heget_process_n_helicities(heget_process_t p);
+
+/* Drop helicity combinations whose colour-summed |M|^2 is below rel_threshold
+ * times the largest one on every one of n_probe generated events (an exact
+ * zero gives 0 on every event).  Synchronous; uses the handle's own kernel.
+ * Returns the number kept in *n_kept.  Errors: HEGET_E_INVALID, HEGET_E_HIP. */
+heget_status heget_filter_helicities(heget_process_t p, int64_t n_probe, uint64_t seed, double sqrt_s,
+                                     double rel_threshold, int32_t* n_kept);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* heget_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,139 @@
+"""heget on MI355X: per-event tree-level SM helicity amplitudes (HEGET-style)
+as hand-written HIP for gfx950 behind the C ABI of include/heget.h.
+
+Python is argument marshalling only: ``Process`` turns an ``ir.Process`` into
+the C IR structs, and ``eval`` / ``integrate`` pass device pointers and the
+current HIP stream to libheget.so.  PyTorch provides device memory and
+streams.  Every step of the amplitude path runs in the library's kernels; if
+libheget.so is missing the calls raise.
+"""
+import ctypes
+
+from . import _lib, ir
+from ._lib import HEGET_FP64, HEGET_MIXED, HegetError, check
+
+__all__ = ["Process", "default_sm", "HegetError", "ir"]
+
+
+def default_sm(**kw):
+    """SM inputs of the benchmark workloads (overridable by keyword)."""
+    d = dict(alpha=1.0 / 128.0, sw2=0.2222, mz=91.1876, wz=2.4952, mw=80.4, ww=2.085,
+             mt=175.0, wt=1.55, mh=125.0, wh=0.00407, alpha_s=0.118, mb_yuk=4.7, complex_mass=0)
+    d.update(kw)
+    return d
+
+
+class _IRBuffers:
+    """C structs for one ir.Process, kept alive while the library reads them."""
+
+    def __init__(self, proc, sm, helicities=None):
+        L = _lib
+        self.legs = (L.heget_leg * proc.n_legs)(*[
+            L.heget_leg(l.kind, int(l.incoming), l.flow, l.particle, l.colour) for l in proc.legs])
+        self.cpl = (L.heget_coupling * len(proc.couplings))(*[
+            L.heget_coupling(ir.CPL[c.kind], c.particle, c.charge, c.t3) for c in proc.couplings])
+        calls = []
+        for c in proc.calls:
+            ins = list(c.ins) + [-1] * (4 - len(c.ins))
+            calls.append(L.heget_call(ir.OP[c.op], (ctypes.c_int32 * 4)(*ins), c.out, c.cpl, c.prop))
+        self.calls = (L.heget_call * len(calls))(*calls)
+        dense = [0.0] * (proc.n_flows * proc.n_amps * 2)
+        for f, terms in enumerate(proc.jamp):
+            for a, coef in terms:
+                k = (f * proc.n_amps + a) * 2
+                dense[k] += complex(coef).real
+                dense[k + 1] += complex(coef).imag
+        self.jamp = (ctypes.c_double * len(dense))(*dense)
+        den = proc.colour_denominator()
+        num = [float(x * den) for row in proc.colour for x in row]
+        self.colour = (ctypes.c_double * len(num))(*num)
+        hels = helicities if helicities is not None else proc.helicities
+        flat = [int(h) for row in hels for h in row]
+        self.hel = (ctypes.c_int8 * len(flat))(*flat)
+        self.sm = L.heget_sm(**sm)
+        self.ir = L.heget_process_ir(
+            proc.n_legs, self.legs, self.sm, len(proc.couplings), self.cpl, len(calls), self.calls,
+            proc.n_amps, proc.n_flows, self.jamp, self.colour, float(den), len(hels), self.hel,
+            proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr)
+
+
+class Process:
+    """A created process handle (heget_process_create)."""
+
+    def __init__(self, proc, precision="fp64", sm=None, helicities=None):
+        self.ir = proc
+        s = default_sm(**proc.sm_overrides)
+        if sm:
+            s.update(sm)
+        self._buf = _IRBuffers(proc, s, helicities)
+        self._lib = _lib.load()
+        self.precision = precision
+        prec = HEGET_FP64 if precision == "fp64" else HEGET_MIXED
+        h = ctypes.c_void_p()
+        check(self._lib.heget_process_create(ctypes.byref(self._buf.ir), prec, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def n_legs(self):
+        return self.ir.n_legs
+
+    @property
+    def n_helicities(self):
+        return self._lib.heget_process_n_helicities(self._h)
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def eval(self, n=None, momenta=None, seed=0, counter_offset=0, sqrt_s=None, me2_out=None,
+             momenta_out=None, want_momenta=False, stream=None):
+        """|M|^2 summed over helicities and colours for n events.  momenta: a
+        float64 CUDA tensor [n_legs][4][n] (SoA) or None to generate them from
+        (seed, counter_offset, sqrt_s).  Returns me2 (and momenta if requested)."""
+        import torch
+        if momenta is not None:
+            if momenta.dtype != torch.float64 or not momenta.is_cuda or not momenta.is_contiguous():
+                raise ValueError("momenta must be a contiguous float64 CUDA tensor")
+            if momenta.dim() != 3 or momenta.shape[0] != self.n_legs or momenta.shape[1] != 4:
+                raise ValueError(f"momenta must have shape [{self.n_legs}][4][n]")
+            n = momenta.shape[2] if n is None else n
+            if n != momenta.shape[2]:
+                raise ValueError("n does not match momenta")
+        if n is None:
+            raise ValueError("n is required when momenta are generated")
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        dev = momenta.device if momenta is not None else torch.device("cuda")
+        if me2_out is None:
+            me2_out = torch.empty(n, dtype=torch.float64, device=dev)
+        if want_momenta and momenta_out is None:
+            momenta_out = torch.empty((self.n_legs, 4, n), dtype=torch.float64, device=dev)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        check(self._lib.heget_eval(self._h, n, ptr(momenta), seed, counter_offset, float(sqrt_s),
+                                   ptr(me2_out), ptr(momenta_out), self._stream(stream)))
+        return (me2_out, momenta_out) if want_momenta else me2_out
+
+    def integrate(self, n, seed=0, sqrt_s=None, stream=None):
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        r = _lib.heget_result()
+        check(self._lib.heget_integrate(self._h, n, float(sqrt_s), seed, ctypes.byref(r), self._stream(stream)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
+    def filter_helicities(self, n_probe=64, seed=12345, sqrt_s=None, rel_threshold=1e-20):
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        kept = ctypes.c_int32()
+        check(self._lib.heget_filter_helicities(self._h, n_probe, seed, float(sqrt_s), rel_threshold,
+                                                ctypes.byref(kept)))
+        return kept.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.heget_process_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

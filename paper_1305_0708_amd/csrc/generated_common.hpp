@@ -1,0 +1,70 @@
+// Common code included by every generated amplitude kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "heget_device.hpp"
+#include "kernel_args.hpp"
+#include "phase_space.hpp"
+
+namespace heget {
+
+// Compiled kernel of one process IR, looked up by fingerprint at create time.
+struct GenEntry {
+  uint64_t fingerprint;
+  const char* name;
+  int n_legs;
+  const void* kernel_fp64;    // __global__ void(KernelArgs), T = double
+  const void* kernel_mixed;   // T = float, FP64 momenta and denominators
+};
+void register_kernel(const GenEntry* e);
+struct Registrar {
+  explicit Registrar(const GenEntry* e) { register_kernel(e); }
+};
+
+template <int NL>
+__device__ __forceinline__ void store_momenta(const KernelArgs& a, int64_t i, const mom* p) {
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    double* b = a.mom_out + int64_t(k) * 4 * a.mom_stride + i;
+    b[0] = p[k].e;
+    b[a.mom_stride] = p[k].x;
+    b[2 * a.mom_stride] = p[k].y;
+    b[3 * a.mom_stride] = p[k].z;
+  }
+}
+
+// Deterministic per-block partial sums (w, w^2, accepted) for the cross
+// section: a fixed butterfly inside each 64-lane wavefront, then the waves in
+// order.  Every thread of the block must call it.
+__device__ __forceinline__ void block_partials(const KernelArgs& a, double wgt, bool acc) {
+  double s = wgt, s2 = wgt * wgt, c = acc ? 1.0 : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+  __shared__ double red[3][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = s;
+    red[1][wave] = s2;
+    red[2][wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0, t2 = 0.0, tc = 0.0;
+    for (int k = 0; k < nw; ++k) {
+      t += red[0][k];
+      t2 += red[1][k];
+      tc += red[2][k];
+    }
+    a.partials[3 * blockIdx.x + 0] = t;
+    a.partials[3 * blockIdx.x + 1] = t2;
+    a.partials[3 * blockIdx.x + 2] = tc;
+  }
+}
+
+}  // namespace heget

@@ -1,0 +1,538 @@
+// C ABI of libheget: process handles, coupling derivation, kernel launches and
+// the deterministic cross-section reduction.  Declarations: include/heget.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "generated_common.hpp"
+#include "heget.h"
+
+namespace heget {
+
+static std::vector<const GenEntry*>& registry() {
+  static std::vector<const GenEntry*> r;
+  return r;
+}
+void register_kernel(const GenEntry* e) { registry().push_back(e); }
+
+}  // namespace heget
+
+using heget::GenEntry;
+using heget::KernelArgs;
+using heget::PropEntry;
+
+namespace {
+
+thread_local std::string g_err;
+
+heget_status fail(heget_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(HEGET_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// FNV-1a over the canonical serialisation of the kernel-relevant IR structure
+struct Hasher {
+  uint64_t h = 0xCBF29CE484222325ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t k = 0; k < n; ++k) {
+      h ^= b[k];
+      h *= 0x100000001B3ull;
+    }
+  }
+  void i32(int32_t x) { bytes(&x, 4); }
+  void f64(double x) { bytes(&x, 8); }
+};
+
+uint64_t fingerprint(const heget_process_ir* ir) {
+  Hasher H;
+  H.i32(ir->n_legs);
+  for (int k = 0; k < ir->n_legs; ++k) {
+    const heget_leg& l = ir->legs[k];
+    H.i32(l.kind);
+    H.i32(l.incoming);
+    H.i32(l.flow);
+    H.i32(l.particle);
+    H.i32(l.colour);
+  }
+  H.i32(ir->n_couplings);
+  for (int k = 0; k < ir->n_couplings; ++k) {
+    const heget_coupling& c = ir->couplings[k];
+    H.i32(c.kind);
+    H.f64(c.charge);
+    H.f64(c.t3);
+    H.i32(c.particle);
+  }
+  H.i32(ir->n_calls);
+  for (int k = 0; k < ir->n_calls; ++k) {
+    const heget_call& c = ir->calls[k];
+    H.i32(c.op);
+    for (int j = 0; j < 4; ++j) H.i32(c.in[j]);
+    H.i32(c.out);
+    H.i32(c.coupling);
+    H.i32(c.prop);
+  }
+  H.i32(ir->n_amps);
+  H.i32(ir->n_flows);
+  for (int f = 0; f < ir->n_flows; ++f)
+    for (int a = 0; a < ir->n_amps; ++a) {
+      H.f64(ir->jamp[(f * ir->n_amps + a) * 2]);
+      H.f64(ir->jamp[(f * ir->n_amps + a) * 2 + 1]);
+    }
+  for (int k = 0; k < ir->n_flows * ir->n_flows; ++k) H.f64(ir->colour_num[k]);
+  H.f64(ir->colour_den);
+  H.i32(ir->cut_enabled);
+  return H.h;
+}
+
+// inputs per opcode: 'F', 'V', 'S'; output kind or 'A' for amplitudes
+struct OpSig {
+  const char* in;
+  char out;
+};
+const OpSig kSig[HEGET_N_OPS] = {
+    {"FFV", 'A'}, {"FV", 'F'}, {"FV", 'F'}, {"FF", 'V'},     // iov fvi fvo jio
+    {"FFS", 'A'}, {"FS", 'F'}, {"FS", 'F'}, {"FF", 'S'},     // ios fsi fso hio
+    {"VVV", 'A'}, {"VV", 'V'},                               // vvv jvv
+    {"VVVV", 'A'}, {"VVV", 'V'}, {"VVVV", 'A'}, {"VVV", 'V'},  // gggg jggg wwww jwww
+    {"VVS", 'A'}, {"VS", 'V'}, {"VV", 'S'},                  // vvs jvs hvv
+    {"VVSS", 'A'}, {"VSS", 'V'}, {"VVS", 'S'},               // vvss jvss hvvs
+    {"SSS", 'A'}, {"SS", 'S'}, {"SSSS", 'A'}, {"SSS", 'S'},  // sss hss ssss hsss
+};
+
+heget_status validate(const heget_process_ir* ir) {
+  if (ir->n_legs < 3 || ir->n_legs > 12 || !ir->legs) return fail(HEGET_E_IR, "n_legs must be 3..12");
+  if (!ir->legs[0].incoming || !ir->legs[1].incoming)
+    return fail(HEGET_E_IR, "legs 0 and 1 must be the incoming partons");
+  for (int k = 2; k < ir->n_legs; ++k)
+    if (ir->legs[k].incoming) return fail(HEGET_E_IR, "only legs 0 and 1 may be incoming");
+  for (int k = 0; k < ir->n_legs; ++k) {
+    const heget_leg& l = ir->legs[k];
+    if (l.kind < 0 || l.kind > 2 || l.particle < 0 || l.particle >= HEGET_N_PARTICLES)
+      return fail(HEGET_E_IR, "leg " + std::to_string(k) + ": bad kind or particle");
+    if (k >= 2 && l.particle != HEGET_P_ZERO)
+      return fail(HEGET_E_UNSUPPORTED, "final-state legs must be massless (RAMBO phase space)");
+  }
+  if (ir->n_couplings < 1 || !ir->couplings) return fail(HEGET_E_IR, "no couplings");
+  for (int k = 0; k < ir->n_couplings; ++k)
+    if (ir->couplings[k].kind < 0 || ir->couplings[k].kind >= HEGET_N_CPL)
+      return fail(HEGET_E_IR, "coupling " + std::to_string(k) + ": bad kind");
+  if (ir->n_calls < 1 || !ir->calls) return fail(HEGET_E_IR, "no calls");
+  std::vector<char> kind(ir->n_legs + ir->n_calls + 1, 0);
+  for (int k = 0; k < ir->n_legs; ++k) kind[k] = "FVS"[ir->legs[k].kind];
+  std::vector<char> amp_seen(ir->n_amps > 0 ? ir->n_amps : 1, 0);
+  for (int k = 0; k < ir->n_calls; ++k) {
+    const heget_call& c = ir->calls[k];
+    const std::string at = "call " + std::to_string(k) + ": ";
+    if (c.op < 0 || c.op >= HEGET_N_OPS) return fail(HEGET_E_IR, at + "bad opcode");
+    const OpSig& sg = kSig[c.op];
+    const int nin = int(std::strlen(sg.in));
+    for (int j = 0; j < 4; ++j) {
+      if (j < nin) {
+        const int s = c.in[j];
+        if (s < 0 || s >= int(kind.size()) || kind[s] == 0) return fail(HEGET_E_IR, at + "input slot undefined");
+        if (kind[s] != sg.in[j]) return fail(HEGET_E_IR, at + "input slot has the wrong kind");
+      } else if (c.in[j] != -1) {
+        return fail(HEGET_E_IR, at + "unused inputs must be -1");
+      }
+    }
+    if (c.coupling < 0 || c.coupling >= ir->n_couplings) return fail(HEGET_E_IR, at + "bad coupling index");
+    if (c.prop < 0 || c.prop >= HEGET_N_PARTICLES) return fail(HEGET_E_IR, at + "bad propagator particle");
+    if (sg.out == 'A') {
+      if (c.out < 0 || c.out >= ir->n_amps || amp_seen[c.out]) return fail(HEGET_E_IR, at + "bad amplitude index");
+      amp_seen[c.out] = 1;
+    } else {
+      if (c.out < ir->n_legs || c.out >= int(kind.size()) || kind[c.out] != 0)
+        return fail(HEGET_E_IR, at + "output slot reused or out of range");
+      kind[c.out] = sg.out;
+    }
+  }
+  for (int a = 0; a < ir->n_amps; ++a)
+    if (!amp_seen[a]) return fail(HEGET_E_IR, "amplitude " + std::to_string(a) + " is never produced");
+  if (ir->n_flows < 1 || !ir->jamp || !ir->colour_num || !(ir->colour_den > 0))
+    return fail(HEGET_E_IR, "jamp / colour matrix missing");
+  for (int f = 0; f < ir->n_flows; ++f)
+    for (int g = 0; g < ir->n_flows; ++g)
+      if (ir->colour_num[f * ir->n_flows + g] != ir->colour_num[g * ir->n_flows + f])
+        return fail(HEGET_E_IR, "colour matrix is not symmetric");
+  if (ir->n_hel < 1 || !ir->helicities) return fail(HEGET_E_IR, "empty helicity table");
+  for (int h = 0; h < ir->n_hel * ir->n_legs; ++h) {
+    const int v = ir->helicities[h];
+    if (!(v == -1 || v == 0 || v == 1 || v == 4)) return fail(HEGET_E_IR, "helicity values must be -1, 0, 1 or 4");
+  }
+  if (ir->n_a_n_b < 1 || ir->symmetry < 1) return fail(HEGET_E_IR, "averaging factors must be >= 1");
+  return HEGET_OK;
+}
+
+// ------------------------------------------------------------ SM couplings
+using cd = std::complex<double>;
+
+struct Derived {
+  double e, sw, cw, gw, gz, gs, mw, ww, v;
+  cd muw2, muz2, numw2, numz2, muw, muz;
+};
+
+Derived derive(const heget_sm& sm) {
+  Derived d;
+  const double pi = 3.14159265358979323846;
+  d.e = std::sqrt(4.0 * pi * sm.alpha);
+  d.sw = std::sqrt(sm.sw2);
+  d.cw = std::sqrt(1.0 - sm.sw2);
+  d.gw = d.e / d.sw;
+  d.gz = d.e / (d.sw * d.cw);
+  d.gs = std::sqrt(4.0 * pi * sm.alpha_s);
+  if (sm.complex_mass) {
+    d.mw = d.cw * sm.mz;   // mu_W^2 = c_W^2 mu_Z^2
+    d.ww = d.cw * sm.wz;
+  } else {
+    d.mw = sm.mw;
+    d.ww = sm.ww;
+  }
+  d.muw2 = cd(d.mw * d.mw, -d.mw * d.ww);
+  d.muz2 = cd(sm.mz * sm.mz, -sm.mz * sm.wz);
+  d.numw2 = sm.complex_mass ? d.muw2 : cd(d.mw * d.mw, 0.0);
+  d.numz2 = sm.complex_mass ? d.muz2 : cd(sm.mz * sm.mz, 0.0);
+  d.muw = sm.complex_mass ? std::sqrt(d.muw2) : cd(d.mw, 0.0);
+  d.muz = sm.complex_mass ? std::sqrt(d.muz2) : cd(sm.mz, 0.0);
+  d.v = 2.0 * d.mw / d.gw;
+  return d;
+}
+
+void coupling_values(const heget_sm& sm, const heget_coupling& c, double out[4]) {
+  const Derived d = derive(sm);
+  cd g0 = 0.0, g1 = 0.0;
+  switch (c.kind) {
+    case HEGET_CPL_GAMMA_FF: g0 = g1 = -d.e * c.charge; break;
+    case HEGET_CPL_Z_FF: g0 = -d.gz * (c.t3 - c.charge * sm.sw2); g1 = d.gz * c.charge * sm.sw2; break;
+    case HEGET_CPL_W_FF: g0 = -d.gw / std::sqrt(2.0); g1 = 0.0; break;
+    case HEGET_CPL_G_QQ: g0 = g1 = d.gs; break;
+    case HEGET_CPL_GGG: g0 = d.gs; break;
+    case HEGET_CPL_GGGG: g0 = d.gs * d.gs; break;
+    case HEGET_CPL_WWZ: g0 = d.gw * d.cw; break;
+    case HEGET_CPL_WWA: g0 = d.e; break;
+    case HEGET_CPL_WWH: g0 = d.gw * d.muw; break;
+    case HEGET_CPL_ZZH: g0 = d.gz * d.muz; break;
+    case HEGET_CPL_WWHH: g0 = 0.5 * d.gw * d.gw; break;
+    case HEGET_CPL_ZZHH: g0 = 0.5 * d.gz * d.gz; break;
+    case HEGET_CPL_HHH: g0 = -3.0 * sm.mh * sm.mh / d.v; break;
+    case HEGET_CPL_HHHH: g0 = -3.0 * sm.mh * sm.mh / (d.v * d.v); break;
+    case HEGET_CPL_HBB: g0 = g1 = -sm.mb_yuk / d.v; break;
+    case HEGET_CPL_WWWW: g0 = -d.gw * d.gw; break;
+    case HEGET_CPL_WWZZ: g0 = d.gw * d.gw * d.cw * d.cw; break;
+    default: break;
+  }
+  out[0] = g0.real();
+  out[1] = g0.imag();
+  out[2] = g1.real();
+  out[3] = g1.imag();
+}
+
+void prop_table(const heget_sm& sm, PropEntry t[HEGET_N_PARTICLES]) {
+  const Derived d = derive(sm);
+  auto fill = [](PropEntry& e, double m, double w, cd pole, cd num) {
+    e.m = m;
+    e.w = w;
+    e.pole_r = pole.real();
+    e.pole_i = pole.imag();
+    const cd inv = (std::abs(num) > 0) ? 1.0 / num : cd(0.0, 0.0);
+    e.inum_r = inv.real();
+    e.inum_i = inv.imag();
+  };
+  fill(t[HEGET_P_ZERO], 0.0, 0.0, 0.0, 0.0);
+  fill(t[HEGET_P_W], d.mw, d.ww, d.muw2, d.numw2);
+  fill(t[HEGET_P_Z], sm.mz, sm.wz, d.muz2, d.numz2);
+  fill(t[HEGET_P_TOP], sm.mt, sm.wt, cd(sm.mt * sm.mt, -sm.mt * sm.wt), 0.0);
+  fill(t[HEGET_P_H], sm.mh, sm.wh, cd(sm.mh * sm.mh, -sm.mh * sm.wh), 0.0);
+}
+
+double phase_space_volume(double sqrt_s, int n) {
+  const double pi = 3.14159265358979323846;
+  double f1 = 1.0, f2 = 1.0;
+  for (int i = 2; i <= n - 1; ++i) f1 *= i;
+  for (int i = 2; i <= n - 2; ++i) f2 *= i;
+  const double s = sqrt_s * sqrt_s;
+  return std::pow(2.0 * pi, 4 - 3 * n) * std::pow(0.5 * pi, n - 1) * std::pow(s, n - 2) / (f1 * f2);
+}
+
+// Fixed-order reduction of the per-block partials with Neumaier compensation:
+// thread t sums blocks t, t + T, ... in order, then the T partial results are
+// combined by thread 0 in order.
+__global__ __launch_bounds__(256) void reduce_partials(const double* partials, int64_t nblocks, double* out) {
+  __shared__ double sm[3][256];
+  __shared__ double cm[3][256];
+  const int t = threadIdx.x;
+  double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+  for (int64_t b = t; b < nblocks; b += blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      const double x = partials[3 * b + k];
+      const double u = s[k] + x;
+      c[k] += (fabs(s[k]) >= fabs(x)) ? ((s[k] - u) + x) : ((x - u) + s[k]);
+      s[k] = u;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    sm[k][t] = s[k];
+    cm[k][t] = c[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int k = 0; k < 3; ++k) {
+      double S = 0.0, C = 0.0;
+      for (int j = 0; j < int(blockDim.x); ++j) {
+        const double x = sm[k][j];
+        const double u = S + x;
+        C += (fabs(S) >= fabs(x)) ? ((S - u) + x) : ((x - u) + S);
+        S = u;
+        C += cm[k][j];
+      }
+      out[k] = S + C;
+    }
+  }
+}
+
+}  // namespace
+
+struct heget_process {
+  const GenEntry* entry = nullptr;
+  heget_precision prec = HEGET_FP64;
+  int n_legs = 0;
+  int n_hel = 0;
+  int cut_enabled = 0;
+  double cut_pt = 0, cut_dr = 0;
+  int n_a_n_b = 1, symmetry = 1;
+  double* d_cpl = nullptr;
+  PropEntry* d_prop = nullptr;
+  int8_t* d_hel = nullptr;
+  double* d_part = nullptr;  // integrate partials, grown on demand and reused
+  int64_t part_cap = 0;
+  std::vector<int8_t> hel;  // host copy of the current table
+};
+
+namespace {
+
+heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
+  if (a.n == 0) return HEGET_OK;
+  const int block = 256;
+  const int64_t grid = (a.n + block - 1) / block;
+  if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
+  const void* fn = p->prec == HEGET_FP64 ? p->entry->kernel_fp64 : p->entry->kernel_mixed;
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(block), args, 0, stream));
+  return HEGET_OK;
+}
+
+KernelArgs base_args(heget_process_t p) {
+  KernelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.hel = p->d_hel;
+  a.n_hel = p->n_hel;
+  a.cut_enabled = p->cut_enabled;
+  a.cpl = p->d_cpl;
+  a.prop = p->d_prop;
+  a.cut_pt = p->cut_pt;
+  a.cut_dr = p->cut_dr;
+  return a;
+}
+
+void release(heget_process* p) {
+  if (!p) return;
+  if (p->d_cpl) (void)hipFree(p->d_cpl);
+  if (p->d_prop) (void)hipFree(p->d_prop);
+  if (p->d_hel) (void)hipFree(p->d_hel);
+  if (p->d_part) (void)hipFree(p->d_part);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* heget_last_error(void) { return g_err.c_str(); }
+
+heget_status heget_process_create(const heget_process_ir* ir, heget_precision prec, heget_process_t* out) {
+  g_err.clear();
+  if (!ir || !out) return fail(HEGET_E_INVALID, "null argument");
+  *out = nullptr;
+  if (prec != HEGET_FP64 && prec != HEGET_MIXED) return fail(HEGET_E_INVALID, "unknown precision");
+  if (heget_status s = validate(ir)) return s;
+  const uint64_t fp = fingerprint(ir);
+  const GenEntry* entry = nullptr;
+  for (const GenEntry* e : heget::registry())
+    if (e->fingerprint == fp && e->n_legs == ir->n_legs) entry = e;
+  if (!entry) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "no kernel compiled for this IR structure (fingerprint 0x%016llx)",
+                  (unsigned long long)fp);
+    return fail(HEGET_E_UNSUPPORTED, buf);
+  }
+  heget_process* p = new heget_process();
+  p->entry = entry;
+  p->prec = prec;
+  p->n_legs = ir->n_legs;
+  p->n_hel = ir->n_hel;
+  p->cut_enabled = ir->cut_enabled;
+  p->cut_pt = ir->cut_pt;
+  p->cut_dr = ir->cut_dr;
+  p->n_a_n_b = ir->n_a_n_b;
+  p->symmetry = ir->symmetry;
+  p->hel.assign(ir->helicities, ir->helicities + size_t(ir->n_hel) * ir->n_legs);
+  std::vector<double> cpl(size_t(ir->n_couplings) * 4);
+  for (int k = 0; k < ir->n_couplings; ++k) coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
+  PropEntry prop[HEGET_N_PARTICLES];
+  prop_table(ir->sm, prop);
+  if (hipMalloc(&p->d_cpl, cpl.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_prop, sizeof(prop)) != hipSuccess || hipMalloc(&p->d_hel, p->hel.size()) != hipSuccess) {
+    release(p);
+    return fail(HEGET_E_OOM, "device allocation of process tables failed");
+  }
+  if (hipMemcpy(p->d_cpl, cpl.data(), cpl.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_prop, prop, sizeof(prop), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_hel, p->hel.data(), p->hel.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    release(p);
+    return fail(HEGET_E_HIP, "upload of process tables failed");
+  }
+  *out = p;
+  return HEGET_OK;
+}
+
+heget_status heget_process_destroy(heget_process_t p) {
+  g_err.clear();
+  if (!p) return fail(HEGET_E_INVALID, "null handle");
+  (void)hipDeviceSynchronize();
+  release(p);
+  return HEGET_OK;
+}
+
+int32_t heget_process_n_helicities(heget_process_t p) { return p ? p->n_hel : -1; }
+
+heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, uint64_t seed,
+                        uint64_t counter_offset, double sqrt_s, double* me2_out, double* momenta_out,
+                        void* stream) {
+  g_err.clear();
+  if (!p) return fail(HEGET_E_INVALID, "null handle");
+  if (n < 0) return fail(HEGET_E_INVALID, "n < 0");
+  if (!momenta_in && !(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0 when generating momenta");
+  KernelArgs a = base_args(p);
+  a.n = n;
+  a.mom_in = momenta_in;
+  a.mom_stride = n;
+  a.seed = seed;
+  a.counter_offset = counter_offset;
+  a.sqrt_s = sqrt_s;
+  a.me2_out = me2_out;
+  a.mom_out = momenta_out;
+  return launch(p, a, static_cast<hipStream_t>(stream));
+}
+
+heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
+                             void* stream) {
+  g_err.clear();
+  if (!p || !out) return fail(HEGET_E_INVALID, "null argument");
+  if (n < 2) return fail(HEGET_E_INVALID, "need n >= 2 events");
+  if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nblocks = (n + 255) / 256;
+  if (p->part_cap < nblocks * 3 + 3) {
+    HIP_TRY(hipStreamSynchronize(st));
+    if (p->d_part) (void)hipFree(p->d_part);
+    p->d_part = nullptr;
+    p->part_cap = 0;
+    if (hipMalloc(&p->d_part, size_t(nblocks * 3 + 3) * sizeof(double)) != hipSuccess)
+      return fail(HEGET_E_OOM, "partials allocation failed");
+    p->part_cap = nblocks * 3 + 3;
+  }
+  double* d_part = p->d_part;
+  const double s = sqrt_s * sqrt_s;
+  KernelArgs a = base_args(p);
+  a.n = n;
+  a.mom_stride = n;
+  a.seed = seed;
+  a.sqrt_s = sqrt_s;
+  a.weight_factor = phase_space_volume(sqrt_s, p->n_legs - 2) / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
+  a.partials = d_part;
+  heget_status rc = launch(p, a, st);
+  double h[3] = {0, 0, 0};
+  if (rc == HEGET_OK) {
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, d_part + 3 * nblocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d_part + 3 * nblocks, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
+  }
+  if (rc != HEGET_OK) return rc;
+  const double N = double(n);
+  out->sum_w = h[0];
+  out->sum_w2 = h[1];
+  out->n_generated = n;
+  out->n_accepted = int64_t(h[2] + 0.5);
+  out->sigma_gev2 = h[0] / N;
+  const double var = std::max(h[1] / N - out->sigma_gev2 * out->sigma_gev2, 0.0);
+  out->err_gev2 = std::sqrt(var / (N - 1.0));
+  const double hbarc2 = 0.3893793721e9;
+  out->sigma_pb = out->sigma_gev2 * hbarc2;
+  out->err_pb = out->err_gev2 * hbarc2;
+  return HEGET_OK;
+}
+
+heget_status heget_filter_helicities(heget_process_t p, int64_t n_probe, uint64_t seed, double sqrt_s,
+                                     double rel_threshold, int32_t* n_kept) {
+  g_err.clear();
+  if (!p || !n_kept) return fail(HEGET_E_INVALID, "null argument");
+  if (n_probe < 1 || !(sqrt_s > 0) || !(rel_threshold >= 0)) return fail(HEGET_E_INVALID, "bad probe arguments");
+  const int nh = p->n_hel, nl = p->n_legs;
+  double* d_me2 = nullptr;
+  if (hipMalloc(&d_me2, size_t(nh) * n_probe * sizeof(double)) != hipSuccess)
+    return fail(HEGET_E_OOM, "probe allocation failed");
+  heget_status rc = HEGET_OK;
+  for (int h = 0; h < nh && rc == HEGET_OK; ++h) {
+    KernelArgs a = base_args(p);
+    a.hel = p->d_hel + size_t(h) * nl;
+    a.n_hel = 1;
+    a.n = n_probe;
+    a.mom_stride = n_probe;
+    a.seed = seed;
+    a.sqrt_s = sqrt_s;
+    a.me2_out = d_me2 + size_t(h) * n_probe;
+    rc = launch(p, a, nullptr);
+  }
+  std::vector<double> me(size_t(nh) * n_probe);
+  if (rc == HEGET_OK && (hipMemcpy(me.data(), d_me2, me.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+    rc = fail(HEGET_E_HIP, "probe copy failed");
+  (void)hipFree(d_me2);
+  if (rc != HEGET_OK) return rc;
+  std::vector<int8_t> kept;
+  int nk = 0;
+  for (int h = 0; h < nh; ++h) {
+    bool keep = false;
+    for (int64_t e = 0; e < n_probe && !keep; ++e) {
+      double mx = 0.0;
+      for (int g = 0; g < nh; ++g) mx = std::max(mx, me[size_t(g) * n_probe + e]);
+      keep = me[size_t(h) * n_probe + e] > rel_threshold * mx;
+    }
+    if (keep) {
+      kept.insert(kept.end(), p->hel.begin() + size_t(h) * nl, p->hel.begin() + size_t(h + 1) * nl);
+      ++nk;
+    }
+  }
+  if (nk == 0) return fail(HEGET_E_INVALID, "every helicity vanished on the probe events");
+  if (hipMemcpy(p->d_hel, kept.data(), kept.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(HEGET_E_HIP, "helicity table upload failed");
+  p->hel = kept;
+  p->n_hel = nk;
+  *n_kept = nk;
+  return HEGET_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,33 @@
+// Arguments shared by every generated amplitude kernel and the library.
+#pragma once
+#include <stdint.h>
+
+namespace heget {
+
+// Per-particle propagator data, filled by the library from the SM inputs.
+struct PropEntry {
+  double m, w;            // mass and width
+  double pole_r, pole_i;  // pole of the denominator q^2 - pole (m^2 - i m Gamma, or the complex mass)
+  double inum_r, inum_i;  // 1 / (mass^2 in the unitary-gauge numerator)
+};
+
+struct KernelArgs {
+  int64_t n;                 // events in this launch
+  const double* mom_in;      // SoA [n_legs][4][n] physical momenta, or null (generate)
+  int64_t mom_stride;        // n of the SoA arrays (>= n)
+  uint64_t seed;             // Philox key
+  uint64_t counter_offset;   // event index of the first event of this launch
+  double sqrt_s;
+  double* me2_out;           // [n] helicity- and colour-summed |M|^2, or null
+  double* mom_out;           // SoA [n_legs][4][mom_stride] or null
+  const int8_t* hel;         // [n_hel][n_legs]
+  int32_t n_hel;
+  int32_t cut_enabled;
+  const double* cpl;         // 4 doubles per coupling: g0 (re, im), g1 (re, im)
+  const PropEntry* prop;     // indexed by particle id
+  double cut_pt, cut_dr;
+  double weight_factor;      // phase-space weight x flux x averages x 1/S (integrate)
+  double* partials;          // integrate: [gridDim.x][3] (sum w, sum w^2, accepted), or null
+};
+
+}  // namespace heget

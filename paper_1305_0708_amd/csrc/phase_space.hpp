@@ -1,0 +1,106 @@
+// Counter-based uniforms, RAMBO momenta and the gluon generation cut (device).
+//
+// Philox4x32-10 follows its published definition (Salmon et al., SC'11): ten
+// rounds of two 32x32->64-bit products with the Weyl key schedule.  Counter
+// layout per event i: (i_lo, i_hi, block j, 0), key (seed_lo, seed_hi); each
+// block gives two uniforms u = (floor(x / 2^12) + 1/2) 2^-52 from the 64-bit
+// words x = w0 2^32 + w1 and x = w2 2^32 + w3 (exact in FP64, strictly inside
+// (0,1)).  RAMBO (Kleiss, Stirling, Ellis 1986) draws per particle
+// (cos theta, phi, u3, u4) and maps to massless momenta at sqrt_s; its weight is
+// the closed-form n-body volume of the paper's invariant phase space (Sec. 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "heget_device.hpp"
+
+namespace heget {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t a0 = c[0], a2 = c[2];
+    const uint32_t hi0 = __umulhi(0xD2511F53u, a0), lo0 = 0xD2511F53u * a0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, a2), lo1 = 0xCD9E8D57u * a2;
+    c[0] = hi1 ^ c[1] ^ k0;
+    c[1] = lo1;
+    c[2] = hi0 ^ c[3] ^ k1;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double unit_open(uint32_t hi, uint32_t lo) {
+  const uint64_t x = (uint64_t(hi) << 32) | uint64_t(lo);
+  return (double(x >> 12) + 0.5) * 0x1.0p-52;
+}
+
+// RAMBO for NOUT massless particles; writes the physical momenta p[0..NOUT-1]
+template <int NOUT>
+__device__ __forceinline__ void rambo(uint64_t seed, uint64_t event, double sqrt_s, mom* p) {
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0, Q3 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NOUT; ++k) {
+    double u[4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      uint32_t c[4] = {uint32_t(event), uint32_t(event >> 32), uint32_t(2 * k + b), 0u};
+      philox4x32_10(c, k0, k1);
+      u[2 * b] = unit_open(c[0], c[1]);
+      u[2 * b + 1] = unit_open(c[2], c[3]);
+    }
+    const double ct = 2.0 * u[0] - 1.0;
+    const double st = sqrt(1.0 - ct * ct);
+    double sf, cf;
+    sincos(6.283185307179586476925 * u[1], &sf, &cf);
+    const double e = -log(u[2] * u[3]);
+    p[k] = {e, e * st * cf, e * st * sf, e * ct};
+    Q0 += p[k].e;
+    Q1 += p[k].x;
+    Q2 += p[k].y;
+    Q3 += p[k].z;
+  }
+  const double M = sqrt(Q0 * Q0 - Q1 * Q1 - Q2 * Q2 - Q3 * Q3);
+  const double iM = 1.0 / M;
+  const double b1 = -Q1 * iM, b2 = -Q2 * iM, b3 = -Q3 * iM;
+  const double g = Q0 * iM;
+  const double a = 1.0 / (1.0 + g);
+  const double x = sqrt_s * iM;
+#pragma unroll
+  for (int k = 0; k < NOUT; ++k) {
+    const double bq = b1 * p[k].x + b2 * p[k].y + b3 * p[k].z;
+    const double q0 = p[k].e;
+    p[k] = {x * (g * q0 + bq), x * (p[k].x + b1 * q0 + a * bq * b1), x * (p[k].y + b2 * q0 + a * bq * b2),
+            x * (p[k].z + b3 * q0 + a * bq * b3)};
+  }
+}
+
+// every final particle has pT > pt_min and every final pair Delta R > dr_min
+template <int NOUT>
+__device__ __forceinline__ bool pass_pt_dr(const mom* p, double pt_min, double dr_min) {
+  double eta[NOUT], phi[NOUT];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < NOUT; ++k) {
+    const double pt = sqrt(p[k].x * p[k].x + p[k].y * p[k].y);
+    const double pp = sqrt(pt * pt + p[k].z * p[k].z);
+    ok = ok && (pt > pt_min);
+    eta[k] = 0.5 * log((pp + p[k].z) / (pp - p[k].z));
+    phi[k] = atan2(p[k].y, p[k].x);
+  }
+  const double pi = 3.14159265358979323846;
+#pragma unroll
+  for (int k = 0; k < NOUT; ++k)
+#pragma unroll
+    for (int l = k + 1; l < NOUT; ++l) {
+      double dphi = fabs(phi[k] - phi[l]);
+      if (dphi > pi) dphi = 2.0 * pi - dphi;
+      const double deta = eta[k] - eta[l];
+      ok = ok && (sqrt(deta * deta + dphi * dphi) > dr_min);
+    }
+  return ok;
+}
+
+}  // namespace heget

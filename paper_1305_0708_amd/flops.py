@@ -1,0 +1,79 @@
+"""Algorithmic floating-point operation counts of the amplitude path.
+
+Counted from the device functions as written (heget_device.hpp): a complex
+multiply is 6 flops, a complex add 2, a real-times-complex product 2; square
+roots, divisions and transcendentals are counted as one operation each.  Per
+event, the helicity loop executes the external wavefunctions, every call of
+the IR, the jamp sums and the colour form once per helicity combination; the
+momenta, internal-line momenta and propagator denominators are formed once.
+"""
+from .ir import AMP_OPS, F, V, S, P_ZERO, P_W, P_Z
+
+CMUL, CADD, RMUL = 6, 2, 2
+DOT_CC = 4 * CMUL + 3 * CADD          # 30: complex four-vector dot
+DOT_CR = 4 * RMUL + 3 * CADD          # 14: complex . real four-vector
+WEYL_C = 4 + 2 * (2 + 2 * CMUL + CADD)  # 36: 2x2 sigma.V on a 2-spinor, V complex
+WEYL_R = 2 * (1 + RMUL + CMUL + CADD)   # 22: the same with a real momentum
+PROP_MASSLESS = 4 * CMUL              # 24: A / D
+PROP_MASSIVE = DOT_CR + CMUL + 4 * (RMUL + CADD) + PROP_MASSLESS   # 60: unitary gauge
+
+OP_FLOPS = {
+    "iov": 2 * WEYL_C + 2 * (3 * CMUL + CADD) + CADD,           # 114
+    "ffv_current": 8 * CMUL + 4 * (2 * CMUL + 3 * CADD),        # 120
+    "fvi": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
+    "fvo": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
+    "ios": 2 * (2 * CMUL + CADD) + 2 * CMUL + CADD + CMUL,      # 48
+    "hio": 2 * (2 * CMUL + CADD) + 2 * CMUL + CADD + CMUL,      # 48
+    "fsi": 4 * CMUL + 2 * WEYL_R + CMUL + RMUL + 4 * (2 * CMUL + CADD),      # 134
+    "fso": 4 * CMUL + 2 * WEYL_R + CMUL + RMUL + 4 * (2 * CMUL + CADD),      # 134
+    "vvv": 12 + 3 * DOT_CC + 3 * DOT_CR + 3 * CMUL + 2 * CADD + RMUL,       # 168
+    "jvv_vertex": 4 + 8 + 8 + DOT_CC + 2 * DOT_CR + 4 * (RMUL + 2 * CMUL + 2 * CADD + RMUL) + 4,  # 162
+    "gggg": 4 * DOT_CC + 2 * CMUL + CADD + RMUL,                # 136
+    "jggg_vertex": 2 * DOT_CC + 2 * RMUL + 4 * (2 * CMUL + CADD),            # 120
+    "wwww": 2 * (4 * DOT_CC + 2 * CMUL + CADD + RMUL) + CADD,   # 274
+    "jwww_vertex": 3 * DOT_CC + 4 * (4 * CMUL + 3 * CADD) + 4 * RMUL,        # 218
+    "vvs": DOT_CC + 2 * CMUL,                                   # 42
+    "jvs_vertex": CMUL + 4 * CMUL,                              # 30
+    "hvv": DOT_CC + 2 * CMUL,                                   # 42
+    "vvss": DOT_CC + 3 * CMUL,                                  # 48
+    "jvss_vertex": 2 * CMUL + 4 * CMUL,                         # 36
+    "hvvs": DOT_CC + 3 * CMUL,                                  # 48
+    "sss": 3 * CMUL,                                            # 18
+    "hss": 3 * CMUL,                                            # 18
+    "ssss": 4 * CMUL,                                           # 24
+    "hsss": 4 * CMUL,                                           # 24
+}
+EXTERNAL = {"f_massless": 6, "f_massive": 30, "v": 24, "s": 0}
+MASSIVE = {P_W, P_Z}
+
+
+def call_flops(c):
+    op = c.op
+    prop = PROP_MASSIVE if c.prop in MASSIVE else PROP_MASSLESS
+    if op == "jio":
+        return OP_FLOPS["ffv_current"] + prop
+    if op in ("jvv", "jggg", "jwww", "jvs", "jvss"):
+        return OP_FLOPS[op + "_vertex"] + prop
+    return OP_FLOPS[op]
+
+
+def per_helicity(proc):
+    """flops of one helicity combination of one event"""
+    n = 0
+    for leg in proc.legs:
+        if leg.kind == F:
+            n += EXTERNAL["f_massless"] if leg.particle == P_ZERO else EXTERNAL["f_massive"]
+        elif leg.kind == V:
+            n += EXTERNAL["v"]
+    n += sum(call_flops(c) for c in proc.calls)
+    n += sum(CADD * max(len(t) - 1, 0) for t in proc.jamp)          # jamp sums
+    nf = proc.n_flows
+    n += nf * 4 + (nf * (nf - 1) // 2) * 4 + 2                      # colour quadratic form
+    return n
+
+
+def per_event(proc, n_hel=None):
+    """flops of one event: helicity loop plus the per-event denominators"""
+    nh = len(proc.helicities) if n_hel is None else n_hel
+    n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS)
+    return nh * per_helicity(proc) + n_cur * (7 + 8)

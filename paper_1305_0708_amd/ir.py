@@ -1,0 +1,230 @@
+"""Process IR: the data a process is created from.
+
+The IR plays the role the paper gives to MadGraph's generated amplitude
+routine as converted by MG2CUDA (Sec. 5): external legs, the list of
+HEGET-style vertex/propagator calls (Sec. 4, Tables of external-line and vertex
+functions), the decomposition of the amplitudes into colour flows (jamps) and
+the colour matrix (Sec. 5.4), plus the helicity combinations to sum over.
+
+It is plain data; ``heget_process_create`` receives it as C structs
+(``include/heget.h``) and ``codegen`` turns the structural part into a
+straight-line HIP kernel.  SM parameter values, the helicity table and the cut
+thresholds are runtime data and are not part of the kernel's fingerprint.
+"""
+from dataclasses import dataclass, field
+from fractions import Fraction
+from typing import List, Optional, Tuple
+import struct
+
+# leg kinds
+F, V, S = 0, 1, 2
+# particle ids used for masses / widths (index into the runtime mass table)
+P_ZERO, P_W, P_Z, P_TOP, P_H = 0, 1, 2, 3, 4
+PARTICLE_NAMES = {P_ZERO: "zero", P_W: "W", P_Z: "Z", P_TOP: "top", P_H: "H"}
+
+# call opcodes (HEGET function equivalents)
+OPS = [
+    "iov", "fvi", "fvo", "jio",            # FFV
+    "ios", "fsi", "fso", "hio",            # FFS
+    "vvv", "jvv",                          # VVV
+    "gggg", "jggg", "wwww", "jwww",        # VVVV
+    "vvs", "jvs", "hvv",                   # VVS
+    "vvss", "jvss", "hvvs",                # VVSS
+    "sss", "hss", "ssss", "hsss",          # SSS, SSSS
+]
+OP = {name: i for i, name in enumerate(OPS)}
+AMP_OPS = {"iov", "ios", "vvv", "gggg", "wwww", "vvs", "vvss", "sss", "ssss"}
+# kind of the output wavefunction of each current op
+OUT_KIND = {"fvi": F, "fvo": F, "jio": V, "fsi": F, "fso": F, "hio": S, "jvv": V, "jggg": V,
+            "jwww": V, "jvs": V, "hvv": S, "jvss": V, "hvvs": S, "hss": S, "hsss": S}
+# input kinds per op (in argument order)
+IN_KINDS = {
+    "iov": (F, F, V), "fvi": (F, V), "fvo": (F, V), "jio": (F, F),
+    "ios": (F, F, S), "fsi": (F, S), "fso": (F, S), "hio": (F, F),
+    "vvv": (V, V, V), "jvv": (V, V),
+    "gggg": (V, V, V, V), "jggg": (V, V, V), "wwww": (V, V, V, V), "jwww": (V, V, V),
+    "vvs": (V, V, S), "jvs": (V, S), "hvv": (V, V),
+    "vvss": (V, V, S, S), "jvss": (V, S, S), "hvvs": (V, V, S),
+    "sss": (S, S, S), "hss": (S, S), "ssss": (S, S, S, S), "hsss": (S, S, S),
+}
+
+# coupling kinds (values are derived from the SM inputs by the library)
+CPL_KINDS = ["gamma_ff", "z_ff", "w_ff", "g_qq", "ggg", "gggg", "wwz", "wwa",
+             "wwh", "zzh", "wwhh", "zzhh", "hhh", "hhhh", "hbb", "wwww", "wwzz"]
+CPL = {name: i for i, name in enumerate(CPL_KINDS)}
+
+
+@dataclass(frozen=True)
+class Leg:
+    kind: int            # F, V or S
+    incoming: bool
+    flow: int = 1        # fermions: +1 particle, -1 antiparticle
+    particle: int = P_ZERO
+    colour: int = 1      # 1, 3 or 8
+    name: str = ""
+
+
+@dataclass(frozen=True)
+class Coupling:
+    kind: str
+    charge: float = 0.0  # electric charge Q (gamma_ff, z_ff)
+    t3: float = 0.0      # weak isospin T3 (z_ff)
+    particle: int = P_ZERO  # reserved
+
+
+@dataclass(frozen=True)
+class Call:
+    op: str
+    ins: Tuple[int, ...]
+    out: int             # output slot (currents) or amplitude index (amplitude ops)
+    cpl: int = -1        # index into Process.couplings
+    prop: int = P_ZERO   # propagator particle of a current
+
+
+@dataclass
+class Process:
+    name: str
+    legs: List[Leg]
+    couplings: List[Coupling]
+    calls: List[Call]
+    n_amps: int
+    n_flows: int
+    jamp: List[List[Tuple[int, complex]]]       # per flow: (amp index, coefficient)
+    colour: List[List[Fraction]]                # n_flows x n_flows
+    helicities: List[Tuple[int, ...]]
+    sqrt_s: float
+    n_a_n_b: int
+    symmetry: int
+    cut_pt: float = 0.0
+    cut_dr: float = 0.0
+    cut_enabled: bool = False
+    sm_overrides: dict = field(default_factory=dict)
+
+    @property
+    def n_legs(self):
+        return len(self.legs)
+
+    def n_slots(self):
+        m = self.n_legs - 1
+        for c in self.calls:
+            if c.op not in AMP_OPS:
+                m = max(m, c.out)
+        return m + 1
+
+    def colour_denominator(self):
+        d = 1
+        for row in self.colour:
+            for x in row:
+                d = d * Fraction(x).denominator // _gcd(d, Fraction(x).denominator)
+        return d
+
+    def validate(self):
+        kinds = {i: leg.kind for i, leg in enumerate(self.legs)}
+        amps = set()
+        for k, c in enumerate(self.calls):
+            if c.op not in OP:
+                raise ValueError(f"call {k}: unknown op {c.op}")
+            want = IN_KINDS[c.op]
+            if len(c.ins) != len(want):
+                raise ValueError(f"call {k}: {c.op} takes {len(want)} inputs")
+            for s, w in zip(c.ins, want):
+                if s not in kinds:
+                    raise ValueError(f"call {k}: slot {s} used before it is defined")
+                if kinds[s] != w:
+                    raise ValueError(f"call {k}: slot {s} has the wrong kind for {c.op}")
+            if c.op in AMP_OPS:
+                if not (0 <= c.out < self.n_amps) or c.out in amps:
+                    raise ValueError(f"call {k}: bad amplitude index {c.out}")
+                amps.add(c.out)
+            else:
+                if c.out in kinds:
+                    raise ValueError(f"call {k}: slot {c.out} defined twice")
+                kinds[c.out] = OUT_KIND[c.op]
+            if not (0 <= c.cpl < len(self.couplings)):
+                raise ValueError(f"call {k}: bad coupling index")
+        if amps != set(range(self.n_amps)):
+            raise ValueError("every amplitude index must be produced exactly once")
+        if len(self.jamp) != self.n_flows or len(self.colour) != self.n_flows:
+            raise ValueError("jamp / colour sizes disagree with n_flows")
+        for r in range(self.n_flows):
+            for c in range(self.n_flows):
+                if self.colour[r][c] != self.colour[c][r]:
+                    raise ValueError("colour matrix must be symmetric")
+        for h in self.helicities:
+            if len(h) != self.n_legs:
+                raise ValueError("helicity row length != number of legs")
+        return self
+
+    # -------------------------------------------------------------- fingerprint
+    def structure_bytes(self):
+        """Canonical serialisation of the parts baked into the kernel: legs,
+        couplings' kinds, calls, jamp coefficients, colour matrix, cut kind.
+        Must match fingerprint() in the library (FNV-1a over the same bytes)."""
+        b = bytearray()
+        i32 = lambda x: b.extend(struct.pack("<i", int(x)))
+        f64 = lambda x: b.extend(struct.pack("<d", float(x)))
+        i32(self.n_legs)
+        for leg in self.legs:
+            for x in (leg.kind, int(leg.incoming), leg.flow, leg.particle, leg.colour):
+                i32(x)
+        i32(len(self.couplings))
+        for c in self.couplings:
+            i32(CPL[c.kind])
+            f64(c.charge)
+            f64(c.t3)
+            i32(c.particle)
+        i32(len(self.calls))
+        for c in self.calls:
+            i32(OP[c.op])
+            ins = list(c.ins) + [-1] * (4 - len(c.ins))
+            for x in ins:
+                i32(x)
+            for x in (c.out, c.cpl, c.prop):
+                i32(x)
+        i32(self.n_amps)
+        i32(self.n_flows)
+        for f, terms in enumerate(self.jamp):
+            for a in range(self.n_amps):
+                coef = 0j
+                for (ai, cc) in terms:
+                    if ai == a:
+                        coef += cc
+                f64(coef.real)
+                f64(coef.imag)
+        den = self.colour_denominator()
+        for row in self.colour:
+            for x in row:
+                f64(float(Fraction(x) * den))
+        f64(float(den))
+        i32(int(self.cut_enabled))
+        return bytes(b)
+
+    def fingerprint(self):
+        h = 0xCBF29CE484222325
+        for byte in self.structure_bytes():
+            h ^= byte
+            h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+        return h
+
+
+def _gcd(a, b):
+    while b:
+        a, b = b, a % b
+    return a
+
+
+def all_helicities(legs, massive_vector_states=False):
+    """All helicity combinations in lexicographic order, last leg fastest:
+    fermions and massless vectors -1, +1; massive vectors -1, 0, +1; scalars 0."""
+    choices = []
+    for leg in legs:
+        if leg.kind == S:
+            choices.append((0,))
+        elif leg.kind == V and leg.particle != P_ZERO:
+            choices.append((-1, 0, 1))
+        else:
+            choices.append((-1, 1))
+    out = [()]
+    for ch in choices:
+        out = [h + (c,) for h in out for c in ch]
+    return out

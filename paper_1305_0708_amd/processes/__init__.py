@@ -1,0 +1,126 @@
+"""Process IRs of the benchmark workloads.
+
+Each builder returns an ``ir.Process``: the HEGET-style call list with its
+colour decomposition, written out the way the paper's generated integrands
+call the HEGET functions (Sec. 5.1) with the colour factors of Sec. 4.2:
+quark-gluon vertex -T^a x (FFV output), triple-gluon vertex i f^abc x (VVV
+output), four-gluon vertex f f x (VVVV output, three colour structures).
+
+Leg order (the momentum layout of heget_eval):
+  ee_mumu      e-(in, +z) e+(in, -z) mu- mu+
+  gg_ttbar_6f  g g b e+ nu_e bbar mu- nu_mu~      (t -> b e+ nu_e, tbar -> bbar mu- nu_mu~)
+  ud_udhh_4b   u d u d b bbar b bbar              (H -> b bbar twice)
+  gg_4g        g g g g g g
+"""
+from fractions import Fraction
+
+from .. import ir
+from ..ir import F, V, S, P_ZERO, P_W, P_Z, P_TOP, P_H, Leg, Call, Coupling, Process
+
+Q_U, Q_D, Q_E = 2.0 / 3.0, -1.0 / 3.0, -1.0
+
+
+def ee_mumu(sqrt_s=200.0):
+    """e+ e- -> mu+ mu- via s-channel photon and Z (2 diagrams, 1 colour flow)."""
+    legs = [Leg(F, True, +1, name="e-"), Leg(F, True, -1, name="e+"),
+            Leg(F, False, +1, name="mu-"), Leg(F, False, -1, name="mu+")]
+    cpl = [Coupling("gamma_ff", charge=Q_E), Coupling("z_ff", charge=Q_E, t3=-0.5)]
+    calls = [
+        Call("jio", (0, 1), 4, 0, P_ZERO),      # photon current from e- (|fi>) and e+ (<fo|)
+        Call("iov", (3, 2, 4), 0, 0),           # <mu-| A |mu+>
+        Call("jio", (0, 1), 5, 1, P_Z),         # Z current
+        Call("iov", (3, 2, 5), 1, 1),
+    ]
+    return Process("ee_mumu", legs, cpl, calls, n_amps=2, n_flows=1,
+                   jamp=[[(0, 1.0), (1, 1.0)]], colour=[[Fraction(1)]],
+                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=1, symmetry=1).validate()
+
+
+def gg_ttbar_6f(sqrt_s=1000.0):
+    """g g -> t tbar, t -> b e+ nu_e, tbar -> bbar mu- nu_mu~ with Breit-Wigner
+    tops and W's: s-channel gluon, t- and u-channel top (3 diagrams).
+
+    Colour: T = (T^a T^b)_ij (gluon 0 next to the top), U = (T^b T^a)_ij,
+    S = (i f^abc)(-T^c) = -[T^a, T^b].  Flows are the two orderings
+    {(T^a T^b)_ij, (T^b T^a)_ij}; colour matrix [[16/3, -2/3], [-2/3, 16/3]]."""
+    legs = [Leg(V, True, colour=8, name="g"), Leg(V, True, colour=8, name="g"),
+            Leg(F, False, +1, colour=3, name="b"), Leg(F, False, -1, name="e+"),
+            Leg(F, False, +1, name="nu_e"), Leg(F, False, -1, colour=3, name="bbar"),
+            Leg(F, False, +1, name="mu-"), Leg(F, False, -1, name="nu_mu~")]
+    cpl = [Coupling("w_ff"), Coupling("g_qq"), Coupling("ggg")]
+    W, GQ, GGG = 0, 1, 2
+    calls = [
+        Call("jio", (3, 4), 8, W, P_W),          # W+ -> e+ nu_e
+        Call("jio", (7, 6), 9, W, P_W),          # W- -> mu- nu_mu~
+        Call("fvo", (2, 8), 10, W, P_TOP),       # <t| from <b| and the W+
+        Call("fvi", (5, 9), 11, W, P_TOP),       # |tbar> from |bbar> and the W-
+        Call("jvv", (0, 1), 12, GGG, P_ZERO),    # s-channel gluon
+        Call("iov", (11, 10, 12), 0, GQ),
+        Call("fvo", (10, 0), 13, GQ, P_TOP),     # gluon 0 next to the top
+        Call("iov", (11, 13, 1), 1, GQ),
+        Call("fvo", (10, 1), 14, GQ, P_TOP),     # gluon 1 next to the top
+        Call("iov", (11, 14, 0), 2, GQ),
+    ]
+    jamp = [[(1, 1.0), (0, -1.0)], [(2, 1.0), (0, 1.0)]]
+    colour = [[Fraction(16, 3), Fraction(-2, 3)], [Fraction(-2, 3), Fraction(16, 3)]]
+    return Process("gg_ttbar_6f", legs, cpl, calls, n_amps=3, n_flows=2, jamp=jamp, colour=colour,
+                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64, symmetry=1).validate()
+
+
+def ud_udhh_4b(sqrt_s=2000.0):
+    """u d -> u d H H via W W and Z Z fusion, each H -> b bbar (16 diagrams).
+
+    For each fusion class V in {Z Z, W W} and b pairing in {(b0 bbar1)(b2 bbar3),
+    (b0 bbar3)(b2 bbar1)}: contact VVHH, s-channel H* -> H H, and t-/u-channel
+    V exchange.  The W W class pairs the quark lines differently from Z Z and the
+    second b pairing swaps two identical fermions: each carries a Fermi sign -1.
+    Colour flows (quark pairing) x (b pairing), matrix [[9,3],[3,9]] (x) [[9,3],[3,9]]."""
+    legs = [Leg(F, True, +1, colour=3, name="u"), Leg(F, True, +1, colour=3, name="d"),
+            Leg(F, False, +1, colour=3, name="u"), Leg(F, False, +1, colour=3, name="d"),
+            Leg(F, False, +1, colour=3, name="b"), Leg(F, False, -1, colour=3, name="bbar"),
+            Leg(F, False, +1, colour=3, name="b"), Leg(F, False, -1, colour=3, name="bbar")]
+    cpl = [Coupling("z_ff", charge=Q_U, t3=0.5), Coupling("z_ff", charge=Q_D, t3=-0.5),
+           Coupling("w_ff"), Coupling("hbb"),
+           Coupling("zzh"), Coupling("wwh"), Coupling("zzhh"), Coupling("wwhh"), Coupling("hhh")]
+    ZU, ZD, W, HB, ZZH, WWH, ZZHH, WWHH, HHH = range(9)
+    calls = []
+    slot = [8]
+
+    def cur(op, ins, cp, prop):
+        s = slot[0]
+        slot[0] += 1
+        calls.append(Call(op, ins, s, cp, prop))
+        return s
+    # Higgs currents for both b pairings
+    hA = (cur("hio", (5, 4), HB, P_H), cur("hio", (7, 6), HB, P_H))
+    hB = (cur("hio", (7, 4), HB, P_H), cur("hio", (5, 6), HB, P_H))
+    classes = [
+        # (V1 current, V2 current, boson, vvh coupling, vvhh coupling, sign)
+        (cur("jio", (0, 2), ZU, P_Z), cur("jio", (1, 3), ZD, P_Z), P_Z, ZZH, ZZHH, +1.0),
+        (cur("jio", (0, 3), W, P_W), cur("jio", (1, 2), W, P_W), P_W, WWH, WWHH, -1.0),
+    ]
+    amp = 0
+    jamp = [[] for _ in range(4)]
+    for ci, (v1, v2, boson, c3, c4, sgn) in enumerate(classes):
+        hs = cur("hvv", (v1, v2), c3, P_H)
+        for pi, (h1, h2) in enumerate((hA, hB)):
+            psign = sgn * (1.0 if pi == 0 else -1.0)
+            flow = ci + 2 * pi
+            calls.append(Call("vvss", (v1, v2, h1, h2), amp, c4)); jamp[flow].append((amp, psign)); amp += 1
+            calls.append(Call("sss", (hs, h1, h2), amp, HHH)); jamp[flow].append((amp, psign)); amp += 1
+            vt = cur("jvs", (v1, h1), c3, boson)
+            calls.append(Call("vvs", (vt, v2, h2), amp, c3)); jamp[flow].append((amp, psign)); amp += 1
+            vu = cur("jvs", (v1, h2), c3, boson)
+            calls.append(Call("vvs", (vu, v2, h1), amp, c3)); jamp[flow].append((amp, psign)); amp += 1
+    cq = [[9, 3], [3, 9]]
+    colour = [[Fraction(cq[a % 2][b % 2] * cq[a // 2][b // 2]) for b in range(4)] for a in range(4)]
+    return Process("ud_udhh_4b", legs, cpl, calls, n_amps=amp, n_flows=4, jamp=jamp, colour=colour,
+                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=9, symmetry=4,
+                   sm_overrides={"complex_mass": 1}).validate()
+
+
+def by_name(name):
+    if name == "gg_4g":
+        from .gluons import gg_ng
+        return gg_ng(6)
+    return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "ud_udhh_4b": ud_udhh_4b}[name]()
