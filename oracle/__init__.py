@@ -153,6 +153,20 @@ def me2(proc, mom, prm=None, threads=0):
     return out
 
 
+def condition(proc, mom, prm=None, threads=0):
+    """Per-event conditioning kappa of the diagram sum (see oracle.h)."""
+    prm = prm or params()
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    if mom.ndim == 2:
+        mom = mom[None]
+    out = np.zeros(mom.shape[0])
+    lib().or_condition.argtypes = [ctypes.c_int, ctypes.POINTER(Params), ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    if lib().or_condition(proc, ctypes.byref(prm), mom.shape[0], _dp(mom), _dp(out), threads) != 0:
+        raise ValueError(f"oracle: no diagram list for process {proc}")
+    return out
+
+
 def amp_colour(proc, mom, hel, col, prm=None):
     prm = prm or params()
     mom = np.ascontiguousarray(mom, dtype=np.float64)

@@ -62,6 +62,29 @@ extern "C" int or_eval(int proc, const or_params* prm, int64_t n_events, const d
   return 0;
 }
 
+extern "C" int or_condition(int proc, const or_params* prm, int64_t n_events, const double* mom, double* kappa,
+                            int n_threads) {
+  const SM sm(*prm);
+  const ProcDef* P = find_proc(proc);
+  if (!P) return -1;
+  const auto& C = colour_assignments(proc, *P);
+  const auto hels = helicity_table(*P);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_events; ++i) {
+    Vec4 p[16];
+    load(mom + i * P->nlegs * 4, P->nlegs, p);
+    double a2 = 0.0, b2 = 0.0;
+    for (const auto& h : hels) condition_one_helicity(*P, C, sm, p, h.data(), a2, b2);
+    kappa[i] = std::sqrt(b2 / a2);
+  }
+  return 0;
+}
+
 extern "C" int or_amp_colour(int proc, const or_params* prm, const double* mom, const int* hel, const int* col,
                              double* out) {
   const ProcDef* P = find_proc(proc);

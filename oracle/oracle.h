@@ -82,6 +82,13 @@ void or_cut_gluons(int64_t n_events, int n_legs, const double* mom, double pt_mi
 int or_eval(int proc, const or_params* prm, int64_t n_events, const double* mom, double* me2,
             int n_threads);
 
+/* Conditioning of the diagram sum per event (processes with a diagram list):
+ * kappa = sqrt( sum_{hel,col} (sum_d |c_d M_d|)^2 / sum_{hel,col} |sum_d c_d M_d|^2 ),
+ * the factor by which rounding errors of the individual diagrams are amplified
+ * in the relative error of F.  kappa >= 1; 1 means no cancellation. */
+int or_condition(int proc, const or_params* prm, int64_t n_events, const double* mom, double* kappa,
+                 int n_threads);
+
 /* Amplitude for one helicity combination and one explicit colour assignment
  * (processes with quarks: 1, 3, 14).  Colour indices: gluons 0..7, quarks 0..2,
  * one per leg (ignored for colourless legs).  out = {re, im}. */

@@ -380,6 +380,25 @@ double me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& co
   return s;
 }
 
+// Conditioning of the diagram sum for one helicity: accumulates
+// sum_col |sum_d c_d M_d|^2 into a2 and sum_col (sum_d |c_d M_d|)^2 into b2.
+void condition_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm,
+                            const Vec4* p, const int* h, double& a2, double& b2) {
+  const int nd = P.ndiag;
+  std::vector<cd> M(nd);
+  P.amp(sm, p, h, M.data());
+  for (const auto& c : cols) {
+    cd a = 0;
+    double b = 0;
+    for (int d = 0; d < nd; ++d) {
+      a += c[d] * M[d];
+      b += std::abs(c[d] * M[d]);
+    }
+    a2 += std::norm(a);
+    b2 += b * b;
+  }
+}
+
 // ------------------------------------------------ trace-based 2 -> 2 pins
 // Spin sums from the completeness relations sum u ubar = pslash + m,
 // sum v vbar = pslash - m and the physical gluon polarisation sum

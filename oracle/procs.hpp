@@ -24,6 +24,8 @@ const std::vector<std::vector<cd>>& colour_assignments(int id, const ProcDef& P)
 double me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm, const Vec4* p,
                         const int* h);
 double trace_me2(int id, const SM& sm, const Vec4* p);
+void condition_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm,
+                            const Vec4* p, const int* h, double& a2, double& b2);
 
 // n-gluon Berends-Giele
 double gluon_me2(int n, const SM& sm, const Vec4* p);

@@ -105,6 +105,10 @@ class Process:
             raise ValueError("n is required when momenta are generated")
         sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
         dev = momenta.device if momenta is not None else torch.device("cuda")
+        if n < 0:
+            # let the library report the invalid size
+            check(self._lib.heget_eval(self._h, n, None, seed, counter_offset, float(sqrt_s), None, None,
+                                       self._stream(stream)))
         if me2_out is None:
             me2_out = torch.empty(n, dtype=torch.float64, device=dev)
         if want_momenta and momenta_out is None:

@@ -136,8 +136,18 @@ class Gen:
             w(f"  const cx<T> d{s} = cvt<T>(inv_denominator(q{s}, cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
         for s in sorted(self.need_q):
             w(f"  const vec<T> Q{s} = tv<T>(q{s});")
-        for k in range(self.nl):
-            w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
+        for k, leg in enumerate(p.legs):
+            if leg.kind == F and leg.particle == P_ZERO:
+                # helicity-independent Weyl factors, formed in FP64
+                w(f"  const MLF<T> e{k} = mlf_pre<T>(p[{k}]);")
+            elif leg.kind == F:
+                # massive external fermion: both helicity states in FP64
+                fn = "ixxxxx" if self._flowing_in(leg) else "oxxxxx"
+                for lam, tag in ((-1, "m"), (1, "p")):
+                    w(f"  const wf<T> e{k}{tag} = cvtw<T>({fn}<double, false>(tv<double>(p[{k}]), "
+                      f"pe{leg.particle}.m, {lam}, {leg.flow}));")
+            elif leg.kind == V:
+                w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
         w("  double me2 = 0.0;")
         w("  if (pass) {")
         w("    for (int h = 0; h < a.n_hel; ++h) {")
@@ -164,16 +174,20 @@ class Gen:
         w("}  // namespace heget")
         return "\n".join(L) + "\n"
 
+    @staticmethod
+    def _flowing_in(leg):
+        return (leg.incoming and leg.flow > 0) or ((not leg.incoming) and leg.flow < 0)
+
     def _external(self, w, k, leg):
-        m = f"T(pe{leg.particle}.m)"
         if leg.kind == F:
-            flowing_in = (leg.incoming and leg.flow > 0) or ((not leg.incoming) and leg.flow < 0)
-            fn = "ixxxxx" if flowing_in else "oxxxxx"
-            ml = "true" if leg.particle == P_ZERO else "false"
-            w(f"      const wf<T> w{k} = {fn}<T, {ml}>(P{k}, {m}, hh[{k}], {leg.flow});")
+            if leg.particle == P_ZERO:
+                fn = "ixxxxx0" if self._flowing_in(leg) else "oxxxxx0"
+                w(f"      const wf<T> w{k} = {fn}<T>(e{k}, hh[{k}], {leg.flow});")
+            else:
+                w(f"      const wf<T> w{k} = hh[{k}] > 0 ? e{k}p : e{k}m;")
         elif leg.kind == V:
             nsv = -1 if leg.incoming else 1
-            w(f"      const wf<T> w{k} = vxxxxx<T>(P{k}, {m}, hh[{k}], {nsv});")
+            w(f"      const wf<T> w{k} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), hh[{k}], {nsv});")
         else:
             w(f"      const cx<T> w{k} = sxxxxx<T>();")
 

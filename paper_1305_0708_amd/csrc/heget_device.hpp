@@ -82,6 +82,11 @@ struct wf {
   cx<T> c[4];
 };
 
+template <class T, class S>
+__device__ __forceinline__ wf<T> cvtw(const wf<S>& a) {
+  return {{cvt<T>(a.c[0]), cvt<T>(a.c[1]), cvt<T>(a.c[2]), cvt<T>(a.c[3])}};
+}
+
 // Minkowski product of two complex vectors (no conjugation)
 template <class T>
 __device__ __forceinline__ cx<T> dot(const wf<T>& a, const wf<T>& b) {
@@ -127,10 +132,13 @@ __device__ __forceinline__ void chi2(vec<T> p, T pp, int lam, cx<T>& a, cx<T>& b
 
 // Massless Weyl factor sqrt(2E) chi_lam in the sqrt(E+pz) form (exact zeros in
 // the opposite chirality):  lam = +1: (sqrt(E+pz), (px + i py)/sqrt(E+pz)),
-// lam = -1: ((-px + i py)/sqrt(E+pz), sqrt(E+pz)).
+// lam = -1: ((-px + i py)/sqrt(E+pz), sqrt(E+pz)).  E is taken as |p| of the
+// three-momentum, so that a momentum that is massless only up to rounding
+// still defines an exactly massless state.
 template <class T>
 __device__ __forceinline__ void weyl0(vec<T> p, int lam, cx<T>& a, cx<T>& b) {
-  const T s = p.e + p.z;
+  const T pp = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  const T s = pp + p.z;
   if (s > T(0)) {
     const T r = sqrt(s), ir = T(1) / r;
     if (lam > 0) {
@@ -141,7 +149,7 @@ __device__ __forceinline__ void weyl0(vec<T> p, int lam, cx<T>& a, cx<T>& b) {
       b = mk<T>(r, T(0));
     }
   } else {
-    const T r = sqrt(T(2) * p.e);
+    const T r = sqrt(T(2) * pp);
     if (lam > 0) {
       a = mk<T>(T(0), T(0));
       b = mk<T>(r, T(0));
@@ -193,6 +201,53 @@ __device__ __forceinline__ wf<T> ixxxxx(vec<T> p, T m, int lam, int nsf) {
     const T wp = sqrt(E + l * pp), wm = sqrt(E - l * pp);
     f.c[0] = (-l * wp) * a; f.c[1] = (-l * wp) * b; f.c[2] = (l * wm) * a; f.c[3] = (l * wm) * b;
   }
+  return f;
+}
+
+// Helicity-independent part of a massless external fermion: sqrt(2E) chi_+ and
+// sqrt(2E) chi_- formed once per event in FP64 (the sqrt(E+pz) form loses
+// precision in FP32 for momenta near -z), stored in the arithmetic type T.
+template <class T>
+struct MLF {
+  cx<T> ap, bp, am, bm;
+};
+template <class T>
+__device__ __forceinline__ MLF<T> mlf_pre(mom p) {
+  const vec<double> q = {p.e, p.x, p.y, p.z};
+  cx<double> ap, bp, am, bm;
+  weyl0(q, +1, ap, bp);
+  weyl0(q, -1, am, bm);
+  return {cvt<T>(ap), cvt<T>(bp), cvt<T>(am), cvt<T>(bm)};
+}
+// |fi> of a massless fermion from its precomputed Weyl factors (same
+// conventions as ixxxxx<T, true>)
+template <class T>
+__device__ __forceinline__ wf<T> ixxxxx0(const MLF<T>& e, int lam, int nsf) {
+  const cx<T> z = mk<T>(T(0), T(0));
+  wf<T> f;
+  if (nsf > 0) {
+    if (lam > 0) {
+      f.c[0] = z; f.c[1] = z; f.c[2] = e.ap; f.c[3] = e.bp;
+    } else {
+      f.c[0] = e.am; f.c[1] = e.bm; f.c[2] = z; f.c[3] = z;
+    }
+  } else {
+    if (lam > 0) {
+      f.c[0] = -e.am; f.c[1] = -e.bm; f.c[2] = z; f.c[3] = z;
+    } else {
+      f.c[0] = z; f.c[1] = z; f.c[2] = -e.ap; f.c[3] = -e.bp;
+    }
+  }
+  return f;
+}
+template <class T>
+__device__ __forceinline__ wf<T> oxxxxx0(const MLF<T>& e, int lam, int nsf) {
+  const wf<T> s = ixxxxx0(e, lam, nsf);
+  wf<T> f;
+  f.c[0] = conj(s.c[2]);
+  f.c[1] = conj(s.c[3]);
+  f.c[2] = conj(s.c[0]);
+  f.c[3] = conj(s.c[1]);
   return f;
 }
 
