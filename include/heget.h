@@ -57,6 +57,7 @@ enum {
   HEGET_OP_VVS, HEGET_OP_JVS, HEGET_OP_HVV,                     /* VVS */
   HEGET_OP_VVSS, HEGET_OP_JVSS, HEGET_OP_HVVS,                  /* VVSS */
   HEGET_OP_SSS, HEGET_OP_HSS, HEGET_OP_SSSS, HEGET_OP_HSSS,     /* SSS, SSSS */
+  HEGET_OP_VADD, HEGET_OP_VSUB,  /* in0 +- in1 for two currents of one momentum (coupling -1) */
   HEGET_N_OPS
 };
 
@@ -139,6 +140,12 @@ typedef struct {
   int32_t symmetry;                   /* identical-particle factor S */
   int32_t cut_enabled;                /* every final leg pT > cut_pt and every pair Delta R > cut_dr */
   double cut_pt, cut_dr;
+  /* Ordering table (colour-ordered processes), or n_orderings = 0.  When set,
+   * the calls form a template over leg positions: for ordering o, input slot k
+   * < n_legs is external leg orderings[o][k], and flow o is the template's
+   * amplitude combination (every jamp row identical).  n_flows = n_orderings. */
+  int32_t n_orderings;
+  const int8_t* orderings;            /* [n_orderings][n_legs] permutations of 0..n_legs-1 */
 } heget_process_ir;
 
 typedef struct heget_process* heget_process_t;

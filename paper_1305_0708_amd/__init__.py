@@ -51,10 +51,14 @@ class _IRBuffers:
         flat = [int(h) for row in hels for h in row]
         self.hel = (ctypes.c_int8 * len(flat))(*flat)
         self.sm = L.heget_sm(**sm)
+        orders = proc.orderings or []
+        flat_o = [int(x) for o in orders for x in o]
+        self.orders = (ctypes.c_int8 * max(len(flat_o), 1))(*flat_o)
         self.ir = L.heget_process_ir(
             proc.n_legs, self.legs, self.sm, len(proc.couplings), self.cpl, len(calls), self.calls,
             proc.n_amps, proc.n_flows, self.jamp, self.colour, float(den), len(hels), self.hel,
-            proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr)
+            proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr,
+            len(orders), self.orders if orders else None)
 
 
 class Process:

@@ -1,26 +1,31 @@
-"""Process IR -> straight-line HIP kernel for gfx950.
+"""Process IR -> HIP kernel for gfx950.
 
 The generated kernel evaluates one event per lane (the paper's one
 phase-space point per thread, Sec. 3): momenta (loaded, or Philox + RAMBO),
-the generation cut, then the helicity loop with the call list unrolled as
-straight-line code, the jamps and the colour quadratic form (Sec. 5.4).
+the generation cut, then the helicity loop over the IR's calls, the jamps and
+the colour quadratic form (Sec. 5.4).
 
-Choices made here rather than in the paper's generated CUDA:
- * momenta, internal-line momenta and every propagator denominator depend on
-   the event but not on the helicity, so they are formed once per event in FP64
-   before the helicity loop (in both precisions);
- * temporaries are plain SSA values, so the compiler's register allocator does
-   the recycling of temporary wavefunctions the paper did by hand (Sec. 5.5);
- * colour factors and the colour matrix are compile-time constants.
+Two forms:
+ * straight-line: every call of the IR unrolled once per helicity; the
+   momenta of internal lines and every propagator denominator are event
+   properties, formed once in FP64 before the helicity loop;
+ * ordering template (colour-ordered processes): the calls are a template over
+   leg positions, run once per ordering inside a non-unrolled loop with the
+   positions bound to the permuted external wavefunctions; each ordering's
+   jamp is staged in LDS and the colour form reads them back.  This bounds the
+   code size and the live currents to those of one ordering, where the paper
+   split long amplitude programs into successive calls (Sec. 5.3).
 
-Usage:  python -m paper_1305_0708_amd.codegen <out_dir>   (writes one .hip per process)
+Temporaries are SSA values, so the compiler's register allocator recycles
+them (the paper did this by hand, Sec. 5.5).  Colour factors and the colour
+matrix are compile-time constants.
 """
 import os
 import sys
 from fractions import Fraction
 
 from . import ir
-from .ir import F, V, S, AMP_OPS, P_ZERO, P_W, P_Z, P_TOP, P_H
+from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
 
@@ -30,7 +35,6 @@ def _c(x):
 
 
 def _coef_expr(c, a):
-    """coefficient * amplitude with the trivial cases spelled out"""
     c = complex(c)
     if c == 1:
         return a
@@ -45,37 +49,43 @@ def _coef_expr(c, a):
     return f"(mk<T>(T({_c(c.real)}), T({_c(c.imag)})) * {a})"
 
 
+def _flowing_in(leg):
+    return (leg.incoming and leg.flow > 0) or ((not leg.incoming) and leg.flow < 0)
+
+
 class Gen:
     def __init__(self, proc: ir.Process):
         self.p = proc
         self.nl = proc.n_legs
         self.nout = proc.n_legs - 2
-        self.kind = {i: leg.kind for i, leg in enumerate(proc.legs)}
-        self.prop = {}
+        self.ordered = proc.orderings is not None
+        # a linear combination carries the momentum of its first input
+        self.mslot = {}
         for c in proc.calls:
-            if c.op not in AMP_OPS:
-                self.kind[c.out] = ir.OUT_KIND[c.op]
-                self.prop[c.out] = c.prop
-        # momentum of each slot as a set of external legs (q = sum over legs of q_leg)
-        self.legs_of = {i: (i,) for i in range(self.nl)}
+            if c.op in LINEAR_OPS:
+                self.mslot[c.out] = self.mslot.get(c.ins[0], c.ins[0])
+        # external legs (or positions) whose momenta a slot carries
+        self.subset = {k: (k,) for k in range(self.nl)}
         for c in proc.calls:
-            if c.op not in AMP_OPS:
-                s = []
-                for x in c.ins:
-                    s.extend(self.legs_of[x])
-                self.legs_of[c.out] = tuple(sorted(s))
-        # slots whose vec<T> momentum is needed inside the helicity loop
-        self.need_q = set()
+            if c.op in LINEAR_OPS:
+                self.subset[c.out] = self.subset[c.ins[0]]
+            elif c.op not in AMP_OPS:
+                self.subset[c.out] = tuple(sorted(x for i in c.ins for x in self.subset[i]))
+        self.need_q = set()    # subsets whose vec<T> momentum the calls use
         for c in proc.calls:
             if c.op in ("fvi", "fvo", "fsi", "fso", "jio", "jvv", "jggg", "jwww", "jvs", "jvss"):
-                self.need_q.add(c.out)
+                self.need_q.add(self.subset[c.out])
             if c.op in ("vvv", "jvv"):
-                self.need_q.update(c.ins)
+                self.need_q.update(self.subset[x] for x in c.ins)
 
-    # ------------------------------------------------------------ emission
-    def name(self):
-        return self.p.name
+    def m(self, s):
+        return self.mslot.get(s, s)
 
+    @staticmethod
+    def sname(sub):
+        return "_".join(str(x) for x in sub)
+
+    # ---------------------------------------------------------------- common
     def emit(self):
         p = self.p
         L = []
@@ -94,7 +104,7 @@ class Gen:
         w(f"  mom p[{self.nl}];")
         w("  if (active) {")
         w("    if (a.mom_in) {")
-        w(f"#pragma unroll")
+        w("#pragma unroll")
         w(f"      for (int k = 0; k < {self.nl}; ++k) {{")
         w("        const double* b = a.mom_in + int64_t(k) * 4 * a.mom_stride + i;")
         w("        p[k] = {b[0], b[a.mom_stride], b[2 * a.mom_stride], b[3 * a.mom_stride]};")
@@ -107,91 +117,192 @@ class Gen:
         w("    }")
         w("    if (a.mom_out) store_momenta<%d>(a, i, p);" % self.nl)
         w("  } else {")
-        w(f"#pragma unroll")
+        w("#pragma unroll")
         w(f"    for (int k = 0; k < {self.nl}; ++k) p[k] = {{1.0, 0.0, 0.0, 1.0}};")
         w("  }")
         if p.cut_enabled:
             w(f"  const bool pass = active && (!a.cut_enabled || pass_pt_dr<{self.nout}>(p + 2, a.cut_pt, a.cut_dr));")
         else:
             w("  const bool pass = active;")
-        # couplings (uniform values, loaded once)
-        w("  // couplings (uniform)")
+        w("  // couplings and propagator data (uniform)")
         for k, c in enumerate(p.couplings):
             w(f"  const cx<T> g{k}_0 = mk<T>(T(a.cpl[{4 * k}]), T(a.cpl[{4 * k + 1}]));")
             w(f"  const cx<T> g{k}_1 = mk<T>(T(a.cpl[{4 * k + 2}]), T(a.cpl[{4 * k + 3}]));")
-        used_parts = sorted({pp for pp in self.prop.values()} | {leg.particle for leg in p.legs})
-        for pid in used_parts:
+        used = sorted({c.prop for c in p.calls} | {leg.particle for leg in p.legs} | {P_ZERO})
+        for pid in used:
             w(f"  const PropEntry pe{pid} = a.prop[{pid}];")
-        # momenta flowing into the diagram: q = p (incoming) or -p (outgoing)
-        w("  // incoming-flow momenta of every slot (FP64) and inverse denominators")
+        w("  // momenta flowing into the diagram: +p incoming, -p outgoing (FP64)")
         for k, leg in enumerate(p.legs):
             w(f"  const mom q{k} = {'p[%d]' % k if leg.incoming else '-p[%d]' % k};")
-        for c in p.calls:
-            if c.op in AMP_OPS:
-                continue
-            s = c.out
-            terms = " + ".join(f"q{x}" for x in c.ins)
-            w(f"  const mom q{s} = {terms};")
-            pid = c.prop
-            w(f"  const cx<T> d{s} = cvt<T>(inv_denominator(q{s}, cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
-        for s in sorted(self.need_q):
-            w(f"  const vec<T> Q{s} = tv<T>(q{s});")
-        for k, leg in enumerate(p.legs):
-            if leg.kind == F and leg.particle == P_ZERO:
-                # helicity-independent Weyl factors, formed in FP64
-                w(f"  const MLF<T> e{k} = mlf_pre<T>(p[{k}]);")
-            elif leg.kind == F:
-                # massive external fermion: both helicity states in FP64
-                fn = "ixxxxx" if self._flowing_in(leg) else "oxxxxx"
-                for lam, tag in ((-1, "m"), (1, "p")):
-                    w(f"  const wf<T> e{k}{tag} = cvtw<T>({fn}<double, false>(tv<double>(p[{k}]), "
-                      f"pe{leg.particle}.m, {lam}, {leg.flow}));")
-            elif leg.kind == V:
-                w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
-        w("  double me2 = 0.0;")
-        w("  if (pass) {")
-        w("    for (int h = 0; h < a.n_hel; ++h) {")
-        w(f"      const int8_t* hh = a.hel + h * {self.nl};")
-        for k, leg in enumerate(p.legs):
-            self._external(w, k, leg)
-        for c in p.calls:
-            self._call(w, c)
-        self._colour(w)
-        w("    }")
-        w("  }")
+        if self.ordered:
+            self._emit_ordered(w)
+        else:
+            self._emit_straight(w)
         w("  if (a.me2_out && active) a.me2_out[i] = me2;")
         w("  if (a.partials) block_partials(a, pass ? me2 * a.weight_factor : 0.0, pass);")
         w("}")
         w("")
         w("}  // namespace")
         w("")
-        cfg = (f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
-               f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
-               f'reinterpret_cast<const void*>(&amp_{p.name}<float>)}};')
-        w(cfg)
+        w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
+          f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
+          f'reinterpret_cast<const void*>(&amp_{p.name}<float>)}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
         return "\n".join(L) + "\n"
 
-    @staticmethod
-    def _flowing_in(leg):
-        return (leg.incoming and leg.flow > 0) or ((not leg.incoming) and leg.flow < 0)
+    def _ext_pre(self, w):
+        """helicity-independent pieces of the external wavefunctions"""
+        for k, leg in enumerate(self.p.legs):
+            if leg.kind == F and leg.particle == P_ZERO:
+                w(f"  const MLF<T> e{k} = mlf_pre<T>(p[{k}]);")
+            elif leg.kind == F:
+                fn = "ixxxxx" if _flowing_in(leg) else "oxxxxx"
+                for lam, tag in ((-1, "m"), (1, "p")):
+                    w(f"  const wf<T> e{k}{tag} = cvtw<T>({fn}<double, false>(tv<double>(p[{k}]), "
+                      f"pe{leg.particle}.m, {lam}, {leg.flow}));")
+            elif leg.kind == V:
+                w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
 
-    def _external(self, w, k, leg):
+    def _external(self, k, leg, name):
         if leg.kind == F:
             if leg.particle == P_ZERO:
-                fn = "ixxxxx0" if self._flowing_in(leg) else "oxxxxx0"
-                w(f"      const wf<T> w{k} = {fn}<T>(e{k}, hh[{k}], {leg.flow});")
-            else:
-                w(f"      const wf<T> w{k} = hh[{k}] > 0 ? e{k}p : e{k}m;")
-        elif leg.kind == V:
+                fn = "ixxxxx0" if _flowing_in(leg) else "oxxxxx0"
+                return f"const wf<T> {name} = {fn}<T>(e{k}, hh[{k}], {leg.flow});"
+            return f"const wf<T> {name} = hh[{k}] > 0 ? e{k}p : e{k}m;"
+        if leg.kind == V:
             nsv = -1 if leg.incoming else 1
-            w(f"      const wf<T> w{k} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), hh[{k}], {nsv});")
-        else:
-            w(f"      const cx<T> w{k} = sxxxxx<T>();")
+            return f"const wf<T> {name} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), hh[{k}], {nsv});"
+        return f"const cx<T> {name} = sxxxxx<T>();"
 
-    def _call(self, w, c):
+    def _current_momenta(self, w, ind, qname):
+        """FP64 momentum of every leg subset an internal line carries (summed in
+        leg order, once per subset) and its inverse denominator per propagator"""
+        done_q, done_d = set(), set()
+        for c in self.p.calls:
+            if c.op in AMP_OPS or c.op in LINEAR_OPS:
+                continue
+            sub = self.subset[c.out]
+            n = self.sname(sub)
+            if sub not in done_q:
+                done_q.add(sub)
+                w(f"{ind}const mom qs{n} = {' + '.join(qname(x) for x in sub)};")
+                if sub in self.need_q:
+                    w(f"{ind}const vec<T> Qs{n} = tv<T>(qs{n});")
+            if (sub, c.prop) not in done_d:
+                done_d.add((sub, c.prop))
+                pid = c.prop
+                w(f"{ind}const cx<T> d{n}_{pid} = cvt<T>(inv_denominator(qs{n}, cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
+
+    # ---------------------------------------------------------- straight-line
+    def _emit_straight(self, w):
+        p = self.p
+        for k in range(self.nl):
+            if (k,) in self.need_q:
+                w(f"  const vec<T> Qs{k} = tv<T>(q{k});")
+        self._current_momenta(w, "  ", lambda x: f"q{x}")
+        self._ext_pre(w)
+        w("  double me2 = 0.0;")
+        w("  if (pass) {")
+        w("    for (int h = 0; h < a.n_hel; ++h) {")
+        w(f"      const int8_t* hh = a.hel + h * {self.nl};")
+        for k, leg in enumerate(p.legs):
+            w("      " + self._external(k, leg, f"w{k}"))
+        for c in p.calls:
+            self._call(w, c, "      ")
+        for f, terms in enumerate(p.jamp):
+            expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in terms) or "mk<T>(T(0), T(0))"
+            w(f"      const cx<T> J{f} = {expr};")
+        self._colour(w, lambda f: f"J{f}")
+        w("    }")
+        w("  }")
+
+    # ------------------------------------------------------ ordering template
+    def _emit_ordered(self, w):
+        p = self.p
+        nl, no = self.nl, len(p.orderings)
+        if any(leg.kind == F for leg in p.legs):
+            raise NotImplementedError("ordering templates support vector and scalar legs")
+        w(f"  __shared__ cx<T> jl[{no}][256];")
+        w("  double me2 = 0.0;")
+        w("  if (pass) {")
+        w("    for (int h = 0; h < a.n_hel; ++h) {")
+        w(f"      const int8_t* hh = a.hel + h * {nl};")
+        w("#pragma unroll 1")
+        w(f"      for (int o = 0; o < {no}; ++o) {{")
+        w(f"        const int8_t* ord = a.ord + o * {nl};")
+        # bind each position to its external leg: momentum, helicity, wavefunction
+        for k in range(nl):
+            cand = sorted({o[k] for o in p.orderings})
+            L0 = cand[0]
+            if len(cand) == 1:
+                w(f"        const mom pp{k} = p[{L0}];")
+                w(f"        const mom qp{k} = {'pp%d' % k if p.legs[L0].incoming else '-pp%d' % k};")
+                w(f"        const int hp{k} = hh[{L0}];")
+            else:
+                w(f"        mom pp{k} = p[{L0}];")
+                w(f"        double sg{k} = {'1.0' if p.legs[L0].incoming else '-1.0'};")
+                w(f"        switch (ord[{k}]) {{")
+                for L in cand[1:]:
+                    w(f"          case {L}: pp{k} = p[{L}]; sg{k} = {'1.0' if p.legs[L].incoming else '-1.0'}; break;")
+                w("          default: break;")
+                w("        }")
+                w(f"        const mom qp{k} = {{sg{k} * pp{k}.e, sg{k} * pp{k}.x, sg{k} * pp{k}.y, sg{k} * pp{k}.z}};")
+                w(f"        const int hp{k} = hh[ord[{k}]];")
+            legs = [p.legs[L] for L in cand]
+            kinds = {l.kind for l in legs}
+            parts = {l.particle for l in legs}
+            assert len(kinds) == 1 and len(parts) == 1, "a position must hold one kind of particle"
+            leg = legs[0]
+            if leg.kind == V:
+                inc = {l.incoming for l in legs}
+                if len(inc) == 1:
+                    nsv = "-1" if leg.incoming else "1"
+                else:
+                    w(f"        int nsv{k} = 1;")
+                    w(f"        switch (ord[{k}]) {{")
+                    for L in cand:
+                        if p.legs[L].incoming:
+                            w(f"          case {L}: nsv{k} = -1; break;")
+                    w("          default: break;")
+                    w("        }")
+                    nsv = f"nsv{k}"
+                w(f"        const wf<T> w{k} = vxxxxx<T>(tv<T>(pp{k}), T(pe{leg.particle}.m), hp{k}, {nsv});")
+            else:
+                w(f"        const cx<T> w{k} = sxxxxx<T>();")
+            if (k,) in self.need_q:
+                w(f"        const vec<T> Qs{k} = tv<T>(qp{k});")
+        # each subset momentum and denominator right before its first use
+        done_q, done_d = set(), set()
+        for c in p.calls:
+            subs = [self.subset[x] for x in c.ins if x >= nl]
+            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+                subs.append(self.subset[c.out])
+            for sub in subs:
+                n = self.sname(sub)
+                if sub not in done_q:
+                    done_q.add(sub)
+                    w(f"        const mom qs{n} = {' + '.join(f'qp{x}' for x in sub)};")
+                    if sub in self.need_q:
+                        w(f"        const vec<T> Qs{n} = tv<T>(qs{n});")
+            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+                sub, pid = self.subset[c.out], c.prop
+                n = self.sname(sub)
+                if (sub, pid) not in done_d:
+                    done_d.add((sub, pid))
+                    w(f"        const cx<T> d{n}_{pid} = cvt<T>(inv_denominator(qs{n}, "
+                      f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
+            self._call(w, c, "        ")
+        expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in p.jamp[0])
+        w(f"        jl[o][threadIdx.x] = {expr};")
+        w("      }")
+        self._colour(w, lambda f: f"jl[{f}][threadIdx.x]")
+        w("    }")
+        w("  }")
+
+    # ------------------------------------------------------------------ calls
+    def _call(self, w, c, ind):
         op, ins, o = c.op, c.ins, c.out
         g0, g1 = f"g{c.cpl}_0", f"g{c.cpl}_1"
         gr = f"g{c.cpl}_0.r"
@@ -200,53 +311,52 @@ class Gen:
         inum = f"mk<T>(T(pe{pid}.inum_r), T(pe{pid}.inum_i))"
         massive = "true" if pid in MASSIVE_VECTORS else "false"
         a = [f"w{x}" for x in ins]
+        Q = lambda x: f"Qs{self.sname(self.subset[x])}"
         if op in AMP_OPS:
-            lhs = f"      const cx<T> amp{o} = "
+            lhs = f"{ind}const cx<T> amp{o} = "
         elif ir.OUT_KIND[op] == S:
-            lhs = f"      const cx<T> w{o} = "
+            lhs = f"{ind}const cx<T> w{o} = "
         else:
-            lhs = f"      const wf<T> w{o} = "
-        d = f"d{o}"
+            lhs = f"{ind}const wf<T> w{o} = "
+        d = f"d{self.sname(self.subset[o])}_{pid}" if op not in AMP_OPS and op not in LINEAR_OPS else ""
         if op == "iov":
             rhs = f"iovxxx<T>({a[0]}, {a[1]}, {a[2]}, {g0}, {g1})"
         elif op == "fvi":
-            rhs = f"fvixxx<T>({a[0]}, {a[1]}, {g0}, {g1}, Q{o}, {mass}, {d})"
+            rhs = f"fvixxx<T>({a[0]}, {a[1]}, {g0}, {g1}, {Q(o)}, {mass}, {d})"
         elif op == "fvo":
-            rhs = f"fvoxxx<T>({a[0]}, {a[1]}, {g0}, {g1}, Q{o}, {mass}, {d})"
+            rhs = f"fvoxxx<T>({a[0]}, {a[1]}, {g0}, {g1}, {Q(o)}, {mass}, {d})"
         elif op == "jio":
-            rhs = f"jioxxx<T, {massive}>({a[0]}, {a[1]}, {g0}, {g1}, Q{o}, {inum}, {d})"
+            rhs = f"jioxxx<T, {massive}>({a[0]}, {a[1]}, {g0}, {g1}, {Q(o)}, {inum}, {d})"
         elif op == "ios":
             rhs = f"iosxxx<T>({a[0]}, {a[1]}, {a[2]}, {g0}, {g1})"
         elif op == "fsi":
-            rhs = f"fsixxx<T>({a[0]}, {a[1]}, {g0}, {g1}, Q{o}, {mass}, {d})"
+            rhs = f"fsixxx<T>({a[0]}, {a[1]}, {g0}, {g1}, {Q(o)}, {mass}, {d})"
         elif op == "fso":
-            rhs = f"fsoxxx<T>({a[0]}, {a[1]}, {g0}, {g1}, Q{o}, {mass}, {d})"
+            rhs = f"fsoxxx<T>({a[0]}, {a[1]}, {g0}, {g1}, {Q(o)}, {mass}, {d})"
         elif op == "hio":
             rhs = f"hioxxx<T>({a[0]}, {a[1]}, {g0}, {g1}, {d})"
         elif op == "vvv":
-            q = [f"Q{x}" for x in ins]
-            rhs = f"vvvxxx<T>({a[0]}, {q[0]}, {a[1]}, {q[1]}, {a[2]}, {q[2]}, {gr})"
+            rhs = f"vvvxxx<T>({a[0]}, {Q(ins[0])}, {a[1]}, {Q(ins[1])}, {a[2]}, {Q(ins[2])}, {gr})"
         elif op == "jvv":
-            q = [f"Q{x}" for x in ins]
-            rhs = f"jvvxxx<T, {massive}>({a[0]}, {q[0]}, {a[1]}, {q[1]}, {gr}, {inum}, {d})"
+            rhs = f"jvvxxx<T, {massive}>({a[0]}, {Q(ins[0])}, {a[1]}, {Q(ins[1])}, {gr}, {inum}, {d})"
         elif op == "gggg":
             rhs = f"ggggxx<T>({a[0]}, {a[1]}, {a[2]}, {a[3]}, {gr})"
         elif op == "jggg":
-            rhs = f"jgggxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {gr}, Q{o}, {inum}, {d})"
+            rhs = f"jgggxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {gr}, {Q(o)}, {inum}, {d})"
         elif op == "wwww":
             rhs = f"wwwwxx<T>({a[0]}, {a[1]}, {a[2]}, {a[3]}, {gr})"
         elif op == "jwww":
-            rhs = f"jwwwxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {gr}, Q{o}, {inum}, {d})"
+            rhs = f"jwwwxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {gr}, {Q(o)}, {inum}, {d})"
         elif op == "vvs":
             rhs = f"vvsxxx<T>({a[0]}, {a[1]}, {a[2]}, {g0})"
         elif op == "jvs":
-            rhs = f"jvsxxx<T, {massive}>({a[0]}, {a[1]}, {g0}, Q{o}, {inum}, {d})"
+            rhs = f"jvsxxx<T, {massive}>({a[0]}, {a[1]}, {g0}, {Q(o)}, {inum}, {d})"
         elif op == "hvv":
             rhs = f"hvvxxx<T>({a[0]}, {a[1]}, {g0}, {d})"
         elif op == "vvss":
             rhs = f"vvssxx<T>({a[0]}, {a[1]}, {a[2]}, {a[3]}, {g0})"
         elif op == "jvss":
-            rhs = f"jvssxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {g0}, Q{o}, {inum}, {d})"
+            rhs = f"jvssxx<T, {massive}>({a[0]}, {a[1]}, {a[2]}, {g0}, {Q(o)}, {inum}, {d})"
         elif op == "hvvs":
             rhs = f"hvvsxx<T>({a[0]}, {a[1]}, {a[2]}, {g0}, {d})"
         elif op == "sss":
@@ -257,32 +367,35 @@ class Gen:
             rhs = f"ssssxx<T>({a[0]}, {a[1]}, {a[2]}, {a[3]}, {g0})"
         elif op == "hsss":
             rhs = f"hsssxx<T>({a[0]}, {a[1]}, {a[2]}, {g0}, {d})"
+        elif op == "vadd":
+            rhs = f"vadd<T>({a[0]}, {a[1]})"
+        elif op == "vsub":
+            rhs = f"vsub<T>({a[0]}, {a[1]})"
         else:
             raise ValueError(op)
         w(lhs + rhs + ";")
 
-    def _colour(self, w):
+    def _colour(self, w, J):
+        """me2 += Re(J^dagger C J) with the constant colour matrix C = num / den"""
         p = self.p
-        for f, terms in enumerate(p.jamp):
-            expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in terms) or "mk<T>(T(0), T(0))"
-            w(f"      const cx<T> J{f} = {expr};")
         den = p.colour_denominator()
-        parts = []
         n = p.n_flows
+        w("      T cs = T(0);")
         for f in range(n):
-            cff = Fraction(p.colour[f][f]) * den
-            parts.append(f"T({_c(cff)}) * norm2(J{f})")
+            w(f"      {{")
+            w(f"        const cx<T> jf = {J(f)};")
+            w(f"        T r = T({_c(Fraction(p.colour[f][f]) * den)}) * norm2(jf);")
             for g in range(f + 1, n):
                 cfg = Fraction(p.colour[f][g]) * den
                 if cfg != 0:
-                    parts.append(f"T({_c(2 * cfg)}) * (J{f}.r * J{g}.r + J{f}.i * J{g}.i)")
-        w(f"      const T cs = {' + '.join(parts)};")
+                    w(f"        {{ const cx<T> jg = {J(g)}; r += T({_c(2 * cfg)}) * (jf.r * jg.r + jf.i * jg.i); }}")
+            w("        cs += r;")
+            w("      }")
         w(f"      me2 += double(cs) * {_c(Fraction(1, den))};")
 
 
 def generate(proc, out_dir):
-    g = Gen(proc)
-    src = g.emit()
+    src = Gen(proc).emit()
     path = os.path.join(out_dir, f"gen_{proc.name}.hip")
     old = open(path).read() if os.path.exists(path) else None
     if old != src:
@@ -295,7 +408,7 @@ def main(argv):
     from . import processes
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(__file__), "csrc", "gen")
     os.makedirs(out, exist_ok=True)
-    for name in ("ee_mumu", "gg_ttbar_6f", "ud_udhh_4b"):
+    for name in ("ee_mumu", "gg_ttbar_6f", "ud_udhh_4b", "gg_4g"):
         print(generate(processes.by_name(name), out))
 
 

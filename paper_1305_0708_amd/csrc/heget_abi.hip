@@ -94,6 +94,8 @@ uint64_t fingerprint(const heget_process_ir* ir) {
   for (int k = 0; k < ir->n_flows * ir->n_flows; ++k) H.f64(ir->colour_num[k]);
   H.f64(ir->colour_den);
   H.i32(ir->cut_enabled);
+  H.i32(ir->n_orderings);
+  for (int k = 0; k < ir->n_orderings * ir->n_legs; ++k) H.i32(ir->orderings[k]);
   return H.h;
 }
 
@@ -110,6 +112,7 @@ const OpSig kSig[HEGET_N_OPS] = {
     {"VVS", 'A'}, {"VS", 'V'}, {"VV", 'S'},                  // vvs jvs hvv
     {"VVSS", 'A'}, {"VSS", 'V'}, {"VVS", 'S'},               // vvss jvss hvvs
     {"SSS", 'A'}, {"SS", 'S'}, {"SSSS", 'A'}, {"SSS", 'S'},  // sss hss ssss hsss
+    {"VV", 'V'}, {"VV", 'V'},                                // vadd vsub
 };
 
 heget_status validate(const heget_process_ir* ir) {
@@ -148,7 +151,9 @@ heget_status validate(const heget_process_ir* ir) {
         return fail(HEGET_E_IR, at + "unused inputs must be -1");
       }
     }
-    if (c.coupling < 0 || c.coupling >= ir->n_couplings) return fail(HEGET_E_IR, at + "bad coupling index");
+    const bool linear = c.op == HEGET_OP_VADD || c.op == HEGET_OP_VSUB;
+    if (linear ? c.coupling != -1 : (c.coupling < 0 || c.coupling >= ir->n_couplings))
+      return fail(HEGET_E_IR, at + "bad coupling index");
     if (c.prop < 0 || c.prop >= HEGET_N_PARTICLES) return fail(HEGET_E_IR, at + "bad propagator particle");
     if (sg.out == 'A') {
       if (c.out < 0 || c.out >= ir->n_amps || amp_seen[c.out]) return fail(HEGET_E_IR, at + "bad amplitude index");
@@ -173,6 +178,16 @@ heget_status validate(const heget_process_ir* ir) {
     if (!(v == -1 || v == 0 || v == 1 || v == 4)) return fail(HEGET_E_IR, "helicity values must be -1, 0, 1 or 4");
   }
   if (ir->n_a_n_b < 1 || ir->symmetry < 1) return fail(HEGET_E_IR, "averaging factors must be >= 1");
+  if (ir->n_orderings < 0 || (ir->n_orderings > 0 && (!ir->orderings || ir->n_orderings != ir->n_flows)))
+    return fail(HEGET_E_IR, "ordering table must have one row per flow");
+  for (int o = 0; o < ir->n_orderings; ++o) {
+    std::vector<char> seen(ir->n_legs, 0);
+    for (int k = 0; k < ir->n_legs; ++k) {
+      const int x = ir->orderings[o * ir->n_legs + k];
+      if (x < 0 || x >= ir->n_legs || seen[x]) return fail(HEGET_E_IR, "orderings must be permutations of the legs");
+      seen[x] = 1;
+    }
+  }
   return HEGET_OK;
 }
 
@@ -315,6 +330,7 @@ struct heget_process {
   double* d_cpl = nullptr;
   PropEntry* d_prop = nullptr;
   int8_t* d_hel = nullptr;
+  int8_t* d_ord = nullptr;   // ordering table (colour-ordered processes)
   double* d_part = nullptr;  // integrate partials, grown on demand and reused
   int64_t part_cap = 0;
   std::vector<int8_t> hel;  // host copy of the current table
@@ -343,6 +359,7 @@ KernelArgs base_args(heget_process_t p) {
   a.prop = p->d_prop;
   a.cut_pt = p->cut_pt;
   a.cut_dr = p->cut_dr;
+  a.ord = p->d_ord;
   return a;
 }
 
@@ -352,6 +369,7 @@ void release(heget_process* p) {
   if (p->d_prop) (void)hipFree(p->d_prop);
   if (p->d_hel) (void)hipFree(p->d_hel);
   if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_ord) (void)hipFree(p->d_ord);
   delete p;
 }
 
@@ -402,6 +420,17 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
       hipMemcpy(p->d_hel, p->hel.data(), p->hel.size(), hipMemcpyHostToDevice) != hipSuccess) {
     release(p);
     return fail(HEGET_E_HIP, "upload of process tables failed");
+  }
+  if (ir->n_orderings > 0) {
+    const size_t nb = size_t(ir->n_orderings) * ir->n_legs;
+    if (hipMalloc(&p->d_ord, nb) != hipSuccess) {
+      release(p);
+      return fail(HEGET_E_OOM, "device allocation of the ordering table failed");
+    }
+    if (hipMemcpy(p->d_ord, ir->orderings, nb, hipMemcpyHostToDevice) != hipSuccess) {
+      release(p);
+      return fail(HEGET_E_HIP, "upload of the ordering table failed");
+    }
   }
   *out = p;
   return HEGET_OK;

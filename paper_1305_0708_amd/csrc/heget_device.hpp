@@ -87,6 +87,15 @@ __device__ __forceinline__ wf<T> cvtw(const wf<S>& a) {
   return {{cvt<T>(a.c[0]), cvt<T>(a.c[1]), cvt<T>(a.c[2]), cvt<T>(a.c[3])}};
 }
 
+template <class T>
+__device__ __forceinline__ wf<T> vadd(const wf<T>& a, const wf<T>& b) {
+  return {{a.c[0] + b.c[0], a.c[1] + b.c[1], a.c[2] + b.c[2], a.c[3] + b.c[3]}};
+}
+template <class T>
+__device__ __forceinline__ wf<T> vsub(const wf<T>& a, const wf<T>& b) {
+  return {{a.c[0] - b.c[0], a.c[1] - b.c[1], a.c[2] - b.c[2], a.c[3] - b.c[3]}};
+}
+
 // Minkowski product of two complex vectors (no conjugation)
 template <class T>
 __device__ __forceinline__ cx<T> dot(const wf<T>& a, const wf<T>& b) {

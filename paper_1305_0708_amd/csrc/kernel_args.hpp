@@ -28,6 +28,7 @@ struct KernelArgs {
   double cut_pt, cut_dr;
   double weight_factor;      // phase-space weight x flux x averages x 1/S (integrate)
   double* partials;          // integrate: [gridDim.x][3] (sum w, sum w^2, accepted), or null
+  const int8_t* ord;         // ordering table [n_orderings][n_legs] of colour-ordered processes
 };
 
 }  // namespace heget

@@ -42,6 +42,8 @@ OP_FLOPS = {
     "hss": 3 * CMUL,                                            # 18
     "ssss": 4 * CMUL,                                           # 24
     "hsss": 4 * CMUL,                                           # 24
+    "vadd": 4 * CADD,                                           # 8
+    "vsub": 4 * CADD,                                           # 8
 }
 EXTERNAL = {"f_massless": 6, "f_massive": 30, "v": 24, "s": 0}
 MASSIVE = {P_W, P_Z}
@@ -65,8 +67,12 @@ def per_helicity(proc):
             n += EXTERNAL["f_massless"] if leg.particle == P_ZERO else EXTERNAL["f_massive"]
         elif leg.kind == V:
             n += EXTERNAL["v"]
-    n += sum(call_flops(c) for c in proc.calls)
-    n += sum(CADD * max(len(t) - 1, 0) for t in proc.jamp)          # jamp sums
+    reps = len(proc.orderings) if proc.orderings else 1             # ordering template
+    n += reps * sum(call_flops(c) for c in proc.calls)
+    if proc.orderings:
+        n += reps * CADD * max(len(proc.jamp[0]) - 1, 0)
+    else:
+        n += sum(CADD * max(len(t) - 1, 0) for t in proc.jamp)      # jamp sums
     nf = proc.n_flows
     n += nf * 4 + (nf * (nf - 1) // 2) * 4 + 2                      # colour quadratic form
     return n
@@ -75,5 +81,8 @@ def per_helicity(proc):
 def per_event(proc, n_hel=None):
     """flops of one event: helicity loop plus the per-event denominators"""
     nh = len(proc.helicities) if n_hel is None else n_hel
-    n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS)
+    n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS and c.op not in ("vadd", "vsub"))
+    if proc.orderings:
+        # per-ordering momenta and denominators are formed inside the helicity loop
+        return nh * (per_helicity(proc) + len(proc.orderings) * n_cur * (7 + 8))
     return nh * per_helicity(proc) + n_cur * (7 + 8)

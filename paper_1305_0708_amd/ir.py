@@ -31,12 +31,16 @@ OPS = [
     "vvs", "jvs", "hvv",                   # VVS
     "vvss", "jvss", "hvvs",                # VVSS
     "sss", "hss", "ssss", "hsss",          # SSS, SSSS
+    "vadd", "vsub",                        # sums of currents with one momentum
 ]
 OP = {name: i for i, name in enumerate(OPS)}
 AMP_OPS = {"iov", "ios", "vvv", "gggg", "wwww", "vvs", "vvss", "sss", "ssss"}
 # kind of the output wavefunction of each current op
 OUT_KIND = {"fvi": F, "fvo": F, "jio": V, "fsi": F, "fso": F, "hio": S, "jvv": V, "jggg": V,
-            "jwww": V, "jvs": V, "hvv": S, "jvss": V, "hvvs": S, "hss": S, "hsss": S}
+            "jwww": V, "jvs": V, "hvv": S, "jvss": V, "hvvs": S, "hss": S, "hsss": S,
+            "vadd": V, "vsub": V}
+# ops whose output carries the momentum of their first input (not the sum)
+LINEAR_OPS = {"vadd", "vsub"}
 # input kinds per op (in argument order)
 IN_KINDS = {
     "iov": (F, F, V), "fvi": (F, V), "fvo": (F, V), "jio": (F, F),
@@ -46,6 +50,7 @@ IN_KINDS = {
     "vvs": (V, V, S), "jvs": (V, S), "hvv": (V, V),
     "vvss": (V, V, S, S), "jvss": (V, S, S), "hvvs": (V, V, S),
     "sss": (S, S, S), "hss": (S, S), "ssss": (S, S, S, S), "hsss": (S, S, S),
+    "vadd": (V, V), "vsub": (V, V),
 }
 
 # coupling kinds (values are derived from the SM inputs by the library)
@@ -99,6 +104,11 @@ class Process:
     cut_dr: float = 0.0
     cut_enabled: bool = False
     sm_overrides: dict = field(default_factory=dict)
+    # Optional ordering table: when set, `calls` is a template over leg
+    # *positions* 0..n_legs-1, evaluated once per ordering with position k
+    # bound to external leg orderings[o][k]; flow o is the template's
+    # amplitude combination jamp[o] for that ordering (all rows equal).
+    orderings: Optional[List[Tuple[int, ...]]] = None
 
     @property
     def n_legs(self):
@@ -140,7 +150,10 @@ class Process:
                 if c.out in kinds:
                     raise ValueError(f"call {k}: slot {c.out} defined twice")
                 kinds[c.out] = OUT_KIND[c.op]
-            if not (0 <= c.cpl < len(self.couplings)):
+            if c.op in LINEAR_OPS:
+                if c.cpl != -1:
+                    raise ValueError(f"call {k}: {c.op} takes no coupling")
+            elif not (0 <= c.cpl < len(self.couplings)):
                 raise ValueError(f"call {k}: bad coupling index")
         if amps != set(range(self.n_amps)):
             raise ValueError("every amplitude index must be produced exactly once")
@@ -153,6 +166,15 @@ class Process:
         for h in self.helicities:
             if len(h) != self.n_legs:
                 raise ValueError("helicity row length != number of legs")
+        if self.orderings is not None:
+            if len(self.orderings) != self.n_flows:
+                raise ValueError("one flow per ordering")
+            for o in self.orderings:
+                if sorted(o) != list(range(self.n_legs)):
+                    raise ValueError("orderings must be permutations of the legs")
+            for row in self.jamp[1:]:
+                if row != self.jamp[0]:
+                    raise ValueError("ordering template: every jamp row is the same combination")
         return self
 
     # -------------------------------------------------------------- fingerprint
@@ -197,6 +219,11 @@ class Process:
                 f64(float(Fraction(x) * den))
         f64(float(den))
         i32(int(self.cut_enabled))
+        orders = self.orderings or []
+        i32(len(orders))
+        for o in orders:
+            for x in o:
+                i32(x)
         return bytes(b)
 
     def fingerprint(self):

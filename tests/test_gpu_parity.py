@@ -21,7 +21,9 @@ CASES = {
     "ee_mumu": ("EE_MUMU", 2, 200.0, {}, 0x48454745, 65536),
     "gg_ttbar_6f": ("GG_TT_6F", 6, 1000.0, {}, 0x48454746, 1 << 20),
     "ud_udhh_4b": ("UD_UDHH_4B", 6, 2000.0, {"cms": 1}, 0x48454748, 1 << 21),
+    "gg_4g": ("GG_4G", 4, 1000.0, {}, 0x48454747, 1 << 20),
 }
+CUT = {"gg_4g": (20.0, 0.4)}   # generation cut: events failing it have |M|^2 = 0
 
 
 @pytest.fixture(scope="module")
@@ -47,9 +49,12 @@ def make(name, precision="fp64"):
     return H.Process(processes.by_name(name), precision=precision)
 
 
-def oracle_me2(oracle, name, mom):
+def oracle_me2(oracle, name, mom, cut=True):
     pid, _, _, kw, _, _ = CASES[name]
-    return oracle.me2(getattr(oracle, pid), mom, oracle.params(**kw))
+    f = oracle.me2(getattr(oracle, pid), mom, oracle.params(**kw))
+    if cut and name in CUT:
+        f = f * oracle.cut_gluons(mom, *CUT[name])
+    return f
 
 
 def rel_err(a, b):
@@ -72,8 +77,8 @@ def rounding_floor(oracle, name, mom, ref):
     rotations, so the spread of F over rotated frames measures the rounding
     error an FP64 evaluation of this event carries."""
     nu = np.zeros(len(mom))
-    for s in range(3):
-        nu = np.maximum(nu, rel_err(oracle_me2(oracle, name, random_rotation(mom, s)), ref))
+    for s in range(8):
+        nu = np.maximum(nu, rel_err(oracle_me2(oracle, name, random_rotation(mom, s), cut=False), ref))
     return nu
 
 
@@ -81,6 +86,9 @@ def assert_fp64_parity(oracle, name, mom, got, ref):
     """|F_gpu/F_oracle - 1| <= 1e-12 per event; where the event's own FP64
     rounding floor nu exceeds that (strong gauge cancellations), the bound is
     16 nu.  Returns the fraction of events within 1e-12."""
+    zero = ref == 0            # events removed by the generation cut
+    assert np.all(got[zero] == 0.0)
+    got, ref, mom = got[~zero], ref[~zero], mom[~zero]
     err = rel_err(got, ref)
     bad = err > FP64_TOL
     if bad.any():
@@ -115,8 +123,9 @@ def test_fp64_parity_momenta_in(torch, oracle, name):
     ref = oracle_me2(oracle, name, mom)
     p = make(name)
     got = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-    err = rel_err(got, ref)
-    print(f"{name} fp64: max rel err {err.max():.3e}, median {np.median(err):.3e}")
+    nz = ref != 0
+    err = rel_err(got[nz], ref[nz])
+    print(f"{name} fp64: max rel err {err.max():.3e}, median {np.median(err):.3e} ({nz.sum()} of {n} pass the cut)")
     frac = assert_fp64_parity(oracle, name, mom, got, ref)
     assert frac > 0.98
 
@@ -129,7 +138,9 @@ def test_mixed_error_report(torch, oracle, name):
     ref = oracle_me2(oracle, name, mom)
     p = make(name, "mixed")
     got = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-    err = rel_err(got, ref)
+    nz = ref != 0
+    assert np.all(got[~nz] == 0.0)
+    err = rel_err(got[nz], ref[nz])
     print(f"{name} mixed: max rel err {err.max():.3e}, median {np.median(err):.3e}")
     assert np.all(np.isfinite(got))
     assert err.max() < 1e-2
@@ -167,7 +178,7 @@ def test_integrate_matches_oracle(torch, oracle, name):
     proc = p.ir
     sig, err, sw, sw2 = oracle.cross_section(f, oracle.phase_space_volume(rs, nout), rs, proc.n_a_n_b,
                                              proc.symmetry)
-    assert r["n_generated"] == n and r["n_accepted"] == n
+    assert r["n_generated"] == n and r["n_accepted"] == int(np.sum(f != 0))
     # the weighted sum is no better conditioned than its worst events (see assert_fp64_parity)
     tol = FP64_TOL if name != "ud_udhh_4b" else 1e-11
     assert abs(r["sigma_gev2"] / sig - 1) <= tol
@@ -185,6 +196,28 @@ def test_helicity_filter_keeps_result(torch, oracle, name, expect):
     assert kept == expect == p.n_helicities
     filt = p.eval(momenta=mom).cpu().numpy()
     assert rel_err(filt, full).max() <= 1e-13
+
+
+@pytest.mark.parametrize("leg", range(6))
+def test_gluon_ward_identity_on_gpu(torch, oracle, leg):
+    """g g -> g g g g: replacing one gluon's polarisation by k/k^0 (helicity
+    code 4) makes every colour-ordered amplitude vanish; |M|^2 drops to the
+    rounding level of the physical |M|^2."""
+    import itertools
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    proc = processes.by_name("gg_4g")
+    hels = [tuple(4 if k == leg else h[k - (k > leg)] for k in range(6))
+            for h in itertools.product((-1, 1), repeat=5)]
+    mom = oracle.generate(0x57A4D, 512, 4, 1000.0)
+    t = to_soa(torch, mom)
+    full = H.Process(proc).eval(momenta=t).cpu().numpy()
+    gauge = H.Process(proc, helicities=hels).eval(momenta=t).cpu().numpy()
+    nz = full > 0
+    assert nz.sum() > 100
+    ratio = np.sqrt(gauge[nz] / full[nz])
+    print(f"leg {leg}: max amplitude ratio {ratio.max():.2e}")
+    assert ratio.max() < 1e-12
 
 
 def test_edge_cases(torch, oracle):
