@@ -77,6 +77,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-leg", choices=["fp64", "mixed"], default=None,
+                    help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 1 GiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -88,6 +92,22 @@ def main():
     from paper_1305_0708_amd import processes, flops
 
     proc_ir = processes.gg_ttbar_6f()
+    if args.profile_leg:
+        proc = H.Process(proc_ir, precision=args.profile_leg)
+        wall, kern, r = time_path(torch, proc, args.steps, args.warmup)
+        out = {"leg": args.profile_leg, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
+               "events_per_launch": N_EVENTS, "flop_per_event": flops.per_event(proc_ir)}
+        if args.copy_calibration:
+            src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+            dst = torch.empty_like(src)
+            src.fill_(1.0)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            out["copy_bytes_each_way"] = src.numel() * 8
+        print(json.dumps(out), flush=True)
+        return
     fp64 = H.Process(proc_ir, precision="fp64")
     mixed = H.Process(proc_ir, precision="mixed")
 
