@@ -27,6 +27,23 @@ SEED = 0x48454746
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 
+# HBM traffic of one amplitude-kernel launch in the integrate step (FP64, 2^20
+# events), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch, steady-state launches) scaled by what the same counters read for a
+# plain 1 GiB device copy in the same run (FETCH_SIZE read 524,299.5 KiB for
+# 1,048,576 KiB fetched -> x2.0; WRITE_SIZE read 1,048,576 KiB -> x1.0).
+# Tied to the kernel source it was taken on: a different digest reports null.
+TRAFFIC_FP64 = {"source_digest": "e1e903ca35bf1a4c04cb286dd8187bb90cc70f374e94638d186806d215cc7bb1",
+                "fetch_kib": 349.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0}
+
+
+def measured_traffic(proc_ir):
+    from paper_1305_0708_amd import codegen
+    t = TRAFFIC_FP64
+    if codegen.source_digest(proc_ir) != t["source_digest"]:
+        return None
+    return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def time_path(torch, proc, steps, warmup, n=N_EVENTS):
     """Per step: one heget_integrate (amplitude kernel + reduction).  Also
@@ -142,7 +159,8 @@ def main():
                                "per step, 256 helicity combinations, 2 colour flows",
                    "events_per_step": N_EVENTS, "helicities": 256},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(proc_ir),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "amp_gg_ttbar_6f<double>", "kernel_ms": kern64 * 1e3,
                      "flop_per_event": flop_event},
         "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,

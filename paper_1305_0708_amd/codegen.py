@@ -394,6 +394,22 @@ class Gen:
         w(f"      me2 += double(cs) * {_c(Fraction(1, den))};")
 
 
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+_DEVICE_HEADERS = ("generated_common.hpp", "heget_device.hpp", "kernel_args.hpp", "phase_space.hpp")
+
+
+def source_digest(proc):
+    """SHA-256 over a process kernel's generated source and the device headers
+    it includes: it changes whenever the compiled kernel can change, so a
+    measurement tied to one kernel can tell that it has gone stale."""
+    import hashlib
+    h = hashlib.sha256(Gen(proc).emit().encode())
+    for name in _DEVICE_HEADERS:
+        with open(os.path.join(_CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def generate(proc, out_dir):
     src = Gen(proc).emit()
     path = os.path.join(out_dir, f"gen_{proc.name}.hip")
