@@ -131,7 +131,8 @@ typedef struct {
   const heget_call* calls;
   int32_t n_amps;
   int32_t n_flows;
-  const double* jamp;                 /* [n_flows][n_amps][2]: J_f = sum_a jamp[f][a] * amp_a */
+  const double* jamp;                 /* [rows][n_amps][2]: J_f = sum_a jamp[f][a] * amp_a; rows =
+                                         n_flows, or n_orderings for an ordering template */
   const double* colour_num;           /* [n_flows][n_flows] symmetric numerators */
   double colour_den;                  /* colour matrix = colour_num / colour_den */
   int32_t n_hel;
@@ -142,10 +143,17 @@ typedef struct {
   double cut_pt, cut_dr;
   /* Ordering table (colour-ordered processes), or n_orderings = 0.  When set,
    * the calls form a template over leg positions: for ordering o, input slot k
-   * < n_legs is external leg orderings[o][k], and flow o is the template's
-   * amplitude combination (every jamp row identical).  n_flows = n_orderings. */
+   * < n_legs is external leg orderings[o][k], and A_o is the template's
+   * amplitude combination (every jamp row identical). */
   int32_t n_orderings;
   const int8_t* orderings;            /* [n_orderings][n_legs] permutations of 0..n_legs-1 */
+  /* Flow map for an ordering template, or NULL: flow f's jamp is
+   * J_f = sum_o flow_map[f][o] A_o (e.g. the Kleiss-Kuijf expansion of the
+   * (n-1)! trace-basis partial amplitudes over the (n-2)! evaluated ones).
+   * NULL means J_o = A_o and n_flows = n_orderings.  Every row needs at least
+   * one non-zero entry.  Templates with n_flows >= 32 contract the colour
+   * matrix on MFMA (Sec. 5.4's colour sum as a batched dense product). */
+  const int8_t* flow_map;             /* [n_flows][n_orderings] */
 } heget_process_ir;
 
 typedef struct heget_process* heget_process_t;

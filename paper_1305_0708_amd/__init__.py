@@ -37,7 +37,7 @@ class _IRBuffers:
             ins = list(c.ins) + [-1] * (4 - len(c.ins))
             calls.append(L.heget_call(ir.OP[c.op], (ctypes.c_int32 * 4)(*ins), c.out, c.cpl, c.prop))
         self.calls = (L.heget_call * len(calls))(*calls)
-        dense = [0.0] * (proc.n_flows * proc.n_amps * 2)
+        dense = [0.0] * (len(proc.jamp) * proc.n_amps * 2)
         for f, terms in enumerate(proc.jamp):
             for a, coef in terms:
                 k = (f * proc.n_amps + a) * 2
@@ -54,11 +54,13 @@ class _IRBuffers:
         orders = proc.orderings or []
         flat_o = [int(x) for o in orders for x in o]
         self.orders = (ctypes.c_int8 * max(len(flat_o), 1))(*flat_o)
+        flat_m = [int(x) for r in (proc.flow_map or []) for x in r]
+        self.flow_map = (ctypes.c_int8 * max(len(flat_m), 1))(*flat_m)
         self.ir = L.heget_process_ir(
             proc.n_legs, self.legs, self.sm, len(proc.couplings), self.cpl, len(calls), self.calls,
             proc.n_amps, proc.n_flows, self.jamp, self.colour, float(den), len(hels), self.hel,
             proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr,
-            len(orders), self.orders if orders else None)
+            len(orders), self.orders if orders else None, self.flow_map if flat_m else None)
 
 
 class Process:

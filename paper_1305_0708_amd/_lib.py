@@ -48,7 +48,8 @@ class heget_process_ir(ctypes.Structure):
                 ("n_hel", ctypes.c_int32), ("helicities", ctypes.POINTER(ctypes.c_int8)),
                 ("n_a_n_b", ctypes.c_int32), ("symmetry", ctypes.c_int32),
                 ("cut_enabled", ctypes.c_int32), ("cut_pt", ctypes.c_double), ("cut_dr", ctypes.c_double),
-                ("n_orderings", ctypes.c_int32), ("orderings", ctypes.POINTER(ctypes.c_int8))]
+                ("n_orderings", ctypes.c_int32), ("orderings", ctypes.POINTER(ctypes.c_int8)),
+                ("flow_map", ctypes.POINTER(ctypes.c_int8))]
 
 
 class heget_result(ctypes.Structure):

@@ -144,9 +144,11 @@ class Gen:
         w("")
         w("}  // namespace")
         w("")
+        mf = p.uses_colour_mfma()
+        nks, nfo = ((p.n_flows + 3) // 4, (p.n_flows + 15) // 16) if mf else (0, 0)
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
-          f'reinterpret_cast<const void*>(&amp_{p.name}<float>)}};')
+          f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
@@ -224,9 +226,15 @@ class Gen:
         nl, no = self.nl, len(p.orderings)
         if any(leg.kind == F for leg in p.legs):
             raise NotImplementedError("ordering templates support vector and scalar legs")
+        mf = p.uses_colour_mfma()
         w(f"  __shared__ cx<T> jl[{no}][256];")
         w("  double me2 = 0.0;")
-        w("  if (pass) {")
+        if mf:
+            # the MFMA colour form needs every lane of the wavefront: run the
+            # chain wave-uniformly and stage zero amplitudes for failed lanes
+            w("  if (__any(pass)) {")
+        else:
+            w("  if (pass) {")
         w("    for (int h = 0; h < a.n_hel; ++h) {")
         w(f"      const int8_t* hh = a.hel + h * {nl};")
         w("#pragma unroll 1")
@@ -295,9 +303,21 @@ class Gen:
                       f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
             self._call(w, c, "        ")
         expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in p.jamp[0])
-        w(f"        jl[o][threadIdx.x] = {expr};")
-        w("      }")
-        self._colour(w, lambda f: f"jl[{f}][threadIdx.x]")
+        if mf:
+            w(f"        const cx<T> jo = {expr};")
+            w("        jl[o][threadIdx.x] = pass ? jo : cx<T>{T(0), T(0)};")
+            w("      }")
+            nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
+            w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
+            w("      __builtin_amdgcn_wave_barrier();")
+            w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
+            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}>(&jl[0][0], a.cstep, a.cterm, "
+              f"static_cast<const T*>(a.cfrag)));")
+            w("      __builtin_amdgcn_wave_barrier();")
+        else:
+            w(f"        jl[o][threadIdx.x] = {expr};")
+            w("      }")
+            self._colour(w, lambda f: f"jl[{f}][threadIdx.x]")
         w("    }")
         w("  }")
 
@@ -424,7 +444,8 @@ def main(argv):
     from . import processes
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(__file__), "csrc", "gen")
     os.makedirs(out, exist_ok=True)
-    for name in ("ee_mumu", "gg_ttbar_6f", "ud_udhh_4b", "gg_4g"):
+    from .build import PROCESSES
+    for name in PROCESSES:
         print(generate(processes.by_name(name), out))
 
 

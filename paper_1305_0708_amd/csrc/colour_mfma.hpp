@@ -1,0 +1,107 @@
+// Colour quadratic form Re(J^dagger C J) on the matrix cores (Sec. 5.4: the
+// colour sum of every event is the same dense symmetric form, so a batch of
+// events is one dense product).
+//
+// For one wavefront and one helicity, the 64 events are four column tiles of
+// 16 events.  With X the real (or imaginary) parts of the jamps, events x
+// flows, the kernel forms Z = C X^T with 16x16x4 MFMAs (rows = flows, columns
+// = events) and then sum_f X[e][f] Z[f][e] per event.  The K index of the
+// product is arranged so that the B operand a lane supplies at k-step
+// 4 fo + r is exactly the X element that multiplies the D element it holds in
+// register r of output tile fo: the final dot product is lane-local and only
+// the four lane groups are summed with two butterflies.
+//
+// Lane layout of v_mfma_{f64,f32}_16x16x4 (gfx950): A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4.
+//
+// Flow indices are those of the sorted order built by the library (flows
+// sorted by their number of flow-map terms, so that the four flows of one
+// k-step share one term count): k-step s, lane group g holds sorted flow
+// 4 s + g; output tile fo, row i holds sorted flow 16 fo + 4 (i % 4) + i / 4.
+// The A fragments (colour matrix, permuted and zero-padded) and the term
+// table are built on the host at process creation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "heget_device.hpp"
+
+namespace heget {
+
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc = mfma_d4;
+  static __device__ __forceinline__ acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  using acc = mfma_f4;
+  static __device__ __forceinline__ acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Returns Re(J^dagger C J) for the calling lane's event, where J_f = sum_o
+// coef * A_o over the flow-map terms and A_o = jl[o * 256 + threadIdx.x] are
+// the ordering amplitudes the block staged in LDS (row stride 256 events).
+// Every lane of the wavefront must call it (the MFMAs need the full wave) and
+// the wave's own 64 columns of jl must be written before the call.
+template <class T, int NKS, int NFO>
+__device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const uint32_t* cterm, const T* cfrag) {
+  static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
+  const int wbase = tid - lane;
+  T result = T(0);
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int ev = wbase + 16 * c + col;
+    T xr[4 * NFO], xi[4 * NFO];
+#pragma unroll
+    for (int s = 0; s < 4 * NFO; ++s) {
+      xr[s] = T(0);
+      xi[s] = T(0);
+      if (s < NKS) {
+        const int nt = __builtin_amdgcn_readfirstlane(cstep[2 * s]);
+        const int off = __builtin_amdgcn_readfirstlane(cstep[2 * s + 1]);
+        for (int t = 0; t < nt; ++t) {
+          const uint32_t e = cterm[4 * (off + t) + g];
+          const cx<T> v = jl[int(e & 0xffffu) * 256 + ev];
+          const T cf = T(int(int16_t(uint16_t(e >> 16))));
+          xr[s] += cf * v.r;
+          xi[s] += cf * v.i;
+        }
+      }
+    }
+    // The fragments are the same for every chunk and helicity; hide that from
+    // the optimiser so they stream from cache instead of being hoisted into
+    // (and spilled from) registers.
+    const T* frag = cfrag;
+    asm volatile("" : "+s"(frag));
+    T part = T(0);
+#pragma unroll
+    for (int fo = 0; fo < NFO; ++fo) {
+      typename Mfma<T>::acc zr = {T(0), T(0), T(0), T(0)}, zi = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int s = 0; s < NKS; ++s) {
+        const T av = frag[(fo * NKS + s) * 64 + lane];
+        zr = Mfma<T>::step(av, xr[s], zr);
+        zi = Mfma<T>::step(av, xi[s], zi);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part += zr[r] * xr[4 * fo + r] + zi[r] * xi[4 * fo + r];
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == c) result = part;
+  }
+  return result;
+}
+
+}  // namespace heget

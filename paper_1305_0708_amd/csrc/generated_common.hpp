@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "colour_mfma.hpp"
 #include "heget_device.hpp"
 #include "kernel_args.hpp"
 #include "phase_space.hpp"
@@ -16,6 +17,8 @@ struct GenEntry {
   int n_legs;
   const void* kernel_fp64;    // __global__ void(KernelArgs), T = double
   const void* kernel_mixed;   // T = float, FP64 momenta and denominators
+  int colour_mfma;            // 1: the colour form runs on MFMA and needs the tables below
+  int nks, nfo;               // its k-steps (ceil(n_flows / 4)) and output tiles (ceil(n_flows / 16))
 };
 void register_kernel(const GenEntry* e);
 struct Registrar {

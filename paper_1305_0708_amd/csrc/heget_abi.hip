@@ -2,6 +2,7 @@
 // the deterministic cross-section reduction.  Declarations: include/heget.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -41,6 +42,9 @@ heget_status fail(heget_status s, const std::string& msg) {
     hipError_t e_ = (expr);                                                                \
     if (e_ != hipSuccess) return fail(HEGET_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// rows of the jamp matrix: one per flow, or one per ordering for a template
+int jamp_rows(const heget_process_ir* ir) { return ir->n_orderings > 0 ? ir->n_orderings : ir->n_flows; }
 
 // FNV-1a over the canonical serialisation of the kernel-relevant IR structure
 struct Hasher {
@@ -86,7 +90,7 @@ uint64_t fingerprint(const heget_process_ir* ir) {
   }
   H.i32(ir->n_amps);
   H.i32(ir->n_flows);
-  for (int f = 0; f < ir->n_flows; ++f)
+  for (int f = 0; f < jamp_rows(ir); ++f)
     for (int a = 0; a < ir->n_amps; ++a) {
       H.f64(ir->jamp[(f * ir->n_amps + a) * 2]);
       H.f64(ir->jamp[(f * ir->n_amps + a) * 2 + 1]);
@@ -96,6 +100,9 @@ uint64_t fingerprint(const heget_process_ir* ir) {
   H.i32(ir->cut_enabled);
   H.i32(ir->n_orderings);
   for (int k = 0; k < ir->n_orderings * ir->n_legs; ++k) H.i32(ir->orderings[k]);
+  H.i32(ir->flow_map ? 1 : 0);
+  if (ir->flow_map)
+    for (int k = 0; k < ir->n_flows * ir->n_orderings; ++k) H.i32(ir->flow_map[k]);
   return H.h;
 }
 
@@ -178,8 +185,19 @@ heget_status validate(const heget_process_ir* ir) {
     if (!(v == -1 || v == 0 || v == 1 || v == 4)) return fail(HEGET_E_IR, "helicity values must be -1, 0, 1 or 4");
   }
   if (ir->n_a_n_b < 1 || ir->symmetry < 1) return fail(HEGET_E_IR, "averaging factors must be >= 1");
-  if (ir->n_orderings < 0 || (ir->n_orderings > 0 && (!ir->orderings || ir->n_orderings != ir->n_flows)))
-    return fail(HEGET_E_IR, "ordering table must have one row per flow");
+  if (ir->n_orderings < 0 || (ir->n_orderings > 0 && !ir->orderings))
+    return fail(HEGET_E_IR, "ordering table missing");
+  if (ir->n_orderings > 127) return fail(HEGET_E_IR, "at most 127 orderings");
+  if (ir->flow_map) {
+    if (ir->n_orderings == 0) return fail(HEGET_E_IR, "a flow map needs an ordering table");
+    for (int f = 0; f < ir->n_flows; ++f) {
+      bool any = false;
+      for (int o = 0; o < ir->n_orderings; ++o) any |= ir->flow_map[f * ir->n_orderings + o] != 0;
+      if (!any) return fail(HEGET_E_IR, "flow map row " + std::to_string(f) + " is all zero");
+    }
+  } else if (ir->n_orderings > 0 && ir->n_orderings != ir->n_flows) {
+    return fail(HEGET_E_IR, "without a flow map the ordering table must have one row per flow");
+  }
   for (int o = 0; o < ir->n_orderings; ++o) {
     std::vector<char> seen(ir->n_legs, 0);
     for (int k = 0; k < ir->n_legs; ++k) {
@@ -331,6 +349,9 @@ struct heget_process {
   PropEntry* d_prop = nullptr;
   int8_t* d_hel = nullptr;
   int8_t* d_ord = nullptr;   // ordering table (colour-ordered processes)
+  int* d_cstep = nullptr;    // MFMA colour form: k-step table, term table, colour fragments
+  uint32_t* d_cterm = nullptr;
+  void* d_cfrag = nullptr;
   double* d_part = nullptr;  // integrate partials, grown on demand and reused
   int64_t part_cap = 0;
   std::vector<int8_t> hel;  // host copy of the current table
@@ -360,6 +381,9 @@ KernelArgs base_args(heget_process_t p) {
   a.cut_pt = p->cut_pt;
   a.cut_dr = p->cut_dr;
   a.ord = p->d_ord;
+  a.cstep = p->d_cstep;
+  a.cterm = p->d_cterm;
+  a.cfrag = p->d_cfrag;
   return a;
 }
 
@@ -370,7 +394,69 @@ void release(heget_process* p) {
   if (p->d_hel) (void)hipFree(p->d_hel);
   if (p->d_part) (void)hipFree(p->d_part);
   if (p->d_ord) (void)hipFree(p->d_ord);
+  if (p->d_cstep) (void)hipFree(p->d_cstep);
+  if (p->d_cterm) (void)hipFree(p->d_cterm);
+  if (p->d_cfrag) (void)hipFree(p->d_cfrag);
   delete p;
+}
+
+// Host tables of the MFMA colour form (layouts in colour_mfma.hpp).  Flows are
+// sorted by their number of flow-map terms (stable), so that the four flows of
+// one k-step share one term count; a k-step's shorter rows are padded with
+// zero-coefficient terms.
+struct ColourTables {
+  std::vector<int> cstep;        // [nks][2] (terms, offset)
+  std::vector<uint32_t> cterm;   // [sum terms][4]
+  std::vector<double> cfrag;     // [nfo][nks][64]
+};
+
+heget_status colour_tables(const heget_process_ir* ir, const GenEntry* e, ColourTables& t) {
+  const int nf = ir->n_flows, no = ir->n_orderings;
+  if (no <= 0) return fail(HEGET_E_IR, "the MFMA colour form needs an ordering table");
+  if (e->nks != (nf + 3) / 4 || e->nfo != (nf + 15) / 16)
+    return fail(HEGET_E_IR, "kernel tile counts disagree with n_flows");
+  std::vector<std::vector<std::pair<int, int>>> rows(nf);
+  for (int f = 0; f < nf; ++f)
+    for (int o = 0; o < no; ++o) {
+      const int c = ir->flow_map ? ir->flow_map[f * no + o] : (o == f ? 1 : 0);
+      if (c != 0) rows[f].push_back({o, c});
+    }
+  std::vector<int> order(nf);
+  for (int f = 0; f < nf; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return rows[a].size() < rows[b].size(); });
+  const int nks = e->nks, nfo = e->nfo;
+  t.cstep.assign(2 * size_t(nks), 0);
+  t.cterm.clear();
+  int off = 0;
+  for (int s = 0; s < nks; ++s) {
+    int nt = 0;
+    for (int g = 0; g < 4; ++g)
+      if (4 * s + g < nf) nt = std::max(nt, int(rows[order[4 * s + g]].size()));
+    t.cstep[2 * s] = nt;
+    t.cstep[2 * s + 1] = off;
+    for (int k = 0; k < nt; ++k)
+      for (int g = 0; g < 4; ++g) {
+        uint32_t word = 0;
+        if (4 * s + g < nf) {
+          const auto& r = rows[order[4 * s + g]];
+          if (k < int(r.size())) word = uint32_t(r[k].first) | (uint32_t(uint16_t(int16_t(r[k].second))) << 16);
+        }
+        t.cterm.push_back(word);
+      }
+    off += nt;
+  }
+  auto cs = [&](int a, int b) {
+    return (a < nf && b < nf) ? ir->colour_num[order[a] * nf + order[b]] / ir->colour_den : 0.0;
+  };
+  t.cfrag.assign(size_t(nfo) * nks * 64, 0.0);
+  for (int fo = 0; fo < nfo; ++fo)
+    for (int s = 0; s < nks; ++s)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, k = lane >> 4;
+        t.cfrag[(size_t(fo) * nks + s) * 64 + lane] = cs(16 * fo + 4 * (i % 4) + i / 4, 4 * s + k);
+      }
+  return HEGET_OK;
 }
 
 }  // namespace
@@ -430,6 +516,28 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
     if (hipMemcpy(p->d_ord, ir->orderings, nb, hipMemcpyHostToDevice) != hipSuccess) {
       release(p);
       return fail(HEGET_E_HIP, "upload of the ordering table failed");
+    }
+  }
+  if (entry->colour_mfma) {
+    ColourTables t;
+    if (heget_status st = colour_tables(ir, entry, t)) {
+      release(p);
+      return st;
+    }
+    std::vector<float> f32(t.cfrag.begin(), t.cfrag.end());
+    const void* frag = prec == HEGET_FP64 ? static_cast<const void*>(t.cfrag.data()) : f32.data();
+    const size_t fb = t.cfrag.size() * (prec == HEGET_FP64 ? sizeof(double) : sizeof(float));
+    if (hipMalloc(&p->d_cstep, t.cstep.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_cterm, std::max<size_t>(t.cterm.size(), 4) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&p->d_cfrag, fb) != hipSuccess) {
+      release(p);
+      return fail(HEGET_E_OOM, "device allocation of the colour tables failed");
+    }
+    if (hipMemcpy(p->d_cstep, t.cstep.data(), t.cstep.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_cterm, t.cterm.data(), t.cterm.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_cfrag, frag, fb, hipMemcpyHostToDevice) != hipSuccess) {
+      release(p);
+      return fail(HEGET_E_HIP, "upload of the colour tables failed");
     }
   }
   *out = p;

@@ -29,6 +29,10 @@ struct KernelArgs {
   double weight_factor;      // phase-space weight x flux x averages x 1/S (integrate)
   double* partials;          // integrate: [gridDim.x][3] (sum w, sum w^2, accepted), or null
   const int8_t* ord;         // ordering table [n_orderings][n_legs] of colour-ordered processes
+  // MFMA colour form (ordering templates with many flows; see colour_mfma.hpp)
+  const int* cstep;          // [nks][2]: terms per flow in k-step s, offset of its term rows
+  const uint32_t* cterm;     // [sum nterm][4]: (ordering | coefficient << 16) per lane group
+  const void* cfrag;         // [nfo][nks][64] colour-matrix A fragments, double or float
 };
 
 }  // namespace heget

@@ -74,8 +74,27 @@ def per_helicity(proc):
     else:
         n += sum(CADD * max(len(t) - 1, 0) for t in proc.jamp)      # jamp sums
     nf = proc.n_flows
-    n += nf * 4 + (nf * (nf - 1) // 2) * 4 + 2                      # colour quadratic form
+    if proc.uses_colour_mfma():
+        n += colour_mfma_flops(proc)
+    else:
+        n += nf * 4 + (nf * (nf - 1) // 2) * 4 + 2                  # colour quadratic form
     return n
+
+
+def colour_mfma_flops(proc):
+    """Algorithmic flops of the MFMA colour form for one helicity of one event:
+    the flow-map sums (a complex add per term), the dense product C X^T for
+    the real and the imaginary parts (2 n_f^2 each) and the dot products
+    (2 n_f each).  The zero padding to whole 16 x 16 x 4 tiles is not counted."""
+    nf = proc.n_flows
+    terms = sum(sum(1 for x in row if x) for row in proc.flow_map) if proc.flow_map else nf
+    return CADD * terms + 2 * (2 * nf * nf) + 2 * (2 * nf)
+
+
+def colour_mfma_flops_executed(proc):
+    """flops the MFMA instructions execute per helicity and event, padding included"""
+    nks, nfo = (proc.n_flows + 3) // 4, (proc.n_flows + 15) // 16
+    return 2 * (2 * (16 * nfo) * (4 * nks))
 
 
 def per_event(proc, n_hel=None):

@@ -41,6 +41,7 @@ OUT_KIND = {"fvi": F, "fvo": F, "jio": V, "fsi": F, "fso": F, "hio": S, "jvv": V
             "vadd": V, "vsub": V}
 # ops whose output carries the momentum of their first input (not the sum)
 LINEAR_OPS = {"vadd", "vsub"}
+MFMA_MIN_FLOWS = 32
 # input kinds per op (in argument order)
 IN_KINDS = {
     "iov": (F, F, V), "fvi": (F, V), "fvo": (F, V), "jio": (F, F),
@@ -109,6 +110,16 @@ class Process:
     # bound to external leg orderings[o][k]; flow o is the template's
     # amplitude combination jamp[o] for that ordering (all rows equal).
     orderings: Optional[List[Tuple[int, ...]]] = None
+    # Optional flow map for ordering templates: flow f's jamp is
+    # sum_o flow_map[f][o] * (ordering o's amplitude combination), small
+    # integer coefficients; None means one flow per ordering.  With it the
+    # colour matrix is n_flows x n_flows in the flows' basis.
+    flow_map: Optional[List[List[int]]] = None
+
+    def uses_colour_mfma(self):
+        """The colour quadratic form runs on MFMA for ordering templates with
+        at least MFMA_MIN_FLOWS flows; small colour bases stay on VALU."""
+        return self.orderings is not None and self.n_flows >= MFMA_MIN_FLOWS
 
     @property
     def n_legs(self):
@@ -157,8 +168,10 @@ class Process:
                 raise ValueError(f"call {k}: bad coupling index")
         if amps != set(range(self.n_amps)):
             raise ValueError("every amplitude index must be produced exactly once")
-        if len(self.jamp) != self.n_flows or len(self.colour) != self.n_flows:
-            raise ValueError("jamp / colour sizes disagree with n_flows")
+        n_rows = len(self.orderings) if self.orderings is not None else self.n_flows
+        if len(self.jamp) != n_rows or len(self.colour) != self.n_flows:
+            raise ValueError("jamp / colour sizes disagree with n_flows (jamp: one row per ordering "
+                             "for templates)")
         for r in range(self.n_flows):
             for c in range(self.n_flows):
                 if self.colour[r][c] != self.colour[c][r]:
@@ -166,9 +179,17 @@ class Process:
         for h in self.helicities:
             if len(h) != self.n_legs:
                 raise ValueError("helicity row length != number of legs")
+        if self.flow_map is not None:
+            if self.orderings is None:
+                raise ValueError("a flow map needs an ordering table")
+            if len(self.flow_map) != self.n_flows or any(len(r) != len(self.orderings) for r in self.flow_map):
+                raise ValueError("flow map must be n_flows x n_orderings")
+            for r in self.flow_map:
+                if not any(r) or any(int(x) != x or not -127 <= x <= 127 for x in r):
+                    raise ValueError("flow map rows: int8 coefficients, at least one non-zero")
         if self.orderings is not None:
-            if len(self.orderings) != self.n_flows:
-                raise ValueError("one flow per ordering")
+            if self.flow_map is None and len(self.orderings) != self.n_flows:
+                raise ValueError("one flow per ordering without a flow map")
             for o in self.orderings:
                 if sorted(o) != list(range(self.n_legs)):
                     raise ValueError("orderings must be permutations of the legs")
@@ -223,6 +244,10 @@ class Process:
         i32(len(orders))
         for o in orders:
             for x in o:
+                i32(x)
+        i32(0 if self.flow_map is None else 1)
+        for r in self.flow_map or []:
+            for x in r:
                 i32(x)
         return bytes(b)
 

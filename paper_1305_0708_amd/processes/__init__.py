@@ -10,7 +10,7 @@ Leg order (the momentum layout of heget_eval):
   ee_mumu      e-(in, +z) e+(in, -z) mu- mu+
   gg_ttbar_6f  g g b e+ nu_e bbar mu- nu_mu~      (t -> b e+ nu_e, tbar -> bbar mu- nu_mu~)
   ud_udhh_4b   u d u d b bbar b bbar              (H -> b bbar twice)
-  gg_4g        g g g g g g
+  gg_4g        g g g g g g   (120 trace-basis flows; gg_4g_ddm: the 24 evaluated orderings as flows)
 """
 from fractions import Fraction
 
@@ -120,7 +120,7 @@ def ud_udhh_4b(sqrt_s=2000.0):
 
 
 def by_name(name):
-    if name == "gg_4g":
+    if name in ("gg_4g", "gg_4g_ddm"):
         from .gluons import gg_ng
-        return gg_ng(6)
+        return gg_ng(6, basis="trace" if name == "gg_4g" else "ddm")
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "ud_udhh_4b": ud_udhh_4b}[name]()

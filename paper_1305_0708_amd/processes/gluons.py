@@ -138,8 +138,14 @@ def ddm_colour_matrix(n):
 
 
 # ------------------------------------------------------------- call chains
-def gg_ng(n=6, sqrt_s=1000.0, cut_pt=20.0, cut_dr=0.4):
+def gg_ng(n=6, sqrt_s=1000.0, cut_pt=20.0, cut_dr=0.4, basis="trace"):
     """g g -> (n-2) g with the generation cut (pT > cut_pt, Delta R > cut_dr).
+
+    basis "trace": the (n-1)! trace-basis flows A(0, sigma) with the dense
+    (n-1)! x (n-1)! colour matrix (120 x 120 for n = 6), each flow the
+    Kleiss-Kuijf combination of the evaluated orderings (the flow map); the
+    colour form runs on MFMA from 32 flows on.  basis "ddm": the (n-2)!
+    evaluated orderings are the flows, with K^T C K as colour matrix.
 
     The IR is an ordering template: the calls of one colour ordering over leg
     positions 0..n-1 (position 0 is the root leg 0), evaluated for each of the
@@ -207,10 +213,16 @@ def gg_ng(n=6, sqrt_s=1000.0, cut_pt=20.0, cut_dr=0.4):
             terms.append((amp, 2.0))
             amp += 1
     orders = ddm_orderings(n)
-    colour = ddm_colour_matrix(n)
     name = {4: "gg_gg", 5: "gg_3g", 6: "gg_4g"}.get(n, f"gg_{n - 2}g")
-    proc = Process(name, legs, cpl, calls, n_amps=amp, n_flows=len(orders), jamp=[list(terms)] * len(orders),
+    if basis == "trace":
+        colour, flow_map = colour_matrix(n), [list(r) for r in kk_matrix(n)]
+    elif basis == "ddm":
+        colour, flow_map = ddm_colour_matrix(n), None
+        name += "_ddm"
+    else:
+        raise ValueError(f"unknown colour basis {basis!r}")
+    proc = Process(name, legs, cpl, calls, n_amps=amp, n_flows=len(colour), jamp=[list(terms)] * len(orders),
                    colour=colour, helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64,
                    symmetry=math.factorial(n - 2), cut_pt=cut_pt, cut_dr=cut_dr, cut_enabled=n > 4,
-                   orderings=[tuple(o) for o in orders])
+                   orderings=[tuple(o) for o in orders], flow_map=flow_map)
     return proc.validate()

@@ -53,7 +53,18 @@ def test_ddm_colour_form_equals_trace_form(oracle):
 
 def test_gluon_ir_shape():
     from paper_1305_0708_amd.processes import gluons
+    for basis, nf in (("trace", 120), ("ddm", 24)):
+        p = gluons.gg_ng(6, basis=basis)
+        assert p.n_flows == nf and len(p.orderings) == 24 and len(p.colour) == nf
+        assert all(o[0] == 0 and o[-1] == 5 for o in p.orderings)
+        assert p.symmetry == 24 and p.n_a_n_b == 64 and p.cut_enabled
+        assert p.uses_colour_mfma() == (basis == "trace")
+    # trace basis: flow f is the Kleiss-Kuijf row of ordering f, with 1, 4, 6, 4, 1 terms as the
+    # last gluon sits at the end, one, two, three or four places before it
     p = gluons.gg_ng(6)
-    assert p.n_flows == 24 and len(p.orderings) == 24
-    assert all(o[0] == 0 and o[-1] == 5 for o in p.orderings)
-    assert p.symmetry == 24 and p.n_a_n_b == 64 and p.cut_enabled
+    counts = sorted(sum(1 for x in r if x) for r in p.flow_map)
+    assert counts == sorted([1] * 24 + [4] * 24 + [6] * 24 + [4] * 24 + [1] * 24)
+    ddm = {o: k for k, o in enumerate(p.orderings)}
+    for f, t in enumerate(gluons.trace_orderings(6)):
+        if t[-1] == 5:
+            assert p.flow_map[f] == [1 if k == ddm[t] else 0 for k in range(24)]
