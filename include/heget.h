@@ -214,6 +214,64 @@ heget_status heget_filter_helicities(heget_process_t p, int64_t n_probe, uint64_
 /* Thread-local message describing the last non-OK status ("" if none). */
 const char* heget_last_error(void);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop over resident processes: requests heget_integrate(process,
+ * n, sqrt_s, seed) arrive at any time from any thread, are admitted in arrival
+ * order while their device footprint fits a fixed arena, and run as fused
+ * launches (several requests of one process in one persistent kernel, replayed
+ * from a HIP graph captured at creation), several launches at once on their
+ * own streams.  A request split over several launches keeps the Philox
+ * counters, partial-sum slots and reduction order of heget_integrate of that
+ * request alone: its result is bit-identical to that call on the same handle,
+ * whatever else is in flight.  The process handles stay owned by the caller,
+ * must outlive the server, and must not be used for heget_filter_helicities
+ * while the server exists (the server captures their tables at creation). */
+typedef struct heget_server* heget_server_t;
+
+typedef struct {
+  int32_t n_processes;
+  const heget_process_t* processes;  /* [n_processes], each with its own precision */
+  int64_t arena_bytes;               /* device memory for requests in flight (>= 1 MiB) */
+  int32_t slots_per_process;         /* concurrent fused launches per process, 1..8 */
+  int32_t max_batch_blocks;          /* 256-event blocks per fused launch */
+  int32_t max_chunk_blocks;          /* blocks of one request per fused launch */
+} heget_server_config;
+
+typedef struct {
+  int64_t requests_submitted, requests_done;
+  int64_t launches, segments, events;  /* fused launches, request segments in them, events run */
+  int64_t arena_high_water;            /* bytes */
+  int32_t max_busy_slots;              /* most fused launches in flight at once */
+} heget_server_stats;
+
+/* Allocates the arena, captures one graph per (process, slot) and starts the
+ * scheduler thread on the current device.
+ * Errors: HEGET_E_INVALID (bad configuration), HEGET_E_OOM, HEGET_E_HIP. */
+heget_status heget_server_create(const heget_server_config* cfg, heget_server_t* out);
+
+/* Queue a request; returns at once with its ticket.  Footprint: 24 bytes per
+ * 256 events, plus 8 bytes per event if me2_host is given (then the request's
+ * |M|^2 per event, as heget_eval would give it, is copied into me2_host[n]
+ * before the request completes; the buffer must stay valid until then).
+ * Errors: HEGET_E_INVALID (bad index, n < 2, sqrt_s <= 0, footprint larger
+ * than the arena, server shutting down). */
+heget_status heget_server_submit(heget_server_t s, int32_t process, int64_t n, uint64_t seed, double sqrt_s,
+                                 double* me2_host, uint64_t* ticket);
+
+/* Result of a request: with wait != 0 blocks until it is done.  Sets *done;
+ * when done, fills *out and the submit-to-completion time *latency_s (may be
+ * NULL) and forgets the ticket.  Errors: HEGET_E_INVALID (unknown ticket), or
+ * the request's own failure (HEGET_E_HIP). */
+heget_status heget_server_poll(heget_server_t s, uint64_t ticket, int32_t wait, heget_result* out,
+                               double* latency_s, int32_t* done);
+
+/* Counters since creation. */
+heget_status heget_server_stats_get(heget_server_t s, heget_server_stats* out);
+
+/* Runs every queued request to completion, stops the scheduler and frees the
+ * server (not the process handles).  Tickets not yet polled are dropped. */
+heget_status heget_server_destroy(heget_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

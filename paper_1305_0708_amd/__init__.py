@@ -147,3 +147,69 @@ class Process:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """The serving engine (heget_server_*): requests heget_integrate(process,
+    n, sqrt_s, seed) submitted at any time run as fused launches over the
+    resident processes; results are bit-identical to Process.integrate."""
+
+    def __init__(self, processes, arena_bytes=1 << 30, slots_per_process=2, max_batch_blocks=4096,
+                 max_chunk_blocks=1024):
+        self._lib = _lib.load()
+        self._procs = list(processes)               # keep the handles alive
+        arr = (ctypes.c_void_p * len(self._procs))(*[p._h.value for p in self._procs])
+        self._arr = arr
+        cfg = _lib.heget_server_config(len(self._procs), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)),
+                                       int(arena_bytes), int(slots_per_process), int(max_batch_blocks),
+                                       int(max_chunk_blocks))
+        h = ctypes.c_void_p()
+        check(self._lib.heget_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._me2 = {}
+
+    def submit(self, process, n, seed, sqrt_s, want_me2=False):
+        """Queue a request for self.processes[process]; returns its ticket."""
+        import numpy as np
+        buf = np.empty(n, dtype=np.float64) if want_me2 else None
+        t = ctypes.c_uint64()
+        ptr = ctypes.c_void_p(buf.ctypes.data) if buf is not None else None
+        check(self._lib.heget_server_submit(self._h, int(process), int(n), int(seed), float(sqrt_s), ptr,
+                                            ctypes.byref(t)))
+        if buf is not None:
+            self._me2[t.value] = buf
+        return t.value
+
+    def poll(self, ticket, wait=True):
+        """None if not done (wait=False), else (result dict, latency in s[, |M|^2 array])."""
+        r = _lib.heget_result()
+        lat = ctypes.c_double()
+        done = ctypes.c_int32()
+        try:
+            check(self._lib.heget_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(r),
+                                              ctypes.byref(lat), ctypes.byref(done)))
+        except Exception:
+            self._me2.pop(ticket, None)
+            raise
+        if not done.value:
+            return None
+        res = {k: getattr(r, k) for k, _ in r._fields_}
+        me2 = self._me2.pop(ticket, None)
+        return (res, lat.value) if me2 is None else (res, lat.value, me2)
+
+    def stats(self):
+        st = _lib.heget_server_stats()
+        check(self._lib.heget_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.heget_server_destroy(self._h))
+            self._h = None
+            self._me2.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

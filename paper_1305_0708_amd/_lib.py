@@ -9,7 +9,9 @@ HEGET_OK, HEGET_E_INVALID, HEGET_E_IR, HEGET_E_OOM, HEGET_E_HIP, HEGET_E_UNSUPPO
 HEGET_FP64, HEGET_MIXED = 0, 1
 
 EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "heget_integrate",
-            "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error"]
+            "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error",
+            "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
+            "heget_server_destroy"]
 
 
 class heget_sm(ctypes.Structure):
@@ -59,6 +61,18 @@ class heget_result(ctypes.Structure):
                 ("n_generated", ctypes.c_int64), ("n_accepted", ctypes.c_int64)]
 
 
+class heget_server_config(ctypes.Structure):
+    _fields_ = [("n_processes", ctypes.c_int32), ("processes", ctypes.POINTER(ctypes.c_void_p)),
+                ("arena_bytes", ctypes.c_int64), ("slots_per_process", ctypes.c_int32),
+                ("max_batch_blocks", ctypes.c_int32), ("max_chunk_blocks", ctypes.c_int32)]
+
+
+class heget_server_stats(ctypes.Structure):
+    _fields_ = [("requests_submitted", ctypes.c_int64), ("requests_done", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("segments", ctypes.c_int64), ("events", ctypes.c_int64),
+                ("arena_high_water", ctypes.c_int64), ("max_busy_slots", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -92,6 +106,18 @@ def load(path=None):
     L.heget_filter_helicities.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_int32)]
     L.heget_filter_helicities.restype = ctypes.c_int
+    L.heget_server_create.argtypes = [ctypes.POINTER(heget_server_config), ctypes.POINTER(vp)]
+    L.heget_server_create.restype = ctypes.c_int
+    L.heget_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, vp,
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    L.heget_server_submit.restype = ctypes.c_int
+    L.heget_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(heget_result),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    L.heget_server_poll.restype = ctypes.c_int
+    L.heget_server_stats_get.argtypes = [vp, ctypes.POINTER(heget_server_stats)]
+    L.heget_server_stats_get.restype = ctypes.c_int
+    L.heget_server_destroy.argtypes = [vp]
+    L.heget_server_destroy.restype = ctypes.c_int
     L.heget_last_error.argtypes = []
     L.heget_last_error.restype = ctypes.c_char_p
     _lib = L

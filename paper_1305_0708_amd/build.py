@@ -34,10 +34,11 @@ def generate_sources():
     return out
 
 
-def _compile(src):
+def _compile(src, force=False):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-    if os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + \
+        [os.path.join(os.path.dirname(CSRC), "..", "include", "heget.h")]
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
         return obj
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,12 +48,14 @@ def _compile(src):
     return obj
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, force=False):
+    """Generate and compile every translation unit and link libheget.so; with
+    force, recompile even objects newer than their sources."""
     os.makedirs(OBJ, exist_ok=True)
-    srcs = generate_sources() + [os.path.join(CSRC, "heget_abi.hip")]
+    srcs = generate_sources() + [os.path.join(CSRC, "heget_abi.hip"), os.path.join(CSRC, "heget_server.hip")]
     jobs = jobs or min(8, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, force), srcs))
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -98,8 +98,8 @@ class Gen:
         w("namespace {")
         w("")
         w("template <class T>")
-        w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
-        w("  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;")
+        w(f"__device__ __forceinline__ void body_{p.name}(const KernelArgs& a, int64_t blk) {{")
+        w("  const int64_t i = blk * blockDim.x + threadIdx.x;")
         w("  const bool active = i < a.n;")
         w(f"  mom p[{self.nl}];")
         w("  if (active) {")
@@ -139,7 +139,29 @@ class Gen:
         else:
             self._emit_straight(w)
         w("  if (a.me2_out && active) a.me2_out[i] = me2;")
-        w("  if (a.partials) block_partials(a, pass ? me2 * a.weight_factor : 0.0, pass);")
+        w("  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor : 0.0, pass);")
+        w("}")
+        w("")
+        w("// one launch: block b evaluates events 256 b ... 256 b + 255")
+        w("template <class T>")
+        w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
+        w(f"  body_{p.name}<T>(a, blockIdx.x);")
+        w("}")
+        w("")
+        w("// fused launch of several requests (serving engine): a persistent grid")
+        w("// walks the virtual blocks of the batch table")
+        w("template <class T>")
+        w(f"__global__ __launch_bounds__(256) void amp_{p.name}_batch(KernelArgs a) {{")
+        w("  const BatchTable* bt = a.batch;")
+        w("  const int64_t total = bt->total_blocks;")
+        w("  const int nseg = bt->n_seg;")
+        w("  int s = 0;")
+        w("  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {")
+        w("    while (s + 1 < nseg && bt->seg[s + 1].block_begin <= vb) ++s;")
+        w("    KernelArgs b = segment_args(a, bt->seg[s]);")
+        w(f"    body_{p.name}<T>(b, bt->seg[s].block_offset + (vb - bt->seg[s].block_begin));")
+        w("    __syncthreads();")
+        w("  }")
         w("}")
         w("")
         w("}  // namespace")
@@ -148,7 +170,9 @@ class Gen:
         nks, nfo = ((p.n_flows + 3) // 4, (p.n_flows + 15) // 16) if mf else (0, 0)
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
-          f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}}};')
+          f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
+          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
+          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>)}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")

@@ -19,7 +19,25 @@ struct GenEntry {
   const void* kernel_mixed;   // T = float, FP64 momenta and denominators
   int colour_mfma;            // 1: the colour form runs on MFMA and needs the tables below
   int nks, nfo;               // its k-steps (ceil(n_flows / 4)) and output tiles (ceil(n_flows / 16))
+  const void* batch_fp64;     // fused persistent variants reading KernelArgs::batch
+  const void* batch_mixed;
 };
+
+// The launch arguments of one request's segment in a fused launch.
+__device__ __forceinline__ KernelArgs segment_args(const KernelArgs& a, const Segment& g) {
+  KernelArgs b = a;
+  b.n = g.n;
+  b.mom_in = nullptr;
+  b.mom_stride = g.n;
+  b.seed = g.seed;
+  b.counter_offset = 0;
+  b.sqrt_s = g.sqrt_s;
+  b.me2_out = g.me2_out;
+  b.mom_out = nullptr;
+  b.weight_factor = g.weight_factor;
+  b.partials = g.partials;
+  return b;
+}
 void register_kernel(const GenEntry* e);
 struct Registrar {
   explicit Registrar(const GenEntry* e) { register_kernel(e); }
@@ -39,8 +57,9 @@ __device__ __forceinline__ void store_momenta(const KernelArgs& a, int64_t i, co
 
 // Deterministic per-block partial sums (w, w^2, accepted) for the cross
 // section: a fixed butterfly inside each 64-lane wavefront, then the waves in
-// order.  Every thread of the block must call it.
-__device__ __forceinline__ void block_partials(const KernelArgs& a, double wgt, bool acc) {
+// order.  Every thread of the block must call it; blk is the block's index
+// within its request.
+__device__ __forceinline__ void block_partials(const KernelArgs& a, int64_t blk, double wgt, bool acc) {
   double s = wgt, s2 = wgt * wgt, c = acc ? 1.0 : 0.0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -64,10 +83,48 @@ __device__ __forceinline__ void block_partials(const KernelArgs& a, double wgt, 
       t2 += red[1][k];
       tc += red[2][k];
     }
-    a.partials[3 * blockIdx.x + 0] = t;
-    a.partials[3 * blockIdx.x + 1] = t2;
-    a.partials[3 * blockIdx.x + 2] = tc;
+    a.partials[3 * blk + 0] = t;
+    a.partials[3 * blk + 1] = t2;
+    a.partials[3 * blk + 2] = tc;
   }
+}
+
+// Fixed-order reduction of per-block partial triples with Neumaier
+// compensation, by one block: thread t sums blocks t, t + T, ... in order, then
+// thread 0 combines the T results in order.  Used by the single-request
+// reduction and by the serving engine's batched one, so both give the same bits.
+__device__ inline void reduce_triples(const double* partials, int64_t nblocks, double* out) {
+  __shared__ double sm[3][256];
+  __shared__ double cm[3][256];
+  const int t = threadIdx.x;
+  double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+  for (int64_t b = t; b < nblocks; b += blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      const double x = partials[3 * b + k];
+      const double u = s[k] + x;
+      c[k] += (fabs(s[k]) >= fabs(x)) ? ((s[k] - u) + x) : ((x - u) + s[k]);
+      s[k] = u;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    sm[k][t] = s[k];
+    cm[k][t] = c[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int k = 0; k < 3; ++k) {
+      double S = 0.0, C = 0.0;
+      for (int j = 0; j < int(blockDim.x); ++j) {
+        const double x = sm[k][j];
+        const double u = S + x;
+        C += (fabs(S) >= fabs(x)) ? ((S - u) + x) : ((x - u) + S);
+        S = u;
+        C += cm[k][j];
+      }
+      out[k] = S + C;
+    }
+  }
+  __syncthreads();
 }
 
 }  // namespace heget

@@ -13,6 +13,7 @@
 
 #include "generated_common.hpp"
 #include "heget.h"
+#include "heget_internal.hpp"
 
 namespace heget {
 
@@ -29,13 +30,17 @@ using heget::KernelArgs;
 using heget::PropEntry;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-heget_status fail(heget_status s, const std::string& msg) {
+heget_status heget::detail::fail(heget_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+
+namespace {
+
+using heget::detail::fail;
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
@@ -290,7 +295,9 @@ void prop_table(const heget_sm& sm, PropEntry t[HEGET_N_PARTICLES]) {
   fill(t[HEGET_P_H], sm.mh, sm.wh, cd(sm.mh * sm.mh, -sm.mh * sm.wh), 0.0);
 }
 
-double phase_space_volume(double sqrt_s, int n) {
+}  // namespace
+
+double heget::detail::phase_space_volume(double sqrt_s, int n) {
   const double pi = 3.14159265358979323846;
   double f1 = 1.0, f2 = 1.0;
   for (int i = 2; i <= n - 1; ++i) f1 *= i;
@@ -299,63 +306,34 @@ double phase_space_volume(double sqrt_s, int n) {
   return std::pow(2.0 * pi, 4 - 3 * n) * std::pow(0.5 * pi, n - 1) * std::pow(s, n - 2) / (f1 * f2);
 }
 
-// Fixed-order reduction of the per-block partials with Neumaier compensation:
-// thread t sums blocks t, t + T, ... in order, then the T partial results are
-// combined by thread 0 in order.
+double heget::detail::weight_factor(heget_process_t p, double sqrt_s) {
+  const double s = sqrt_s * sqrt_s;
+  return phase_space_volume(sqrt_s, p->n_legs - 2) / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
+}
+
+void heget::detail::fill_result(const double h[3], int64_t n, heget_result* out) {
+  const double N = double(n);
+  out->sum_w = h[0];
+  out->sum_w2 = h[1];
+  out->n_generated = n;
+  out->n_accepted = int64_t(h[2] + 0.5);
+  out->sigma_gev2 = h[0] / N;
+  const double var = std::max(h[1] / N - out->sigma_gev2 * out->sigma_gev2, 0.0);
+  out->err_gev2 = std::sqrt(var / (N - 1.0));
+  const double hbarc2 = 0.3893793721e9;
+  out->sigma_pb = out->sigma_gev2 * hbarc2;
+  out->err_pb = out->err_gev2 * hbarc2;
+}
+
+namespace {
+
+// Fixed-order reduction of one request's per-block partials (one block).
 __global__ __launch_bounds__(256) void reduce_partials(const double* partials, int64_t nblocks, double* out) {
-  __shared__ double sm[3][256];
-  __shared__ double cm[3][256];
-  const int t = threadIdx.x;
-  double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
-  for (int64_t b = t; b < nblocks; b += blockDim.x) {
-    for (int k = 0; k < 3; ++k) {
-      const double x = partials[3 * b + k];
-      const double u = s[k] + x;
-      c[k] += (fabs(s[k]) >= fabs(x)) ? ((s[k] - u) + x) : ((x - u) + s[k]);
-      s[k] = u;
-    }
-  }
-  for (int k = 0; k < 3; ++k) {
-    sm[k][t] = s[k];
-    cm[k][t] = c[k];
-  }
-  __syncthreads();
-  if (t == 0) {
-    for (int k = 0; k < 3; ++k) {
-      double S = 0.0, C = 0.0;
-      for (int j = 0; j < int(blockDim.x); ++j) {
-        const double x = sm[k][j];
-        const double u = S + x;
-        C += (fabs(S) >= fabs(x)) ? ((S - u) + x) : ((x - u) + S);
-        S = u;
-        C += cm[k][j];
-      }
-      out[k] = S + C;
-    }
-  }
+  heget::reduce_triples(partials, nblocks, out);
 }
 
 }  // namespace
 
-struct heget_process {
-  const GenEntry* entry = nullptr;
-  heget_precision prec = HEGET_FP64;
-  int n_legs = 0;
-  int n_hel = 0;
-  int cut_enabled = 0;
-  double cut_pt = 0, cut_dr = 0;
-  int n_a_n_b = 1, symmetry = 1;
-  double* d_cpl = nullptr;
-  PropEntry* d_prop = nullptr;
-  int8_t* d_hel = nullptr;
-  int8_t* d_ord = nullptr;   // ordering table (colour-ordered processes)
-  int* d_cstep = nullptr;    // MFMA colour form: k-step table, term table, colour fragments
-  uint32_t* d_cterm = nullptr;
-  void* d_cfrag = nullptr;
-  double* d_part = nullptr;  // integrate partials, grown on demand and reused
-  int64_t part_cap = 0;
-  std::vector<int8_t> hel;  // host copy of the current table
-};
 
 namespace {
 
@@ -370,7 +348,9 @@ heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
   return HEGET_OK;
 }
 
-KernelArgs base_args(heget_process_t p) {
+}  // namespace
+
+KernelArgs heget::detail::base_args(heget_process_t p) {
   KernelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.hel = p->d_hel;
@@ -386,6 +366,10 @@ KernelArgs base_args(heget_process_t p) {
   a.cfrag = p->d_cfrag;
   return a;
 }
+
+namespace {
+
+using heget::detail::base_args;
 
 void release(heget_process* p) {
   if (!p) return;
@@ -597,7 +581,7 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
   a.mom_stride = n;
   a.seed = seed;
   a.sqrt_s = sqrt_s;
-  a.weight_factor = phase_space_volume(sqrt_s, p->n_legs - 2) / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
+  a.weight_factor = heget::detail::weight_factor(p, sqrt_s);
   a.partials = d_part;
   heget_status rc = launch(p, a, st);
   double h[3] = {0, 0, 0};
@@ -609,17 +593,7 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
     if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
   }
   if (rc != HEGET_OK) return rc;
-  const double N = double(n);
-  out->sum_w = h[0];
-  out->sum_w2 = h[1];
-  out->n_generated = n;
-  out->n_accepted = int64_t(h[2] + 0.5);
-  out->sigma_gev2 = h[0] / N;
-  const double var = std::max(h[1] / N - out->sigma_gev2 * out->sigma_gev2, 0.0);
-  out->err_gev2 = std::sqrt(var / (N - 1.0));
-  const double hbarc2 = 0.3893793721e9;
-  out->sigma_pb = out->sigma_gev2 * hbarc2;
-  out->err_pb = out->err_gev2 * hbarc2;
+  heget::detail::fill_result(h, n, out);
   return HEGET_OK;
 }
 

@@ -1,0 +1,51 @@
+// Declarations shared by the library's translation units (not part of the C ABI).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "generated_common.hpp"
+#include "heget.h"
+
+// A created process: its compiled kernel and its resident device tables.
+struct heget_process {
+  const heget::GenEntry* entry = nullptr;
+  heget_precision prec = HEGET_FP64;
+  int n_legs = 0;
+  int n_hel = 0;
+  int cut_enabled = 0;
+  double cut_pt = 0, cut_dr = 0;
+  int n_a_n_b = 1, symmetry = 1;
+  double* d_cpl = nullptr;
+  heget::PropEntry* d_prop = nullptr;
+  int8_t* d_hel = nullptr;
+  int8_t* d_ord = nullptr;   // ordering table (colour-ordered processes)
+  int* d_cstep = nullptr;    // MFMA colour form: k-step table, term table, colour fragments
+  uint32_t* d_cterm = nullptr;
+  void* d_cfrag = nullptr;
+  double* d_part = nullptr;  // integrate partials, grown on demand and reused
+  int64_t part_cap = 0;
+  std::vector<int8_t> hel;   // host copy of the current table
+};
+
+namespace heget {
+namespace detail {
+
+// Records msg as the calling thread's last error and returns s.
+heget_status fail(heget_status s, const std::string& msg);
+
+// Kernel arguments with the process's resident tables filled in.
+KernelArgs base_args(heget_process_t p);
+
+// Massless n-body phase-space volume at sqrt_s (every RAMBO weight).
+double phase_space_volume(double sqrt_s, int n);
+
+// Per-event weight factor of heget_integrate: Phi_n / (2 s) x 1/4 x 1/(n_a n_b) x 1/S.
+double weight_factor(heget_process_t p, double sqrt_s);
+
+// heget_result from the reduced (sum w, sum w^2, accepted) of n generated events.
+void fill_result(const double h[3], int64_t n, heget_result* out);
+
+}  // namespace detail
+}  // namespace heget

@@ -11,6 +11,8 @@ struct PropEntry {
   double inum_r, inum_i;  // 1 / (mass^2 in the unitary-gauge numerator)
 };
 
+struct BatchTable;
+
 struct KernelArgs {
   int64_t n;                 // events in this launch
   const double* mom_in;      // SoA [n_legs][4][n] physical momenta, or null (generate)
@@ -33,6 +35,40 @@ struct KernelArgs {
   const int* cstep;          // [nks][2]: terms per flow in k-step s, offset of its term rows
   const uint32_t* cterm;     // [sum nterm][4]: (ordering | coefficient << 16) per lane group
   const void* cfrag;         // [nfo][nks][64] colour-matrix A fragments, double or float
+  const BatchTable* batch;   // fused launches of the serving engine, else null
+};
+
+// One request's share of a fused launch: virtual blocks [block_begin, next
+// segment's block_begin) evaluate the request's own blocks block_offset,
+// block_offset + 1, ... (256 events each), exactly as a launch of that request
+// alone would (same counters, same per-block partial slots).
+struct Segment {
+  int64_t block_begin;
+  int64_t block_offset;
+  int64_t n;               // the request's event count
+  uint64_t seed;           // the request's Philox key
+  double sqrt_s;
+  double weight_factor;
+  double* me2_out;         // [n] or null
+  double* partials;        // [ceil(n / 256)][3]
+};
+
+// Final reduction of a request whose last blocks are in this launch.
+struct ReduceJob {
+  const double* partials;
+  int64_t nblocks;
+};
+
+constexpr int kMaxSegments = 64;
+constexpr int kMaxJobs = 64;
+
+// Device-resident description of one fused launch, uploaded as a whole.
+struct BatchTable {
+  int64_t total_blocks;
+  int32_t n_seg, n_jobs;
+  Segment seg[kMaxSegments];   // ordered by block_begin, seg[0].block_begin = 0
+  ReduceJob job[kMaxJobs];
+  double result[kMaxJobs][3];  // sum w, sum w^2, accepted (written by the reduction)
 };
 
 }  // namespace heget
