@@ -88,12 +88,45 @@ def cpu_baseline(oracle, target_seconds=12.0):
             "sample": f"{n} events of the same workload (first {n} Philox counters), {dt:.1f} s"}
 
 
+SERVE_SEED = 0x48454749
+SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g", "ud_udhh_4b")   # the four configurations
+SERVE_WEIGHTS = (40, 30, 20, 10)
+SERVE_SQRT_S = (200.0, 1000.0, 1000.0, 2000.0)
+
+
+def serve_leg(n_requests, rate=200.0):
+    """Poisson request stream over the four configurations, served by the
+    engine in mixed precision, against one-at-a-time FP64 heget_integrate."""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes, serve
+    reqs = serve.poisson_mix(SERVE_SEED, n_requests, rate, SERVE_WEIGHTS, SERVE_SQRT_S)
+    mixed = [H.Process(processes.by_name(n), precision="mixed") for n in SERVE_PROCESSES]
+    fp64 = [H.Process(processes.by_name(n), precision="fp64") for n in SERVE_PROCESSES]
+    warm = [serve.Request(0.0, k, 4096, 1, SERVE_SQRT_S[k]) for k in range(4)]
+    srv = H.Server(mixed, arena_bytes=1 << 30, slots_per_process=2, max_batch_blocks=4096, max_chunk_blocks=1024)
+    serve.replay_engine(srv, warm)
+    serve.replay_unbatched(fp64, warm)
+    _, eng = serve.replay_engine(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    _, base = serve.replay_unbatched(fp64, reqs)
+    eng.update({"precision": "mixed", "launches": st["launches"], "segments": st["segments"],
+                "max_busy_slots": st["max_busy_slots"], "arena_high_water_bytes": st["arena_high_water"]})
+    base.update({"precision": "fp64", "kind": "unbatched: one heget_integrate at a time in arrival order"})
+    return {"workload": f"{n_requests} Poisson requests at {rate:g}/s over "
+                        f"{'/'.join(SERVE_PROCESSES)} in proportions {'/'.join(map(str, SERVE_WEIGHTS))}, "
+                        "n log-uniform in [2^10, 2^20), sqrt_s = nominal x 2^U(-1/2,1/2)",
+            "engine": eng, "baseline": base}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests in the serving replay (0: skip it)")
     ap.add_argument("--profile-leg", choices=["fp64", "mixed"], default=None,
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -171,6 +204,8 @@ def main():
                               "mixed_kernel_ms": kernmxf * 1e3},
         "sigma_pb": r64["sigma_pb"], "sigma_err_pb": r64["err_pb"],
     }
+    if args.serve_requests > 0:
+        line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:
         import oracle
         line["cpu_baseline"] = cpu_baseline(oracle)

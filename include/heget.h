@@ -191,6 +191,16 @@ heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, 
                         uint64_t counter_offset, double sqrt_s, double* me2_out, double* momenta_out,
                         void* stream);
 
+/* Phase-space generation alone: the momenta heget_eval would generate for
+ * (seed, counter_offset .. counter_offset + n - 1, sqrt_s), written to the
+ * device FP64 SoA momenta_out [n_legs][4][n] (the Philox -> RAMBO step of the
+ * integrand, Sec. 3; 32 bytes per leg per event, an HBM-bound kernel).
+ * Asynchronous on `stream`.  n = 0 is a no-op (momenta_out may then be NULL).
+ * Errors: HEGET_E_INVALID (null handle, null output with n > 0, n < 0, sqrt_s <= 0),
+ * HEGET_E_UNSUPPORTED (more than 10 final-state legs), HEGET_E_HIP. */
+heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_t counter_offset, double sqrt_s,
+                            double* momenta_out, void* stream);
+
 /* Monte Carlo cross section from n RAMBO events generated from `seed`
  * (counters 0 .. n-1): sigma = (1/N) sum_i w_i with w_i = Phi_n * pass_i * F_i
  * / (2 s 4 n_a n_b S), reduced on the device in a fixed order.  Synchronises

@@ -124,6 +124,17 @@ class Process:
                                    ptr(me2_out), ptr(momenta_out), self._stream(stream)))
         return (me2_out, momenta_out) if want_momenta else me2_out
 
+    def generate(self, n, seed=0, counter_offset=0, sqrt_s=None, momenta_out=None, stream=None):
+        """The momenta heget_eval generates (Philox -> RAMBO), as a float64
+        CUDA tensor [n_legs][4][n], without evaluating |M|^2."""
+        import torch
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        if momenta_out is None:
+            momenta_out = torch.empty((self.n_legs, 4, max(n, 0)), dtype=torch.float64, device="cuda")
+        check(self._lib.heget_generate(self._h, n, seed, counter_offset, float(sqrt_s),
+                                       ctypes.c_void_p(momenta_out.data_ptr()), self._stream(stream)))
+        return momenta_out
+
     def integrate(self, n, seed=0, sqrt_s=None, stream=None):
         sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
         r = _lib.heget_result()

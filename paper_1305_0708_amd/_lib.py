@@ -9,7 +9,7 @@ HEGET_OK, HEGET_E_INVALID, HEGET_E_IR, HEGET_E_OOM, HEGET_E_HIP, HEGET_E_UNSUPPO
 HEGET_FP64, HEGET_MIXED = 0, 1
 
 EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "heget_integrate",
-            "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error",
+            "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error", "heget_generate",
             "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
             "heget_server_destroy"]
 
@@ -98,6 +98,8 @@ def load(path=None):
     L.heget_process_destroy.restype = ctypes.c_int
     L.heget_eval.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp, vp]
     L.heget_eval.restype = ctypes.c_int
+    L.heget_generate.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp]
+    L.heget_generate.restype = ctypes.c_int
     L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.POINTER(heget_result), vp]
     L.heget_integrate.restype = ctypes.c_int

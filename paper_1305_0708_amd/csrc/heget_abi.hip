@@ -327,6 +327,24 @@ void heget::detail::fill_result(const double h[3], int64_t n, heget_result* out)
 
 namespace {
 
+// Philox -> RAMBO -> SoA momenta, the generation step of heget_eval alone.
+template <int NOUT>
+__global__ __launch_bounds__(256) void generate_momenta(KernelArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  heget::mom p[NOUT + 2];
+  const double h = 0.5 * a.sqrt_s;
+  p[0] = {h, 0.0, 0.0, h};
+  p[1] = {h, 0.0, 0.0, -h};
+  heget::rambo<NOUT>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);
+  heget::store_momenta<NOUT + 2>(a, i, p);
+}
+
+template <int NOUT>
+const void* generate_kernel() {
+  return reinterpret_cast<const void*>(&generate_momenta<NOUT>);
+}
+
 // Fixed-order reduction of one request's per-block partials (one block).
 __global__ __launch_bounds__(256) void reduce_partials(const double* partials, int64_t nblocks, double* out) {
   heget::reduce_triples(partials, nblocks, out);
@@ -555,6 +573,42 @@ heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, 
   a.me2_out = me2_out;
   a.mom_out = momenta_out;
   return launch(p, a, static_cast<hipStream_t>(stream));
+}
+
+heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_t counter_offset, double sqrt_s,
+                            double* momenta_out, void* stream) {
+  g_err.clear();
+  if (!p) return fail(HEGET_E_INVALID, "null handle");
+  if (n < 0) return fail(HEGET_E_INVALID, "n < 0");
+  if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
+  if (n > 0 && !momenta_out) return fail(HEGET_E_INVALID, "null momenta_out");
+  const void* fn = nullptr;
+  switch (p->n_legs - 2) {
+    case 2: fn = generate_kernel<2>(); break;
+    case 3: fn = generate_kernel<3>(); break;
+    case 4: fn = generate_kernel<4>(); break;
+    case 5: fn = generate_kernel<5>(); break;
+    case 6: fn = generate_kernel<6>(); break;
+    case 7: fn = generate_kernel<7>(); break;
+    case 8: fn = generate_kernel<8>(); break;
+    case 9: fn = generate_kernel<9>(); break;
+    case 10: fn = generate_kernel<10>(); break;
+    default: return fail(HEGET_E_UNSUPPORTED, "generation supports 2..10 final-state legs");
+  }
+  if (n == 0) return HEGET_OK;
+  const int64_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
+  KernelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.mom_stride = n;
+  a.seed = seed;
+  a.counter_offset = counter_offset;
+  a.sqrt_s = sqrt_s;
+  a.mom_out = momenta_out;
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(256), args, 0, static_cast<hipStream_t>(stream)));
+  return HEGET_OK;
 }
 
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,

@@ -275,3 +275,18 @@ def test_colour_bases_agree(torch, oracle):
         err = rel_err(a[nz], b[nz])
         print(f"{prec}: trace/MFMA vs DDM/VALU max rel diff {err.max():.3e}, median {np.median(err):.3e}")
         assert err.max() < tol
+
+
+@pytest.mark.parametrize("name", ["ee_mumu", "gg_ttbar_6f", "gg_4g"])
+def test_generate_alone_matches_eval_and_oracle(torch, oracle, name):
+    """heget_generate writes exactly the momenta heget_eval generates."""
+    _, nout, rs, _, seed, _ = CASES[name]
+    p = make(name)
+    n = 3 * 1024 + 37
+    mom = p.generate(n, seed=seed, counter_offset=11, sqrt_s=rs)
+    _, ref_dev = p.eval(n=n, seed=seed, counter_offset=11, sqrt_s=rs, want_momenta=True)
+    torch.cuda.synchronize()
+    assert torch.equal(mom, ref_dev)
+    ref = oracle.generate(seed, n, nout, rs, counter_offset=11)
+    assert np.max(np.abs(to_aos(mom) - ref)) < (1e-10 if nout == 2 else 1e-13) * rs
+    assert p.generate(0, seed=seed).numel() == 0
