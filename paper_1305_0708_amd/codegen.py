@@ -24,7 +24,7 @@ import os
 import sys
 from fractions import Fraction
 
-from . import ir
+from . import ir, nest
 from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
@@ -168,11 +168,19 @@ class Gen:
         w("")
         mf = p.uses_colour_mfma()
         nks, nfo = ((p.n_flows + 3) // 4, (p.n_flows + 15) // 16) if mf else (0, 0)
+        if self.ordered:
+            canon, n_canon = "nullptr", 0
+        else:
+            rows = ir.all_helicities(p.legs)
+            flat = ", ".join(str(h) for row in rows for h in row)
+            w(f"// the full helicity product in canonical order: tables equal to it run the loop nest")
+            w(f"static const int8_t hel_canon[] = {{{flat}}};")
+            canon, n_canon = "hel_canon", len(rows)
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
-          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>)}};')
+          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
@@ -191,15 +199,16 @@ class Gen:
             elif leg.kind == V:
                 w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
 
-    def _external(self, k, leg, name):
+    def _external(self, k, leg, name, hel=None):
+        hel = hel or f"hh[{k}]"
         if leg.kind == F:
             if leg.particle == P_ZERO:
                 fn = "ixxxxx0" if _flowing_in(leg) else "oxxxxx0"
-                return f"const wf<T> {name} = {fn}<T>(e{k}, hh[{k}], {leg.flow});"
-            return f"const wf<T> {name} = hh[{k}] > 0 ? e{k}p : e{k}m;"
+                return f"const wf<T> {name} = {fn}<T>(e{k}, {hel}, {leg.flow});"
+            return f"const wf<T> {name} = {hel} > 0 ? e{k}p : e{k}m;"
         if leg.kind == V:
             nsv = -1 if leg.incoming else 1
-            return f"const wf<T> {name} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), hh[{k}], {nsv});"
+            return f"const wf<T> {name} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), {hel}, {nsv});"
         return f"const cx<T> {name} = sxxxxx<T>();"
 
     def _current_momenta(self, w, ind, qname):
@@ -230,19 +239,57 @@ class Gen:
         self._current_momenta(w, "  ", lambda x: f"q{x}")
         self._ext_pre(w)
         w("  double me2 = 0.0;")
-        w("  if (pass) {")
+        w("  if (pass && a.hel_nest) {")
+        self._emit_nest(w)
+        w("  } else if (pass) {")
+        w("    // an arbitrary helicity table (filtered, reordered or gauge-test rows)")
         w("    for (int h = 0; h < a.n_hel; ++h) {")
         w(f"      const int8_t* hh = a.hel + h * {self.nl};")
         for k, leg in enumerate(p.legs):
             w("      " + self._external(k, leg, f"w{k}"))
         for c in p.calls:
             self._call(w, c, "      ")
-        for f, terms in enumerate(p.jamp):
-            expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in terms) or "mk<T>(T(0), T(0))"
-            w(f"      const cx<T> J{f} = {expr};")
+        self._jamps(w, "      ")
         self._colour(w, lambda f: f"J{f}")
         w("    }")
         w("  }")
+
+    def _jamps(self, w, ind):
+        for f, terms in enumerate(self.p.jamp):
+            expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in terms) or "mk<T>(T(0), T(0))"
+            w(f"{ind}const cx<T> J{f} = {expr};")
+
+    def _emit_nest(self, w):
+        """the full helicity product as one loop per leg (nest.plan's order);
+        each wavefunction and call sits in the innermost loop its legs need"""
+        p = self.p
+        pl = nest.plan(p)
+        ind = "    "
+        w(f"{ind}// helicity loop nest, outermost leg first: {pl.order}")
+        for lvl, L in enumerate(pl.order):
+            ch = pl.choices[L]
+            if len(ch) == 1:
+                hel = str(ch[0])
+            else:
+                w(f"{ind}#pragma unroll 1")
+                w(f"{ind}for (int c{L} = 0; c{L} < {len(ch)}; ++c{L}) {{")
+                ind += "  "
+                if ch == (-1, 1):
+                    hel = f"(2 * c{L} - 1)"
+                elif ch == (-1, 0, 1):
+                    hel = f"(c{L} - 1)"
+                else:
+                    raise NotImplementedError(f"helicity states {ch}")
+            w(ind + self._external(L, p.legs[L], f"w{L}", hel))
+            for c, cl in zip(p.calls, pl.call_level):
+                if cl == lvl:
+                    self._call(w, c, ind)
+        self._jamps(w, ind)
+        self._colour(w, lambda f: f"J{f}", ind)
+        for L in reversed(pl.order):
+            if len(pl.choices[L]) > 1:
+                ind = ind[:-2]
+                w(f"{ind}}}")
 
     # ------------------------------------------------------ ordering template
     def _emit_ordered(self, w):
@@ -419,23 +466,23 @@ class Gen:
             raise ValueError(op)
         w(lhs + rhs + ";")
 
-    def _colour(self, w, J):
+    def _colour(self, w, J, ind="      "):
         """me2 += Re(J^dagger C J) with the constant colour matrix C = num / den"""
         p = self.p
         den = p.colour_denominator()
         n = p.n_flows
-        w("      T cs = T(0);")
+        w(f"{ind}T cs = T(0);")
         for f in range(n):
-            w(f"      {{")
-            w(f"        const cx<T> jf = {J(f)};")
-            w(f"        T r = T({_c(Fraction(p.colour[f][f]) * den)}) * norm2(jf);")
+            w(f"{ind}{{")
+            w(f"{ind}  const cx<T> jf = {J(f)};")
+            w(f"{ind}  T r = T({_c(Fraction(p.colour[f][f]) * den)}) * norm2(jf);")
             for g in range(f + 1, n):
                 cfg = Fraction(p.colour[f][g]) * den
                 if cfg != 0:
-                    w(f"        {{ const cx<T> jg = {J(g)}; r += T({_c(2 * cfg)}) * (jf.r * jg.r + jf.i * jg.i); }}")
-            w("        cs += r;")
-            w("      }")
-        w(f"      me2 += double(cs) * {_c(Fraction(1, den))};")
+                    w(f"{ind}  {{ const cx<T> jg = {J(g)}; r += T({_c(2 * cfg)}) * (jf.r * jg.r + jf.i * jg.i); }}")
+            w(f"{ind}  cs += r;")
+            w(f"{ind}}}")
+        w(f"{ind}me2 += double(cs) * {_c(Fraction(1, den))};")
 
 
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")

@@ -21,6 +21,8 @@ struct GenEntry {
   int nks, nfo;               // its k-steps (ceil(n_flows / 4)) and output tiles (ceil(n_flows / 16))
   const void* batch_fp64;     // fused persistent variants reading KernelArgs::batch
   const void* batch_mixed;
+  const int8_t* hel_canon;    // full helicity product the kernel's loop nest sums, or null
+  int n_hel_canon;            // its rows (n_legs entries each)
 };
 
 // The launch arguments of one request's segment in a fused launch.

@@ -368,11 +368,17 @@ heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
 
 }  // namespace
 
+bool heget::detail::is_full_product(const GenEntry* e, const int8_t* table, int n_hel, int n_legs) {
+  return e->hel_canon && e->n_hel_canon == n_hel &&
+         std::memcmp(e->hel_canon, table, size_t(n_hel) * n_legs) == 0;
+}
+
 KernelArgs heget::detail::base_args(heget_process_t p) {
   KernelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.hel = p->d_hel;
   a.n_hel = p->n_hel;
+  a.hel_nest = p->hel_nest;
   a.cut_enabled = p->cut_enabled;
   a.cpl = p->d_cpl;
   a.prop = p->d_prop;
@@ -494,6 +500,7 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   p->n_a_n_b = ir->n_a_n_b;
   p->symmetry = ir->symmetry;
   p->hel.assign(ir->helicities, ir->helicities + size_t(ir->n_hel) * ir->n_legs);
+  p->hel_nest = heget::detail::is_full_product(entry, ir->helicities, ir->n_hel, ir->n_legs) ? 1 : 0;
   std::vector<double> cpl(size_t(ir->n_couplings) * 4);
   for (int k = 0; k < ir->n_couplings; ++k) coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
   PropEntry prop[HEGET_N_PARTICLES];
@@ -665,6 +672,7 @@ heget_status heget_filter_helicities(heget_process_t p, int64_t n_probe, uint64_
     KernelArgs a = base_args(p);
     a.hel = p->d_hel + size_t(h) * nl;
     a.n_hel = 1;
+    a.hel_nest = 0;
     a.n = n_probe;
     a.mom_stride = n_probe;
     a.seed = seed;
@@ -696,6 +704,7 @@ heget_status heget_filter_helicities(heget_process_t p, int64_t n_probe, uint64_
     return fail(HEGET_E_HIP, "helicity table upload failed");
   p->hel = kept;
   p->n_hel = nk;
+  p->hel_nest = heget::detail::is_full_product(p->entry, kept.data(), nk, nl) ? 1 : 0;
   *n_kept = nk;
   return HEGET_OK;
 }

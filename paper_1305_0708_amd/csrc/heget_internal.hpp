@@ -14,6 +14,7 @@ struct heget_process {
   heget_precision prec = HEGET_FP64;
   int n_legs = 0;
   int n_hel = 0;
+  int hel_nest = 0;          // the table is the kernel's full helicity product (loop nest)
   int cut_enabled = 0;
   double cut_pt = 0, cut_dr = 0;
   int n_a_n_b = 1, symmetry = 1;
@@ -34,6 +35,9 @@ namespace detail {
 
 // Records msg as the calling thread's last error and returns s.
 heget_status fail(heget_status s, const std::string& msg);
+
+// Whether a helicity table is the compiled kernel's full product in canonical order.
+bool is_full_product(const GenEntry* e, const int8_t* table, int n_hel, int n_legs);
 
 // Kernel arguments with the process's resident tables filled in.
 KernelArgs base_args(heget_process_t p);

@@ -24,6 +24,7 @@ struct KernelArgs {
   double* mom_out;           // SoA [n_legs][4][mom_stride] or null
   const int8_t* hel;         // [n_hel][n_legs]
   int32_t n_hel;
+  int32_t hel_nest;          // 1: the table is the full product; sum it as the kernel's loop nest
   int32_t cut_enabled;
   const double* cpl;         // 4 doubles per coupling: g0 (re, im), g1 (re, im)
   const PropEntry* prop;     // indexed by particle id
