@@ -84,8 +84,21 @@ def cpu_baseline(oracle, target_seconds=12.0):
     f = oracle.me2(oracle.GG_TT_6F, mom, oracle.params(), threads=cores)
     dt = time.perf_counter() - t0
     assert np.all(f > 0)
+    # the same oracle on one core, on a smaller sample (about 3 s)
+    n1 = int(min(max(n / dt / cores * 3.0, 64), n))
+    t0 = time.perf_counter()
+    oracle.me2(oracle.GG_TT_6F, mom[:n1], oracle.params(), threads=1)
+    dt1 = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": n / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} events of the same workload (first {n} Philox counters), {dt:.1f} s"}
+            "sample": f"{n} events of the same workload (first {n} Philox counters), {dt:.1f} s",
+            "value_1core": n1 / dt1, "sample_1core": f"first {n1} of those events, {dt1:.1f} s",
+            "cpu": cpu}
 
 
 SERVE_SEED = 0x48454749

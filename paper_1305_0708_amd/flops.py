@@ -98,9 +98,14 @@ def colour_mfma_flops_executed(proc):
 
 
 def per_event(proc, n_hel=None):
-    """flops of one event: helicity loop plus the per-event denominators"""
-    nh = len(proc.helicities) if n_hel is None else n_hel
+    """flops of one event: the helicity sum plus the per-event denominators.
+    With the full helicity product (n_hel None) a straight-line IR runs as the
+    helicity loop nest (nest.plan); a table of n_hel rows runs row by row."""
     n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS and c.op not in ("vadd", "vsub"))
+    if n_hel is None and not proc.orderings:
+        from . import nest
+        return nest.plan(proc).flops_per_event + n_cur * (7 + 8)
+    nh = len(proc.helicities) if n_hel is None else n_hel
     if proc.orderings:
         # per-ordering momenta and denominators are formed inside the helicity loop
         return nh * (per_helicity(proc) + len(proc.orderings) * n_cur * (7 + 8))
