@@ -281,9 +281,15 @@ class Gen:
                 else:
                     raise NotImplementedError(f"helicity states {ch}")
             w(ind + self._external(L, p.legs[L], f"w{L}", hel))
-            for c, cl in zip(p.calls, pl.call_level):
-                if cl == lvl:
+            for c, cl, bl in zip(p.calls, pl.call_level, pl.bra_level):
+                if cl == lvl and bl is not None:
+                    # FFV amplitude split as <fo| Vslash |fi>: the bra comes from an outer loop
+                    w(f"{ind}const cx<T> amp{c.out} = spinor_dot(bra{c.out}, w{c.ins[0]});")
+                elif cl == lvl:
                     self._call(w, c, ind)
+            for c, bl in zip(p.calls, pl.bra_level):
+                if bl == lvl:
+                    w(f"{ind}const wf<T> bra{c.out} = ffv_bra<T>(w{c.ins[1]}, w{c.ins[2]}, g{c.cpl}_0, g{c.cpl}_1);")
         self._jamps(w, ind)
         self._colour(w, lambda f: f"J{f}", ind)
         for L in reversed(pl.order):

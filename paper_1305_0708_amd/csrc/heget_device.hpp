@@ -399,6 +399,22 @@ __device__ __forceinline__ cx<T> iovxxx(const wf<T>& fi, const wf<T>& fo, const 
   return g0 * (fo.c[2] * a0 + fo.c[3] * a1) + g1 * (fo.c[0] * b0 + fo.c[1] * b1);
 }
 
+// The row spinor <fo| Vslash (g0 P_L + g1 P_R): iovxxx(fi, fo, V) = spinor_dot(ffv_bra(fo, V), fi).
+// Lets a loop nest form it once per (fo, V) and contract it with many fi.
+template <class T>
+__device__ __forceinline__ wf<T> ffv_bra(const wf<T>& fo, const wf<T>& vc, cx<T> g0, cx<T> g1) {
+  cx<T> u0, u1, l0, l1;
+  rsbV(vc.c, fo.c[2], fo.c[3], u0, u1);  // acts on the upper (left-handed) components of fi
+  rsV(vc.c, fo.c[0], fo.c[1], l0, l1);   // acts on the lower (right-handed) components of fi
+  return {{g0 * u0, g0 * u1, g1 * l0, g1 * l1}};
+}
+
+// row spinor times column spinor
+template <class T>
+__device__ __forceinline__ cx<T> spinor_dot(const wf<T>& b, const wf<T>& f) {
+  return b.c[0] * f.c[0] + b.c[1] * f.c[1] + b.c[2] * f.c[2] + b.c[3] * f.c[3];
+}
+
 // contravariant current v^mu = <fo| gamma^mu (g0 P_L + g1 P_R) |fi>
 template <class T>
 __device__ __forceinline__ wf<T> ffv_current(const wf<T>& fi, const wf<T>& fo, cx<T> g0, cx<T> g1) {

@@ -19,6 +19,8 @@ PROP_MASSIVE = DOT_CR + CMUL + 4 * (RMUL + CADD) + PROP_MASSLESS   # 60: unitary
 
 OP_FLOPS = {
     "iov": 2 * WEYL_C + 2 * (3 * CMUL + CADD) + CADD,           # 114
+    "ffv_bra": 2 * WEYL_C + 4 * CMUL,                           # 96: <fo| Vslash (g0 P_L + g1 P_R)
+    "spinor_dot": 4 * CMUL + 3 * CADD,                          # 30
     "ffv_current": 8 * CMUL + 4 * (2 * CMUL + 3 * CADD),        # 120
     "fvi": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
     "fvo": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
