@@ -11,15 +11,19 @@
 // register r of output tile fo: the final dot product is lane-local and only
 // the four lane groups are summed with two butterflies.
 //
-// Lane layout of v_mfma_{f64,f32}_16x16x4 (gfx950): A[i][k] in lane i + 16 k,
-// B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4.
+// Lane layouts on gfx950 (checked with an in-bounds probe): for both
+// v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32, A[i][k] is in lane i + 16 k
+// and B[k][j] in lane j + 16 k.  D[i][j] is in lane j + 16 (i % 4), register
+// i / 4 for f64, and in lane j + 16 (i / 4), register i % 4 for f32.
 //
 // Flow indices are those of the sorted order built by the library (flows
 // sorted by their number of flow-map terms, so that the four flows of one
 // k-step share one term count): k-step s, lane group g holds sorted flow
-// 4 s + g; output tile fo, row i holds sorted flow 16 fo + 4 (i % 4) + i / 4.
-// The A fragments (colour matrix, permuted and zero-padded) and the term
-// table are built on the host at process creation.
+// 4 s + g.  Lane group g, register r of output tile fo must then hold the
+// flow 16 fo + 4 r + g, so row i of tile fo is sorted flow 16 fo + i (f64)
+// or 16 fo + 4 (i % 4) + i / 4 (f32).  The A fragments (colour matrix,
+// permuted that way and zero-padded) and the term table are built on the
+// host at process creation.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

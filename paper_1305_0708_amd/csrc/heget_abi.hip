@@ -418,7 +418,7 @@ struct ColourTables {
   std::vector<double> cfrag;     // [nfo][nks][64]
 };
 
-heget_status colour_tables(const heget_process_ir* ir, const GenEntry* e, ColourTables& t) {
+heget_status colour_tables(const heget_process_ir* ir, const GenEntry* e, heget_precision prec, ColourTables& t) {
   const int nf = ir->n_flows, no = ir->n_orderings;
   if (no <= 0) return fail(HEGET_E_IR, "the MFMA colour form needs an ordering table");
   if (e->nks != (nf + 3) / 4 || e->nfo != (nf + 15) / 16)
@@ -457,12 +457,17 @@ heget_status colour_tables(const heget_process_ir* ir, const GenEntry* e, Colour
   auto cs = [&](int a, int b) {
     return (a < nf && b < nf) ? ir->colour_num[order[a] * nf + order[b]] / ir->colour_den : 0.0;
   };
+  // row i of output tile fo is the flow whose B operand the lane holding D[i][.] supplied at
+  // k-step 4 fo + (register of D[i][.]); the D layouts of the two MFMAs differ (colour_mfma.hpp)
+  auto out_flow = [&](int fo, int i) {
+    return prec == HEGET_FP64 ? 16 * fo + i : 16 * fo + 4 * (i % 4) + i / 4;
+  };
   t.cfrag.assign(size_t(nfo) * nks * 64, 0.0);
   for (int fo = 0; fo < nfo; ++fo)
     for (int s = 0; s < nks; ++s)
       for (int lane = 0; lane < 64; ++lane) {
         const int i = lane & 15, k = lane >> 4;
-        t.cfrag[(size_t(fo) * nks + s) * 64 + lane] = cs(16 * fo + 4 * (i % 4) + i / 4, 4 * s + k);
+        t.cfrag[(size_t(fo) * nks + s) * 64 + lane] = cs(out_flow(fo, i), 4 * s + k);
       }
   return HEGET_OK;
 }
@@ -529,7 +534,7 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   }
   if (entry->colour_mfma) {
     ColourTables t;
-    if (heget_status st = colour_tables(ir, entry, t)) {
+    if (heget_status st = colour_tables(ir, entry, prec, t)) {
       release(p);
       return st;
     }
