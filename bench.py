@@ -101,6 +101,29 @@ def cpu_baseline(oracle, target_seconds=12.0):
             "cpu": cpu}
 
 
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+
+
+def phase_space_leg(torch, proc, steps, warmup):
+    """heget_generate alone (Philox -> RAMBO -> SoA momenta), the HBM-bound
+    kernel of the path: 32 bytes per leg per event written."""
+    n = N_EVENTS
+    out = torch.empty((proc.n_legs, 4, n), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        proc.generate(n, seed=SEED, sqrt_s=SQRT_S, momenta_out=out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(steps):
+        proc.generate(n, seed=SEED + k, sqrt_s=SQRT_S, momenta_out=out)
+    ev1.record(stream)
+    ev1.synchronize()
+    t = ev0.elapsed_time(ev1) / 1e3 / steps
+    nbytes = n * proc.n_legs * 4 * 8
+    return {"kernel": "generate_momenta<6>", "events": n, "bytes_written": nbytes, "kernel_ms": t * 1e3,
+            "achieved_gbs": nbytes / t / 1e9, "peak_gbs": HBM_PEAK_GBS, "frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
+
+
 SERVE_SEED = 0x48454749
 SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g", "ud_udhh_4b")   # the four configurations
 SERVE_WEIGHTS = (40, 30, 20, 10)
@@ -217,6 +240,7 @@ def main():
                               "mixed_kernel_ms": kernmxf * 1e3},
         "sigma_pb": r64["sigma_pb"], "sigma_err_pb": r64["err_pb"],
     }
+    line["phase_space"] = phase_space_leg(torch, fp64, args.steps, args.warmup)
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -260,42 +260,77 @@ class Gen:
             w(f"{ind}const cx<T> J{f} = {expr};")
 
     def _emit_nest(self, w):
-        """the full helicity product as one loop per leg (nest.plan's order);
-        each wavefunction and call sits in the innermost loop its legs need"""
+        """the full helicity product as one loop per leg (nest.schedule): each
+        wavefunction, call, bra, amplitude core and jamp sits in the
+        innermost loop its inputs need"""
         p = self.p
-        pl = nest.plan(p)
+        sc = nest.schedule(p)
+        by_level = {}
+        for it in sc.items:
+            by_level.setdefault(it.level, []).append(it)
         ind = "    "
-        w(f"{ind}// helicity loop nest, outermost leg first: {pl.order}")
-        for lvl, L in enumerate(pl.order):
-            ch = pl.choices[L]
+        w(f"{ind}// helicity loop nest, outermost leg first: {sc.order}")
+        for it in by_level.get(-1, []):
+            self._nest_item(w, it, ind)
+        for lvl, L in enumerate(sc.order):
+            ch = sc.choices[L]
             if len(ch) == 1:
-                hel = str(ch[0])
+                w(f"{ind}const int hh{L} = {ch[0]};")
             else:
                 w(f"{ind}#pragma unroll 1")
                 w(f"{ind}for (int c{L} = 0; c{L} < {len(ch)}; ++c{L}) {{")
                 ind += "  "
                 if ch == (-1, 1):
-                    hel = f"(2 * c{L} - 1)"
+                    w(f"{ind}const int hh{L} = 2 * c{L} - 1;")
                 elif ch == (-1, 0, 1):
-                    hel = f"(c{L} - 1)"
+                    w(f"{ind}const int hh{L} = c{L} - 1;")
                 else:
                     raise NotImplementedError(f"helicity states {ch}")
-            w(ind + self._external(L, p.legs[L], f"w{L}", hel))
-            for c, cl, bl in zip(p.calls, pl.call_level, pl.bra_level):
-                if cl == lvl and bl is not None:
-                    # FFV amplitude split as <fo| Vslash |fi>: the bra comes from an outer loop
-                    w(f"{ind}const cx<T> amp{c.out} = spinor_dot(bra{c.out}, w{c.ins[0]});")
-                elif cl == lvl:
-                    self._call(w, c, ind)
-            for c, bl in zip(p.calls, pl.bra_level):
-                if bl == lvl:
-                    w(f"{ind}const wf<T> bra{c.out} = ffv_bra<T>(w{c.ins[1]}, w{c.ins[2]}, g{c.cpl}_0, g{c.cpl}_1);")
-        self._jamps(w, ind)
+            for it in by_level.get(lvl, []):
+                self._nest_item(w, it, ind)
         self._colour(w, lambda f: f"J{f}", ind)
-        for L in reversed(pl.order):
-            if len(pl.choices[L]) > 1:
+        for L in reversed(sc.order):
+            if len(sc.choices[L]) > 1:
                 ind = ind[:-2]
                 w(f"{ind}}}")
+
+    @staticmethod
+    def _nest_arg(a):
+        if a is nest.ONE:
+            return "mk<T>(T(1), T(0))"
+        return f"w{a[1]}" if a[0] == "w" else a[1]
+
+    def _nest_item(self, w, it, ind):
+        p = self.p
+        if it.kind == "ext":
+            (L,) = it.data
+            w(ind + self._external(L, p.legs[L], f"w{L}", f"hh{L}"))
+        elif it.kind == "call":
+            k, args = it.data
+            self._call(w, p.calls[k], ind, args=[self._nest_arg(a) for a in args])
+        elif it.kind == "mat":
+            name, x, facs = it.data
+            prod = " * ".join(f"w{s}" for s in facs)
+            w(f"{ind}const wf<T> {name} = wscale<T>({prod}, w{x});")
+        elif it.kind == "bra":
+            k, fo, vc = it.data
+            c = p.calls[k]
+            w(f"{ind}const wf<T> bra{c.out} = ffv_bra<T>({self._nest_arg(fo)}, {self._nest_arg(vc)}, "
+              f"g{c.cpl}_0, g{c.cpl}_1);")
+        elif it.kind == "dot":
+            k, fi = it.data
+            c = p.calls[k]
+            w(f"{ind}const cx<T> amp{c.out} = spinor_dot(bra{c.out}, {self._nest_arg(fi)});")
+        elif it.kind == "ksum":
+            f, g, members = it.data
+            expr = " + ".join(_coef_expr(cc, f"amp{a}") for a, cc in members)
+            w(f"{ind}const cx<T> K{f}_{g} = {expr};")
+        elif it.kind == "jamp":
+            f, parts = it.data
+            terms = [(" * ".join([f"w{s}" for s in facs] + [f"K{f}_{g}"])) for g, facs in parts]
+            w(f"{ind}const cx<T> J{f} = {' + '.join(terms) or 'mk<T>(T(0), T(0))'};")
+        else:
+            raise ValueError(it.kind)
 
     # ------------------------------------------------------ ordering template
     def _emit_ordered(self, w):
@@ -399,7 +434,7 @@ class Gen:
         w("  }")
 
     # ------------------------------------------------------------------ calls
-    def _call(self, w, c, ind):
+    def _call(self, w, c, ind, args=None):
         op, ins, o = c.op, c.ins, c.out
         g0, g1 = f"g{c.cpl}_0", f"g{c.cpl}_1"
         gr = f"g{c.cpl}_0.r"
@@ -407,7 +442,7 @@ class Gen:
         mass = f"T(pe{pid}.m)"
         inum = f"mk<T>(T(pe{pid}.inum_r), T(pe{pid}.inum_i))"
         massive = "true" if pid in MASSIVE_VECTORS else "false"
-        a = [f"w{x}" for x in ins]
+        a = args if args is not None else [f"w{x}" for x in ins]
         Q = lambda x: f"Qs{self.sname(self.subset[x])}"
         if op in AMP_OPS:
             lhs = f"{ind}const cx<T> amp{o} = "

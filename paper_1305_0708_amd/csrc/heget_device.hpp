@@ -88,6 +88,11 @@ __device__ __forceinline__ wf<T> cvtw(const wf<S>& a) {
 }
 
 template <class T>
+__device__ __forceinline__ wf<T> wscale(cx<T> s, const wf<T>& a) {
+  return {{s * a.c[0], s * a.c[1], s * a.c[2], s * a.c[3]}};
+}
+
+template <class T>
 __device__ __forceinline__ wf<T> vadd(const wf<T>& a, const wf<T>& b) {
   return {{a.c[0] + b.c[0], a.c[1] + b.c[1], a.c[2] + b.c[2], a.c[3] + b.c[3]}};
 }

@@ -106,7 +106,7 @@ def per_event(proc, n_hel=None):
     n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS and c.op not in ("vadd", "vsub"))
     if n_hel is None and not proc.orderings:
         from . import nest
-        return nest.plan(proc).flops_per_event + n_cur * (7 + 8)
+        return nest.schedule(proc).flops_per_event + n_cur * (7 + 8)
     nh = len(proc.helicities) if n_hel is None else n_hel
     if proc.orderings:
         # per-ordering momenta and denominators are formed inside the helicity loop

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 from typing import Dict, List, Tuple
 
 from . import flops
-from .ir import AMP_OPS, F, V, S, P_ZERO
+from .ir import AMP_OPS, OUT_KIND, F, V, S, P_ZERO
 
 
 @dataclass
@@ -119,3 +119,112 @@ def plan(proc):
             rest.remove(L)
     pos, call_level, bra_level = _levels(order, deps, bdeps)
     return Plan(order, choices, call_level, {L: pos[L] for L in range(nl)}, _cost(order, *args), bra_level)
+
+
+# ------------------------------------------------------------------ schedule
+ONE = None   # an argument slot replaced by the scalar 1 (its value deferred as a factor)
+
+
+@dataclass
+class Item:
+    kind: str          # "ext", "call", "mat", "bra", "dot", "ksum", "jamp"
+    level: int         # loop level (-1: before the loops)
+    data: tuple
+    flops: int
+
+
+@dataclass
+class Schedule:
+    order: List[int]
+    choices: List[Tuple[int, ...]]
+    items: List[Item]          # in dependency order
+    flops_per_event: int       # model flops of the loop nest, per event
+
+
+def schedule(proc):
+    """What the loop nest evaluates where.
+
+    Beyond placing each call in the innermost loop of its legs (plan):
+      * a scalar input sitting in a deeper loop than the call's other inputs is
+        deferred: the call runs with 1 in its place (every vertex and current
+        is linear in each wavefunction input) and the scalar becomes a factor
+        of the result, carried to the amplitudes;
+      * an FFV amplitude whose |fi> sits deeper than <fo| and V is split into
+        a bra formed in the outer loop and a spinor product (plan);
+      * each jamp is sum_groups (product of the group's deferred factors) x
+        (sum of the group's amplitude cores), the inner sums formed in the
+        loop of their amplitudes.
+    Sums (vadd / vsub) take their inputs with the factors multiplied in."""
+    pl = plan(proc)
+    nl = proc.n_legs
+    pos = {L: i for i, L in enumerate(pl.order)}
+    kind = {k: leg.kind for k, leg in enumerate(proc.legs)}
+    clev = {k: pos[k] for k in range(nl)}
+    fac = {k: () for k in range(nl)}          # ((slot, level), ...) deferred scalar factors
+    items = [Item("ext", pos[L], (L,), _ext_flops(proc.legs[L])) for L in pl.order]
+    amp_fac, amp_lev = {}, {}
+    for k, c in enumerate(proc.calls):
+        ins = list(c.ins)
+        args, lv, f = [], -1, ()
+        if c.op in ("vadd", "vsub"):
+            for j, x in enumerate(ins):
+                if fac[x]:
+                    flv = max([clev[x]] + [l for _, l in fac[x]])
+                    name = f"m{k}_{j}"
+                    items.append(Item("mat", flv, (name, x, tuple(s for s, _ in fac[x])),
+                                      len(fac[x]) * 4 * flops.CMUL))
+                    args.append(("m", name))
+                    lv = max(lv, flv)
+                else:
+                    args.append(("w", x))
+                    lv = max(lv, clev[x])
+        else:
+            for x in ins:
+                f += fac[x]
+            scal = [x for x in ins if kind[x] == S]
+            other = [clev[x] for x in ins if kind[x] != S]
+            # an all-scalar call keeps its outermost scalar(s) as arguments
+            keep_lev = max(other) if other else min(clev[x] for x in scal)
+            for x in ins:
+                if kind[x] == S and clev[x] > keep_lev:
+                    f += ((x, clev[x]),)
+                    args.append(ONE)
+                else:
+                    args.append(("w", x))
+                    lv = max(lv, clev[x])
+        if c.op in AMP_OPS:
+            fi_lev = clev[ins[0]] if c.op == "iov" else None
+            if c.op == "iov" and args[0] is not ONE and max(clev[ins[1]], clev[ins[2]]) < fi_lev:
+                blev = max(clev[ins[1]], clev[ins[2]])
+                items.append(Item("bra", blev, (k, args[1], args[2]), flops.OP_FLOPS["ffv_bra"]))
+                items.append(Item("dot", fi_lev, (k, args[0]), flops.OP_FLOPS["spinor_dot"]))
+                amp_lev[c.out] = fi_lev
+            else:
+                items.append(Item("call", lv, (k, tuple(args)), flops.call_flops(c)))
+                amp_lev[c.out] = lv
+            amp_fac[c.out] = tuple(sorted(f))
+        else:
+            items.append(Item("call", lv, (k, tuple(args)), flops.call_flops(c)))
+            clev[c.out] = lv
+            fac[c.out] = f
+            kind[c.out] = OUT_KIND[c.op]
+    inner = len(pl.order) - 1
+    for fl, terms in enumerate(proc.jamp):
+        groups = {}
+        for a, coef in terms:
+            groups.setdefault(amp_fac[a], []).append((a, coef))
+        parts = []
+        for gi, (fk, members) in enumerate(sorted(groups.items())):
+            klev = max(amp_lev[a] for a, _ in members)
+            items.append(Item("ksum", klev, (fl, gi, tuple(members)), flops.CADD * max(len(members) - 1, 0)))
+            parts.append((gi, tuple(s for s, _ in fk)))
+        nmul = sum(len(fs) for _, fs in parts)
+        items.append(Item("jamp", inner, (fl, tuple(parts)), nmul * flops.CMUL + flops.CADD * max(len(parts) - 1, 0)))
+    mult, m = {-1: 1}, 1
+    for i, L in enumerate(pl.order):
+        m *= len(pl.choices[L])
+        mult[i] = m
+    nf = proc.n_flows
+    colour = nf * 4 + (nf * (nf - 1) // 2) * 4 + 2
+    total = sum(it.flops * mult[it.level] for it in items) + colour * mult[inner]
+    return Schedule(pl.order, pl.choices, items, total)
