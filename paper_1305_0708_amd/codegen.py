@@ -56,6 +56,7 @@ def _flowing_in(leg):
 class Gen:
     def __init__(self, proc: ir.Process):
         self.p = proc
+        self._scope, self._opaque = None, set()
         self.nl = proc.n_legs
         self.nout = proc.n_legs - 2
         self.ordered = proc.orderings is not None
@@ -135,6 +136,10 @@ class Gen:
         for k, leg in enumerate(p.legs):
             w(f"  const mom q{k} = {'p[%d]' % k if leg.incoming else '-p[%d]' % k};")
         if self.ordered:
+            w(f"  // the event's momenta in LDS: read per ordering and loop, not held in registers")
+            w(f"  __shared__ mom pm[{self.nl}][256];")
+            w("#pragma unroll")
+            w(f"  for (int k = 0; k < {self.nl}; ++k) pm[k][threadIdx.x] = p[k];")
             self._emit_ordered(w)
         else:
             self._emit_straight(w)
@@ -142,11 +147,23 @@ class Gen:
         w("  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor : 0.0, pass);")
         w("}")
         w("")
-        w("// one launch: block b evaluates events 256 b ... 256 b + 255")
-        w("template <class T>")
-        w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
-        w(f"  body_{p.name}<T>(a, blockIdx.x);")
-        w("}")
+        if self.ordered:
+            w("// one launch: a persistent grid (one workspace slot per block) walks the")
+            w("// 256-event blocks of the launch")
+            w("template <class T>")
+            w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
+            w("  const int64_t nb = (a.n + 255) / 256;")
+            w("  for (int64_t vb = blockIdx.x; vb < nb; vb += gridDim.x) {")
+            w(f"    body_{p.name}<T>(a, vb);")
+            w("    __syncthreads();")
+            w("  }")
+            w("}")
+        else:
+            w("// one launch: block b evaluates events 256 b ... 256 b + 255")
+            w("template <class T>")
+            w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
+            w(f"  body_{p.name}<T>(a, blockIdx.x);")
+            w("}")
         w("")
         w("// fused launch of several requests (serving engine): a persistent grid")
         w("// walks the virtual blocks of the batch table")
@@ -168,19 +185,17 @@ class Gen:
         w("")
         mf = p.uses_colour_mfma()
         nks, nfo = ((p.n_flows + 3) // 4, (p.n_flows + 15) // 16) if mf else (0, 0)
-        if self.ordered:
-            canon, n_canon = "nullptr", 0
-        else:
-            rows = ir.all_helicities(p.legs)
-            flat = ", ".join(str(h) for row in rows for h in row)
-            w(f"// the full helicity product in canonical order: tables equal to it run the loop nest")
-            w(f"static const int8_t hel_canon[] = {{{flat}}};")
-            canon, n_canon = "hel_canon", len(rows)
+        rows = ir.all_helicities(p.legs)
+        flat = ", ".join(str(h) for row in rows for h in row)
+        w(f"// the full helicity product in canonical order: tables equal to it run the loop nest")
+        w(f"static const int8_t hel_canon[] = {{{flat}}};")
+        canon, n_canon = "hel_canon", len(rows)
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
-          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}}};')
+          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
+          f'{int(self.ordered)}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
@@ -334,104 +349,245 @@ class Gen:
 
     # ------------------------------------------------------ ordering template
     def _emit_ordered(self, w):
+        """Ordering templates, two phases per block of 256 events:
+        1. for every ordering, the helicity sum's amplitudes A_o(h) of the
+           lane's event (a loop nest over the positions' helicities, or the
+           table row by row) go to the block's workspace slot [o][h][256];
+        2. for every helicity, the colour form over the orderings' amplitudes
+           (read back from the workspace; on MFMA through LDS for large bases)."""
         p = self.p
         nl, no = self.nl, len(p.orderings)
         if any(leg.kind == F for leg in p.legs):
             raise NotImplementedError("ordering templates support vector and scalar legs")
         mf = p.uses_colour_mfma()
-        w(f"  __shared__ cx<T> jl[{no}][256];")
+        w("  // this block's workspace slot: A[o][h][256] of its events")
+        w("  cx<T>* const work = static_cast<cx<T>*>(a.work) + size_t(blockIdx.x) * size_t(a.work_stride);")
+        w("  const int nh = a.n_hel;")
+        w("  if (pass) {")
+        w("#pragma unroll 1")
+        w(f"    for (int o = 0; o < {no}; ++o) {{")
+        w(f"      const int8_t* ord = a.ord + o * {nl};")
+        ind = "      "
+        self._bind_positions(w, ind)
+        w(f"{ind}if (a.hel_nest) {{")
+        self._emit_template_nest(w, ind + "  ")
+        w(f"{ind}}} else {{")
+        w(f"{ind}  for (int h = 0; h < nh; ++h) {{")
+        w(f"{ind}    const int8_t* hh = a.hel + h * {nl};")
+        done = set()
+        self._scope, self._opaque = "h", set()
+        self._w, self._ind = w, ind + "    "
+        for k in range(nl):
+            w(f"{ind}    const int hp{k} = hh[lk{k}];")
+            w(f"{ind}    " + self._position_external(k))
+        for c in p.calls:
+            self._lazy_kinematics(w, ind + "    ", c, done)
+            self._call(w, c, ind + "    ")
+        self._scope = None
+        expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in p.jamp[0])
+        w(f"{ind}    work[(size_t(o) * nh + h) * 256 + threadIdx.x] = {expr};")
+        w(f"{ind}  }}")
+        w(f"{ind}}}")
+        w("    }")
+        w("  }")
         w("  double me2 = 0.0;")
         if mf:
-            # the MFMA colour form needs every lane of the wavefront: run the
-            # chain wave-uniformly and stage zero amplitudes for failed lanes
-            w("  if (__any(pass)) {")
-        else:
-            w("  if (pass) {")
-        w("    for (int h = 0; h < a.n_hel; ++h) {")
-        w(f"      const int8_t* hh = a.hel + h * {nl};")
-        w("#pragma unroll 1")
-        w(f"      for (int o = 0; o < {no}; ++o) {{")
-        w(f"        const int8_t* ord = a.ord + o * {nl};")
-        # bind each position to its external leg: momentum, helicity, wavefunction
-        for k in range(nl):
-            cand = sorted({o[k] for o in p.orderings})
-            L0 = cand[0]
-            if len(cand) == 1:
-                w(f"        const mom pp{k} = p[{L0}];")
-                w(f"        const mom qp{k} = {'pp%d' % k if p.legs[L0].incoming else '-pp%d' % k};")
-                w(f"        const int hp{k} = hh[{L0}];")
-            else:
-                w(f"        mom pp{k} = p[{L0}];")
-                w(f"        double sg{k} = {'1.0' if p.legs[L0].incoming else '-1.0'};")
-                w(f"        switch (ord[{k}]) {{")
-                for L in cand[1:]:
-                    w(f"          case {L}: pp{k} = p[{L}]; sg{k} = {'1.0' if p.legs[L].incoming else '-1.0'}; break;")
-                w("          default: break;")
-                w("        }")
-                w(f"        const mom qp{k} = {{sg{k} * pp{k}.e, sg{k} * pp{k}.x, sg{k} * pp{k}.y, sg{k} * pp{k}.z}};")
-                w(f"        const int hp{k} = hh[ord[{k}]];")
-            legs = [p.legs[L] for L in cand]
-            kinds = {l.kind for l in legs}
-            parts = {l.particle for l in legs}
-            assert len(kinds) == 1 and len(parts) == 1, "a position must hold one kind of particle"
-            leg = legs[0]
-            if leg.kind == V:
-                inc = {l.incoming for l in legs}
-                if len(inc) == 1:
-                    nsv = "-1" if leg.incoming else "1"
-                else:
-                    w(f"        int nsv{k} = 1;")
-                    w(f"        switch (ord[{k}]) {{")
-                    for L in cand:
-                        if p.legs[L].incoming:
-                            w(f"          case {L}: nsv{k} = -1; break;")
-                    w("          default: break;")
-                    w("        }")
-                    nsv = f"nsv{k}"
-                w(f"        const wf<T> w{k} = vxxxxx<T>(tv<T>(pp{k}), T(pe{leg.particle}.m), hp{k}, {nsv});")
-            else:
-                w(f"        const cx<T> w{k} = sxxxxx<T>();")
-            if (k,) in self.need_q:
-                w(f"        const vec<T> Qs{k} = tv<T>(qp{k});")
-        # each subset momentum and denominator right before its first use
-        done_q, done_d = set(), set()
-        for c in p.calls:
-            subs = [self.subset[x] for x in c.ins if x >= nl]
-            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
-                subs.append(self.subset[c.out])
-            for sub in subs:
-                n = self.sname(sub)
-                if sub not in done_q:
-                    done_q.add(sub)
-                    w(f"        const mom qs{n} = {' + '.join(f'qp{x}' for x in sub)};")
-                    if sub in self.need_q:
-                        w(f"        const vec<T> Qs{n} = tv<T>(qs{n});")
-            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
-                sub, pid = self.subset[c.out], c.prop
-                n = self.sname(sub)
-                if (sub, pid) not in done_d:
-                    done_d.add((sub, pid))
-                    w(f"        const cx<T> d{n}_{pid} = cvt<T>(inv_denominator(qs{n}, "
-                      f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
-            self._call(w, c, "        ")
-        expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in p.jamp[0])
-        if mf:
-            w(f"        const cx<T> jo = {expr};")
-            w("        jl[o][threadIdx.x] = pass ? jo : cx<T>{T(0), T(0)};")
-            w("      }")
             nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
+            w(f"  __shared__ cx<T> jl[{no}][256];")
+            w("  // the MFMA colour form needs every lane of the wavefront: failed lanes take part with zeros")
+            w("  if (__any(pass)) {")
+            w("    for (int h = 0; h < nh; ++h) {")
+            w(f"      for (int o = 0; o < {no}; ++o)")
+            w("        jl[o][threadIdx.x] = pass ? work[(size_t(o) * nh + h) * 256 + threadIdx.x] : cx<T>{T(0), T(0)};")
             w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
             w("      __builtin_amdgcn_wave_barrier();")
             w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
             w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}>(&jl[0][0], a.cstep, a.cterm, "
               f"static_cast<const T*>(a.cfrag)));")
             w("      __builtin_amdgcn_wave_barrier();")
+            w("    }")
+            w("  }")
         else:
-            w(f"        jl[o][threadIdx.x] = {expr};")
-            w("      }")
-            self._colour(w, lambda f: f"jl[{f}][threadIdx.x]")
-        w("    }")
-        w("  }")
+            w("  if (pass) {")
+            w("    for (int h = 0; h < nh; ++h) {")
+            for o in range(no):
+                w(f"      const cx<T> A{o} = work[(size_t({o}) * nh + h) * 256 + threadIdx.x];")
+            self._colour(w, lambda f: f"A{f}")
+            w("    }")
+            w("  }")
+
+    def _bind_positions(self, w, ind):
+        """bind every position to the ordering's leg (uniform over the wave):
+        leg index, flow sign and vector sign.  Momenta are read from the LDS
+        copy where they are used."""
+        p = self.p
+        nl = self.nl
+        self._pos_nsv, self._pos_sign = {}, {}
+        for k in range(nl):
+            cand = sorted({o[k] for o in p.orderings})
+            L0 = cand[0]
+            w(f"{ind}const int lk{k} = {L0 if len(cand) == 1 else f'ord[{k}]'};")
+            signs = {p.legs[L].incoming for L in cand}
+            if len(signs) == 1:
+                self._pos_sign[k] = "+" if p.legs[L0].incoming else "-"
+            else:
+                w(f"{ind}const double sg{k} = lk{k} < 2 ? 1.0 : -1.0;")
+                self._pos_sign[k] = f"sg{k}"
+            legs = [p.legs[L] for L in cand]
+            assert len({l.kind for l in legs}) == 1 and len({l.particle for l in legs}) == 1, \
+                "a position must hold one kind of particle"
+            if legs[0].kind == V:
+                if len(signs) == 1:
+                    self._pos_nsv[k] = "-1" if legs[0].incoming else "1"
+                else:
+                    w(f"{ind}const int nsv{k} = lk{k} < 2 ? -1 : 1;")
+                    self._pos_nsv[k] = f"nsv{k}"
+
+    def _pmom(self, k, w, ind):
+        """physical momentum of position k in the current loop scope (an LDS
+        read behind an opaque leg index, so that it is not hoisted)"""
+        key = (k, self._scope)
+        if key not in self._opaque:
+            self._opaque.add(key)
+            w(f"{ind}const mom pl{k}_{self._scope} = pm[opaque_int(lk{k})][threadIdx.x];")
+        return f"pl{k}_{self._scope}"
+
+    def _qterm(self, k, w, ind):
+        """momentum of position k flowing into the diagram"""
+        name = self._pmom(k, w, ind)
+        sg = self._pos_sign[k]
+        if sg == "+":
+            return name
+        if sg == "-":
+            return f"-{name}"
+        return f"mom{{{sg} * {name}.e, {sg} * {name}.x, {sg} * {name}.y, {sg} * {name}.z}}"
+
+    def _lazy_kinematics(self, w, ind, c, done):
+        """the momenta (FP64, and as T where the call uses them) and the
+        propagator denominator call c needs, each emitted once in scope"""
+        subs = [self.subset[x] for x in c.ins]
+        if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+            subs.append(self.subset[c.out])
+        for sub in subs:
+            n = self.sname(sub)
+            if sub in self.need_q and f"Qs{n}" not in done:
+                if len(sub) == 1:
+                    t = self._qterm(sub[0], w, ind)
+                    w(f"{ind}const vec<T> Qs{n} = tv<T>({t});")
+                else:
+                    if f"qs{n}" not in done:
+                        done.add(f"qs{n}")
+                        t = [self._qterm(x, w, ind) for x in sub]
+                        w(f"{ind}const mom qs{n} = {' + '.join(t)};")
+                    w(f"{ind}const vec<T> Qs{n} = tv<T>(qs{n});")
+                done.add(f"Qs{n}")
+        if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+            sub, pid = self.subset[c.out], c.prop
+            n = self.sname(sub)
+            if f"d{n}_{pid}" not in done:
+                if f"qs{n}" not in done:
+                    done.add(f"qs{n}")
+                    t = [self._qterm(x, w, ind) for x in sub]
+                    w(f"{ind}const mom qs{n} = {' + '.join(t)};")
+                w(f"{ind}const cx<T> d{n}_{pid} = cvt<T>(inv_denominator(qs{n}, "
+                  f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
+                done.add(f"d{n}_{pid}")
+
+    def _position_external(self, k):
+        p = self.p
+        leg = p.legs[p.orderings[0][k]]
+        if leg.kind == V:
+            return (f"const wf<T> w{k} = vxxxxx<T>(tv<T>({self._pmom(k, self._w, self._ind)}), T(pe{leg.particle}.m), "
+                    f"hp{k}, {self._pos_nsv[k]});")
+        return f"const cx<T> w{k} = sxxxxx<T>();"
+
+    def _emit_template_nest(self, w, ind):
+        """one ordering's helicity sum as a loop nest over the positions
+        (nest.template_schedule); the row of the workspace is the helicity
+        combination's index in the canonical table of the legs"""
+        p = self.p
+        nl = self.nl
+        sc = nest.template_schedule(p)
+        by_level = {}
+        for it in sc.items:
+            by_level.setdefault(it.level, []).append(it)
+        # the running sum of the vertex vectors lives in the loop of the last one
+        rs = next(it for it in sc.items if it.kind == "rsum")
+        self._rt_level = rs.level
+        outer = [(a, cf) for a, cf in rs.data if self._r_level(sc, a) < rs.level]
+        lst = by_level[rs.level]
+        first = next(i for i, it in enumerate(lst) if it.kind in ("rvec", "rsum"))
+        lst.insert(first, nest.Item("rstart", rs.level, tuple(outer), 0))
+        by_level[rs.level] = [it for it in lst if it.kind != "rsum"]
+        w(f"{ind}// helicity loop nest over positions, outermost first: {sc.order}")
+        prev = "0"
+        self._done = set()
+        self._opaque = set()
+        for lvl, k in enumerate(sc.order):
+            ch = sc.choices[k]
+            if ch != (-1, 1):
+                raise NotImplementedError("template nests need two-state positions")
+            w(f"{ind}#pragma unroll 1")
+            w(f"{ind}for (int c{k} = 0; c{k} < 2; ++c{k}) {{")
+            ind += "  "
+            w(f"{ind}const int hp{k} = 2 * c{k} - 1;")
+            w(f"{ind}const int r{lvl} = {prev} + (c{k} << ({nl - 1} - lk{k}));")
+            prev = f"r{lvl}"
+            self._scope = lvl
+            for it in by_level.get(lvl, []):
+                self._template_item(w, it, ind, prev)
+        for _ in sc.order:
+            ind = ind[:-2]
+            w(f"{ind}}}")
+        self._scope = None
+
+    def _r_level(self, sc, amp):
+        for it in sc.items:
+            if it.kind == "rvec" and self.p.calls[it.data[0]].out == amp:
+                return it.level
+        raise KeyError(amp)
+
+    def _template_item(self, w, it, ind, row):
+        p = self.p
+        if it.kind == "ext":
+            (k,) = it.data
+            self._w, self._ind = w, ind
+            w(ind + self._position_external(k))
+        elif it.kind == "call":
+            k, _ = it.data
+            self._lazy_kinematics(w, ind, p.calls[k], self._done)
+            self._call(w, p.calls[k], ind)
+        elif it.kind == "rvec":
+            k, sp = it.data
+            c = p.calls[k]
+            coef = dict(p.jamp[0]).get(c.out, 0.0)
+            self._lazy_kinematics(w, ind, c, self._done)
+            a = [f"w{x}" for x in c.ins]
+            Q = lambda x: f"Qs{self.sname(self.subset[x])}"
+            gr = f"g{c.cpl}_0.r"
+            fn = nest.ROOT_SPLIT[(c.op, sp)]
+            if fn == "vvv_r3":
+                rhs = f"vvv_r3<T>({a[0]}, {Q(c.ins[0])}, {a[1]}, {Q(c.ins[1])}, {Q(c.ins[2])}, {gr})"
+            elif fn == "gggg_r4":
+                rhs = f"gggg_r4<T>({a[0]}, {a[1]}, {a[2]}, {gr})"
+            else:
+                rhs = f"gggg_r2<T>({a[0]}, {a[2]}, {a[3]}, {gr})"
+            if it.level == self._rt_level:
+                # accumulate at once, so that only the running sum stays live
+                w(f"{ind}Rt = waxpy<T>(T({_c(coef)}), {rhs}, Rt);")
+            else:
+                w(f"{ind}const wf<T> R{c.out} = {rhs};")
+        elif it.kind == "rstart":
+            terms = [(a, cf) for a, cf in it.data]
+            if terms:
+                comps = [" + ".join(f"T({_c(cf)}) * R{a}.c[{m}]" for a, cf in terms) for m in range(4)]
+                w(f"{ind}wf<T> Rt = {{{{{', '.join(comps)}}}}};")
+            else:
+                w(f"{ind}wf<T> Rt = {{}};")
+        elif it.kind == "adot":
+            w(f"{ind}work[(size_t(o) * nh + {row}) * 256 + threadIdx.x] = dot(w0, Rt);")
+        else:
+            raise ValueError(it.kind)
 
     # ------------------------------------------------------------------ calls
     def _call(self, w, c, ind, args=None):

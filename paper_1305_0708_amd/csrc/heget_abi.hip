@@ -358,8 +358,9 @@ namespace {
 heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
   if (a.n == 0) return HEGET_OK;
   const int block = 256;
-  const int64_t grid = (a.n + block - 1) / block;
+  int64_t grid = (a.n + block - 1) / block;
   if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
+  if (p->entry->persistent) grid = std::min<int64_t>(grid, p->grid_cap);   // one workspace slot per block
   const void* fn = p->prec == HEGET_FP64 ? p->entry->kernel_fp64 : p->entry->kernel_mixed;
   void* args[] = {&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(block), args, 0, stream));
@@ -388,7 +389,21 @@ KernelArgs heget::detail::base_args(heget_process_t p) {
   a.cstep = p->d_cstep;
   a.cterm = p->d_cterm;
   a.cfrag = p->d_cfrag;
+  a.work = p->d_work;
+  a.work_stride = p->work_stride;
   return a;
+}
+
+int heget::detail::resident_blocks(const void* fn) {
+  int dev = 0, per_cu = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) n_cu = 1;
+  return per_cu * n_cu;
+}
+
+size_t heget::detail::complex_bytes(heget_process_t p) {
+  return p->prec == HEGET_FP64 ? 2 * sizeof(double) : 2 * sizeof(float);
 }
 
 namespace {
@@ -405,6 +420,7 @@ void release(heget_process* p) {
   if (p->d_cstep) (void)hipFree(p->d_cstep);
   if (p->d_cterm) (void)hipFree(p->d_cterm);
   if (p->d_cfrag) (void)hipFree(p->d_cfrag);
+  if (p->d_work) (void)hipFree(p->d_work);
   delete p;
 }
 
@@ -530,6 +546,17 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
     if (hipMemcpy(p->d_ord, ir->orderings, nb, hipMemcpyHostToDevice) != hipSuccess) {
       release(p);
       return fail(HEGET_E_HIP, "upload of the ordering table failed");
+    }
+  }
+  if (entry->persistent) {
+    // ordering amplitudes of every resident block's 256 events, all orderings and helicities
+    p->n_orderings = ir->n_orderings;
+    p->grid_cap = heget::detail::resident_blocks(prec == HEGET_FP64 ? entry->kernel_fp64 : entry->kernel_mixed);
+    p->work_stride = int64_t(ir->n_orderings) * ir->n_hel * 256;
+    const size_t wb = size_t(p->grid_cap) * size_t(p->work_stride) * heget::detail::complex_bytes(p);
+    if (hipMalloc(&p->d_work, wb) != hipSuccess) {
+      release(p);
+      return fail(HEGET_E_OOM, "device allocation of the workspace failed (" + std::to_string(wb >> 20) + " MiB)");
     }
   }
   if (entry->colour_mfma) {

@@ -65,6 +65,19 @@ struct mom {
 };
 __device__ __forceinline__ mom operator+(mom a, mom b) { return {a.e + b.e, a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ mom operator-(mom a) { return {-a.e, -a.x, -a.y, -a.z}; }
+// The same momentum, opaque to the optimiser: kinematics computed from it
+// inside a loop stay in that loop (recomputed) instead of being hoisted out and
+// held in registers across it.
+__device__ __forceinline__ mom opaque_mom(mom a) {
+  asm volatile("" : "+v"(a.e), "+v"(a.x), "+v"(a.y), "+v"(a.z));
+  return a;
+}
+// An integer opaque to the optimiser (same value): addresses built from it
+// inside a loop keep their loads in that loop.
+__device__ __forceinline__ int opaque_int(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
 __device__ __forceinline__ double msq(mom a) { return a.e * a.e - a.x * a.x - a.y * a.y - a.z * a.z; }
 
 // four-momentum in the arithmetic type of the wavefunctions
@@ -90,6 +103,11 @@ __device__ __forceinline__ wf<T> cvtw(const wf<S>& a) {
 template <class T>
 __device__ __forceinline__ wf<T> wscale(cx<T> s, const wf<T>& a) {
   return {{s * a.c[0], s * a.c[1], s * a.c[2], s * a.c[3]}};
+}
+
+template <class T>
+__device__ __forceinline__ wf<T> waxpy(T s, const wf<T>& x, const wf<T>& y) {
+  return {{s * x.c[0] + y.c[0], s * x.c[1] + y.c[1], s * x.c[2] + y.c[2], s * x.c[3] + y.c[3]}};
 }
 
 template <class T>
@@ -572,12 +590,42 @@ __device__ __forceinline__ wf<T> jvvxxx(const wf<T>& v1, vec<T> q1, const wf<T>&
   return vector_prop<T, MASSIVE>(A, q, inv_m2, dinv);
 }
 
+// vvvxxx is linear in V3: vvvxxx(v1, q1, v2, q2, v3, q3, g) = dot(v3, vvv_r3(v1, q1, v2, q2, q3, g)).
+// Lets a loop over V3's helicity reuse the rest.
+template <class T>
+__device__ __forceinline__ wf<T> vvv_r3(const wf<T>& v1, vec<T> q1, const wf<T>& v2, vec<T> q2, vec<T> q3, T g) {
+  const vec<T> a = {q2.e - q1.e, q2.x - q1.x, q2.y - q1.y, q2.z - q1.z};
+  const vec<T> b = {q3.e - q2.e, q3.x - q2.x, q3.y - q2.y, q3.z - q2.z};
+  const vec<T> c = {q1.e - q3.e, q1.x - q3.x, q1.y - q3.y, q1.z - q3.z};
+  const cx<T> v12 = -g * dot(v1, v2), v1b = -g * dot(v1, b), v2c = -g * dot(v2, c);
+  wf<T> r;
+  r.c[0] = a.e * v12 + v1b * v2.c[0] + v2c * v1.c[0];
+  r.c[1] = a.x * v12 + v1b * v2.c[1] + v2c * v1.c[1];
+  r.c[2] = a.y * v12 + v1b * v2.c[2] + v2c * v1.c[2];
+  r.c[3] = a.z * v12 + v1b * v2.c[3] + v2c * v1.c[3];
+  return r;
+}
+
 // ------------------------------------------------------------------- VVVV
 // L = gg {(V1*.V4*)(V2*.V3*) - (V1*.V3*)(V2*.V4*)}  (Sec. 4.2.4); for gluons the
 // effective strength gg is g_s^2 (passed already squared).
 template <class T>
 __device__ __forceinline__ cx<T> ggggxx(const wf<T>& v1, const wf<T>& v2, const wf<T>& v3, const wf<T>& v4, T gg) {
   return gg * (dot(v1, v4) * dot(v2, v3) - dot(v1, v3) * dot(v2, v4));
+}
+// ggggxx is linear in each input: ggggxx(v1, v2, v3, v4) = dot(v4, gggg_r4(v1, v2, v3))
+// = dot(v2, gggg_r2(v1, v3, v4)).
+template <class T>
+__device__ __forceinline__ wf<T> gggg_r4(const wf<T>& v1, const wf<T>& v2, const wf<T>& v3, T gg) {
+  const cx<T> a = gg * dot(v2, v3), b = gg * dot(v1, v3);
+  return {{a * v1.c[0] - b * v2.c[0], a * v1.c[1] - b * v2.c[1], a * v1.c[2] - b * v2.c[2],
+           a * v1.c[3] - b * v2.c[3]}};
+}
+template <class T>
+__device__ __forceinline__ wf<T> gggg_r2(const wf<T>& v1, const wf<T>& v3, const wf<T>& v4, T gg) {
+  const cx<T> a = gg * dot(v1, v4), b = gg * dot(v1, v3);
+  return {{a * v3.c[0] - b * v4.c[0], a * v3.c[1] - b * v4.c[1], a * v3.c[2] - b * v4.c[2],
+           a * v3.c[3] - b * v4.c[3]}};
 }
 // V4 current (jgggxx): A = gg {V1 (V2.V3) - V2 (V1.V3)}, propagated
 template <class T, bool MASSIVE>

@@ -28,6 +28,11 @@ struct heget_process {
   double* d_part = nullptr;  // integrate partials, grown on demand and reused
   int64_t part_cap = 0;
   std::vector<int8_t> hel;   // host copy of the current table
+  // persistent kernels (ordering templates): grid cap and one workspace slot per block
+  int grid_cap = 0;
+  void* d_work = nullptr;
+  int64_t work_stride = 0;   // complex values per slot
+  int n_orderings = 0;
 };
 
 namespace heget {
@@ -41,6 +46,12 @@ bool is_full_product(const GenEntry* e, const int8_t* table, int n_hel, int n_le
 
 // Kernel arguments with the process's resident tables filled in.
 KernelArgs base_args(heget_process_t p);
+
+// Resident blocks of a kernel on the current device (occupancy x compute units).
+int resident_blocks(const void* fn);
+
+// Bytes of one complex value of the process's arithmetic type.
+size_t complex_bytes(heget_process_t p);
 
 // Massless n-body phase-space volume at sqrt_s (every RAMBO weight).
 double phase_space_volume(double sqrt_s, int n);

@@ -132,6 +132,7 @@ struct Slot {
   BatchTable* d_table = nullptr;
   BatchTable* h_table = nullptr;  // pinned; read by the graph's upload node
   hipGraphExec_t exec = nullptr;
+  void* d_work = nullptr;         // persistent kernels: this slot's own workspace
   bool busy = false;
   std::vector<Request*> seg_req;  // request of each segment
   std::vector<Request*> job_req;  // request of each reduction job
@@ -325,6 +326,7 @@ void destroy_server(heget_server* s) {
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
     if (sl->d_table) (void)hipFree(sl->d_table);
     if (sl->h_table) (void)hipHostFree(sl->h_table);
+    if (sl->d_work) (void)hipFree(sl->d_work);
   }
   delete s;
 }
@@ -333,18 +335,21 @@ void destroy_server(heget_server* s) {
 heget_status capture_slot(heget_server* s, Slot& sl) {
   heget_process_t p = s->procs[sl.proc];
   const void* fn = p->prec == HEGET_FP64 ? p->entry->batch_fp64 : p->entry->batch_mixed;
-  int per_cu = 0, n_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || n_cu < 1)
-    n_cu = 1;
+  const int grid = heget::detail::resident_blocks(fn);
   KernelArgs a = heget::detail::base_args(p);
   a.batch = sl.d_table;
+  if (p->entry->persistent) {
+    // the slot's own workspace: launches of one process on several slots run concurrently
+    const size_t wb = size_t(grid) * size_t(p->work_stride) * heget::detail::complex_bytes(p);
+    if (hipMalloc(&sl.d_work, wb) != hipSuccess) return fail(HEGET_E_OOM, "slot workspace allocation failed");
+    a.work = sl.d_work;
+  }
   void* args[] = {&a};
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     hipError_t c = hipMemcpyAsync(sl.d_table, sl.h_table, sizeof(BatchTable), hipMemcpyHostToDevice, sl.stream);
-    if (c == hipSuccess) c = hipLaunchKernel(fn, dim3(unsigned(per_cu * n_cu)), dim3(256), args, 0, sl.stream);
+    if (c == hipSuccess) c = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(256), args, 0, sl.stream);
     if (c == hipSuccess) {
       hipLaunchKernelGGL(reduce_jobs, dim3(heget::kMaxJobs), dim3(256), 0, sl.stream, sl.d_table);
       c = hipGetLastError();

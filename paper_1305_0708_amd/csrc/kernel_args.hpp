@@ -37,6 +37,8 @@ struct KernelArgs {
   const uint32_t* cterm;     // [sum nterm][4]: (ordering | coefficient << 16) per lane group
   const void* cfrag;         // [nfo][nks][64] colour-matrix A fragments, double or float
   const BatchTable* batch;   // fused launches of the serving engine, else null
+  void* work;                // persistent kernels: gridDim.x slots of work_stride complex values
+  int64_t work_stride;       //   (ordering amplitudes [n_orderings][n_hel][256] per block)
 };
 
 // One request's share of a fused launch: virtual blocks [block_begin, next

@@ -21,6 +21,9 @@ OP_FLOPS = {
     "iov": 2 * WEYL_C + 2 * (3 * CMUL + CADD) + CADD,           # 114
     "ffv_bra": 2 * WEYL_C + 4 * CMUL,                           # 96: <fo| Vslash (g0 P_L + g1 P_R)
     "spinor_dot": 4 * CMUL + 3 * CADD,                          # 30
+    "vvv_r3": 12 + DOT_CC + 2 * DOT_CR + 3 * RMUL + 4 * (RMUL + 2 * CMUL + 2 * CADD),   # 146
+    "gggg_r4": 2 * DOT_CC + 2 * RMUL + 4 * (2 * CMUL + CADD),   # 120
+    "gggg_r2": 2 * DOT_CC + 2 * RMUL + 4 * (2 * CMUL + CADD),   # 120
     "ffv_current": 8 * CMUL + 4 * (2 * CMUL + 3 * CADD),        # 120
     "fvi": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
     "fvo": 2 * WEYL_C + 4 * CMUL + 2 * WEYL_R + 2 + 4 * (2 * CMUL + CADD),   # 198
@@ -75,12 +78,15 @@ def per_helicity(proc):
         n += reps * CADD * max(len(proc.jamp[0]) - 1, 0)
     else:
         n += sum(CADD * max(len(t) - 1, 0) for t in proc.jamp)      # jamp sums
+    return n + colour_flops(proc)
+
+
+def colour_flops(proc):
+    """the colour quadratic form of one helicity of one event"""
     nf = proc.n_flows
     if proc.uses_colour_mfma():
-        n += colour_mfma_flops(proc)
-    else:
-        n += nf * 4 + (nf * (nf - 1) // 2) * 4 + 2                  # colour quadratic form
-    return n
+        return colour_mfma_flops(proc)
+    return nf * 4 + (nf * (nf - 1) // 2) * 4 + 2
 
 
 def colour_mfma_flops(proc):
@@ -107,6 +113,13 @@ def per_event(proc, n_hel=None):
     if n_hel is None and not proc.orderings:
         from . import nest
         return nest.schedule(proc).flops_per_event + n_cur * (7 + 8)
+    if n_hel is None:
+        # ordering template: per ordering, the momenta and denominators once and
+        # the helicity nest; per helicity, the colour form over all orderings
+        from . import nest
+        nh = len(proc.helicities)
+        return (nest.template_schedule(proc).flops_per_event + len(proc.orderings) * n_cur * (7 + 8)
+                + nh * colour_flops(proc))
     nh = len(proc.helicities) if n_hel is None else n_hel
     if proc.orderings:
         # per-ordering momenta and denominators are formed inside the helicity loop

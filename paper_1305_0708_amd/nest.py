@@ -228,3 +228,106 @@ def schedule(proc):
     colour = nf * 4 + (nf * (nf - 1) // 2) * 4 + 2
     total = sum(it.flops * mult[it.level] for it in items) + colour * mult[inner]
     return Schedule(pl.order, pl.choices, items, total)
+
+
+# ------------------------------------------------- ordering templates (C2)
+# amplitudes of a colour-ordered template are linear in the root position's
+# vector (slot 0); the vertex vector of the other inputs is formed outside the
+# root's loop: (op, index of the root input) -> device function
+ROOT_SPLIT = {("vvv", 2): "vvv_r3", ("gggg", 3): "gggg_r4", ("gggg", 1): "gggg_r2"}
+
+
+def template_plan(proc):
+    """Loop order over the template's positions (root position 0 innermost
+    when that is cheapest) and the root splits of the amplitude calls."""
+    if proc.orderings is None:
+        raise ValueError("not an ordering template")
+    nl = proc.n_legs
+    choices = []
+    for k in range(nl):
+        cand = {leg_choices(proc.legs[o[k]]) for o in proc.orderings}
+        assert len(cand) == 1, "a position must hold one kind of particle"
+        choices.append(cand.pop())
+    deps = call_dependencies(proc)
+    split = []
+    for c in proc.calls:
+        sp = None
+        if c.op in AMP_OPS:
+            for j, x in enumerate(c.ins):
+                if x == 0 and (c.op, j) in ROOT_SPLIT:
+                    sp = j
+        split.append(sp)
+    # the vertex vector of a split amplitude depends on the other inputs only
+    odeps = []
+    dep = {k: frozenset((k,)) for k in range(nl)}
+    for c, d, sp in zip(proc.calls, deps, split):
+        odeps.append(frozenset().union(*(dep[x] for j, x in enumerate(c.ins) if j != sp)) if sp is not None else d)
+        if c.op not in AMP_OPS:
+            dep[c.out] = d
+    call_cost = [flops.call_flops(c) for c in proc.calls]
+    ext_cost = [_ext_flops(proc.legs[proc.orderings[0][k]]) for k in range(nl)]
+
+    def cost(order):
+        pos = {L: i for i, L in enumerate(order)}
+        mult, m = [], 1
+        for L in order:
+            m *= len(choices[L])
+            mult.append(m)
+        c = sum(ext_cost[L] * mult[pos[L]] for L in order)
+        rl = []
+        for cc, d, od, sp, call in zip(call_cost, deps, odeps, split, proc.calls):
+            if sp is None:
+                c += cc * mult[max(pos[L] for L in d)]
+            else:
+                lv = max(pos[L] for L in od)
+                c += flops.OP_FLOPS[ROOT_SPLIT[(call.op, sp)]] * mult[lv]
+                rl.append(lv)
+        if rl:
+            lv = max(rl)
+            c += flops.CADD * 4 * (len(rl) - 1) * mult[lv] + flops.DOT_CC * mult[max(lv, pos[0])]
+        return c
+
+    free = [k for k in range(nl) if len(choices[k]) > 1]
+    fixed = [k for k in range(nl) if len(choices[k]) == 1]
+    if len(free) <= 8:
+        best = min(itertools.permutations(free), key=lambda perm: cost(fixed + list(perm)))
+        order = fixed + list(best)
+    else:
+        order = fixed + sorted(free, key=lambda k: k == 0)
+    return order, choices, deps, odeps, split, cost(order)
+
+
+def template_schedule(proc):
+    """Items of one ordering's helicity loop nest over the template positions:
+    externals, currents, the vertex vectors of the amplitudes with respect to
+    the root (outside the root's loop), their jamp-weighted sum, and the
+    ordering amplitude A = w_root . R innermost."""
+    order, choices, deps, odeps, split, total = template_plan(proc)
+    nl = proc.n_legs
+    pos = {L: i for i, L in enumerate(order)}
+    clev = {k: pos[k] for k in range(nl)}
+    items = [Item("ext", pos[k], (k,), _ext_flops(proc.legs[proc.orderings[0][k]])) for k in order]
+    coef = dict(proc.jamp[0])
+    rterms = []
+    for k, (c, od, sp) in enumerate(zip(proc.calls, odeps, split)):
+        if c.op in AMP_OPS and sp is not None:
+            lv = max(pos[L] for L in od)
+            items.append(Item("rvec", lv, (k, sp), flops.OP_FLOPS[ROOT_SPLIT[(c.op, sp)]]))
+            rterms.append((c.out, coef.get(c.out, 0.0), lv))
+        else:
+            lv = max(clev[x] for x in c.ins)
+            items.append(Item("call", lv, (k, tuple(("w", x) for x in c.ins)), flops.call_flops(c)))
+            if c.op not in AMP_OPS:
+                clev[c.out] = lv
+    amps_split = {a for a, _, _ in rterms}
+    if amps_split != {a for a, _ in proc.jamp[0]} or len(amps_split) != proc.n_amps:
+        raise NotImplementedError("every template amplitude must split on the root")
+    rl = max(lv for _, _, lv in rterms)
+    items.append(Item("rsum", rl, tuple((a, cf) for a, cf, _ in rterms), flops.CADD * 4 * (len(rterms) - 1)))
+    items.append(Item("adot", max(rl, pos[0]), (), flops.DOT_CC))
+    mult, m = {-1: 1}, 1
+    for i, L in enumerate(order):
+        m *= len(choices[L])
+        mult[i] = m
+    per_ordering = sum(it.flops * mult[it.level] for it in items)
+    return Schedule(order, choices, items, per_ordering * len(proc.orderings))
