@@ -45,25 +45,25 @@ def measured_traffic(proc_ir):
     return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
-def time_path(torch, proc, steps, warmup, n=N_EVENTS):
+def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S):
     """Per step: one heget_integrate (amplitude kernel + reduction).  Also
     times the amplitude kernel alone with HIP events on the launch stream."""
     for _ in range(warmup):
-        proc.integrate(n, seed=SEED, sqrt_s=SQRT_S)
+        proc.integrate(n, seed=SEED, sqrt_s=sqrt_s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        r = proc.integrate(n, seed=SEED + k, sqrt_s=SQRT_S)
+        r = proc.integrate(n, seed=SEED + k, sqrt_s=sqrt_s)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     # amplitude kernel alone: eval with |M|^2 written, timed with events on the stream it runs on
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    proc.eval(n=n, seed=SEED, sqrt_s=SQRT_S, me2_out=out)
+    proc.eval(n=n, seed=SEED, sqrt_s=sqrt_s, me2_out=out)
     ev0.record(stream)
     for k in range(steps):
-        proc.eval(n=n, seed=SEED + k, sqrt_s=SQRT_S, me2_out=out)
+        proc.eval(n=n, seed=SEED + k, sqrt_s=sqrt_s, me2_out=out)
     ev1.record(stream)
     ev1.synchronize()
     kern = ev0.elapsed_time(ev1) / 1e3 / steps
@@ -165,6 +165,9 @@ def main():
                     help="requests in the serving replay (0: skip it)")
     ap.add_argument("--profile-leg", choices=["fp64", "mixed"], default=None,
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
+    ap.add_argument("--profile-proc", default="gg_ttbar_6f",
+                    help="process of --profile-leg: gg_ttbar_6f (default), gg_4g, gg_4g_ddm, ud_udhh_4b, ee_mumu, "
+                         "or 'generate' for the phase-space kernel of gg_ttbar_6f alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -179,10 +182,17 @@ def main():
 
     proc_ir = processes.gg_ttbar_6f()
     if args.profile_leg:
-        proc = H.Process(proc_ir, precision=args.profile_leg)
-        wall, kern, r = time_path(torch, proc, args.steps, args.warmup)
-        out = {"leg": args.profile_leg, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
-               "events_per_launch": N_EVENTS, "flop_per_event": flops.per_event(proc_ir)}
+        if args.profile_proc == "generate":
+            proc = H.Process(proc_ir, precision=args.profile_leg)
+            out = phase_space_leg(torch, proc, args.steps, args.warmup)
+            print(json.dumps(out), flush=True)
+            return
+        pir = processes.by_name(args.profile_proc)
+        proc = H.Process(pir, precision=args.profile_leg)
+        wall, kern, r = time_path(torch, proc, args.steps, args.warmup, sqrt_s=pir.sqrt_s)
+        out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
+               "kernel_ms": kern * 1e3, "events_per_launch": N_EVENTS, "flop_per_event": flops.per_event(pir),
+               "events_per_s": N_EVENTS / wall, "n_accepted": r["n_accepted"]}
         if args.copy_calibration:
             src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
             dst = torch.empty_like(src)

@@ -139,9 +139,15 @@ __device__ __forceinline__ cx<double> inv_denominator(mom q, cx<double> pole) {
 // --------------------------------------------------------------- external lines
 // Two-component helicity eigenstates chi_lam of sigma.phat (unit norm), written
 // with sqrt(2|p|(|p|+pz)); for a momentum along -z: chi_+ = (0,1), chi_- = (-1,0).
+// |p| + p_z without cancellation: for p_z < 0 it equals p_T^2 / (|p| - p_z)
+template <class T>
+__device__ __forceinline__ T pp_plus_pz(vec<T> p, T pp) {
+  return p.z >= T(0) ? pp + p.z : (p.x * p.x + p.y * p.y) / (pp - p.z);
+}
+
 template <class T>
 __device__ __forceinline__ void chi2(vec<T> p, T pp, int lam, cx<T>& a, cx<T>& b) {
-  const T s = pp + p.z;
+  const T s = pp_plus_pz(p, pp);
   if (s > T(0)) {
     const T n = T(1) / sqrt(T(2) * pp * s);
     if (lam > 0) {
@@ -170,7 +176,7 @@ __device__ __forceinline__ void chi2(vec<T> p, T pp, int lam, cx<T>& a, cx<T>& b
 template <class T>
 __device__ __forceinline__ void weyl0(vec<T> p, int lam, cx<T>& a, cx<T>& b) {
   const T pp = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
-  const T s = pp + p.z;
+  const T s = pp_plus_pz(p, pp);
   if (s > T(0)) {
     const T r = sqrt(s), ir = T(1) / r;
     if (lam > 0) {
