@@ -30,11 +30,11 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 # HBM traffic of one amplitude-kernel launch in the integrate step (FP64, 2^20
 # events), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch, steady-state launches) scaled by what the same counters read for a
-# plain 1 GiB device copy in the same run (FETCH_SIZE read 524,299.5 KiB for
+# plain 1 GiB device copy in the same runs (FETCH_SIZE read 524,299.5 KiB for
 # 1,048,576 KiB fetched -> x2.0; WRITE_SIZE read 1,048,576 KiB -> x1.0).
 # Tied to the kernel source it was taken on: a different digest reports null.
-TRAFFIC_FP64 = {"source_digest": "e1e903ca35bf1a4c04cb286dd8187bb90cc70f374e94638d186806d215cc7bb1",
-                "fetch_kib": 349.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0}
+TRAFFIC_FP64 = {"source_digest": "29c95eea18961f489eb8aa1c700e92afb43eb85e91540637da3cac88605c53d4",
+                "fetch_kib": 369.0, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0}
 
 
 def measured_traffic(proc_ir):
