@@ -79,6 +79,16 @@ class Gen:
             if c.op in ("vvv", "jvv"):
                 self.need_q.update(self.subset[x] for x in c.ins)
 
+    def cterm_cap(self):
+        """words of the MFMA colour form's term table: flows sorted (stably) by
+        their number of flow-map terms, each k-step of four flows padded to its
+        longest row, four words per term row"""
+        p = self.p
+        rows = p.flow_map if p.flow_map is not None else [[1 if o == f else 0 for o in range(len(p.orderings))]
+                                                          for f in range(p.n_flows)]
+        nnz = sorted(sum(1 for x in r if x) for r in rows)
+        return 4 * sum(max(nnz[4 * s:4 * s + 4]) for s in range((len(nnz) + 3) // 4))
+
     def m(self, s):
         return self.mslot.get(s, s)
 
@@ -152,6 +162,8 @@ class Gen:
             w("// 256-event blocks of the launch")
             w("template <class T>")
             w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
+            if p.uses_colour_mfma():
+                w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
             w("  const int64_t nb = (a.n + 255) / 256;")
             w("  for (int64_t vb = blockIdx.x; vb < nb; vb += gridDim.x) {")
             w(f"    body_{p.name}<T>(a, vb);")
@@ -169,6 +181,8 @@ class Gen:
         w("// walks the virtual blocks of the batch table")
         w("template <class T>")
         w(f"__global__ __launch_bounds__(256) void amp_{p.name}_batch(KernelArgs a) {{")
+        if p.uses_colour_mfma():
+            w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
         w("  const BatchTable* bt = a.batch;")
         w("  const int64_t total = bt->total_blocks;")
         w("  const int nseg = bt->n_seg;")
@@ -195,7 +209,7 @@ class Gen:
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
-          f'{int(self.ordered)}}};')
+          f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
@@ -402,8 +416,7 @@ class Gen:
             w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
             w("      __builtin_amdgcn_wave_barrier();")
             w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
-            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}>(&jl[0][0], a.cstep, a.cterm, "
-              f"static_cast<const T*>(a.cfrag)));")
+            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}>(&jl[0][0], a.cstep, a));")
             w("      __builtin_amdgcn_wave_barrier();")
             w("    }")
             w("  }")

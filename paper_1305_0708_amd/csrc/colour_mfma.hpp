@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include "heget_device.hpp"
+#include "kernel_args.hpp"
 
 namespace heget {
 
@@ -52,14 +53,50 @@ struct Mfma<float> {
   }
 };
 
+// LDS homes of the term table and (FP32) of the colour fragments: one static
+// allocation per kernel, filled once per block by colour_stage.
+template <class T, int NFRAG, int NTERM>
+struct ColourLds {
+  static __device__ __forceinline__ T* frag() {
+    __shared__ T buf[NFRAG];
+    return buf;
+  }
+  static __device__ __forceinline__ uint32_t* term() {
+    __shared__ uint32_t buf[NTERM];
+    return buf;
+  }
+};
+
+// Fragments in LDS for FP32 (61 KB); FP64 (123 KB) streams them from L2.
+template <class T>
+constexpr bool kFragInLds = sizeof(T) == 4;
+
+// Copy the term table (and the FP32 fragments) to LDS; every thread of the
+// block calls it, before its first colour form.
+template <class T, int NKS, int NFO, int NTERM>
+__device__ inline void colour_stage(const KernelArgs& a) {
+  uint32_t* tl = ColourLds<T, NFO * NKS * 64, NTERM>::term();
+  for (int i = threadIdx.x; i < a.cterm_words; i += blockDim.x) tl[i] = a.cterm[i];
+  if constexpr (kFragInLds<T>) {
+    T* fl = ColourLds<T, NFO * NKS * 64, NTERM>::frag();
+    const T* src = static_cast<const T*>(a.cfrag);
+    for (int i = threadIdx.x; i < NFO * NKS * 64; i += blockDim.x) fl[i] = src[i];
+  }
+  __syncthreads();
+}
+
 // Returns Re(J^dagger C J) for the calling lane's event, where J_f = sum_o
 // coef * A_o over the flow-map terms and A_o = jl[o * 256 + threadIdx.x] are
 // the ordering amplitudes the block staged in LDS (row stride 256 events).
 // Every lane of the wavefront must call it (the MFMAs need the full wave) and
-// the wave's own 64 columns of jl must be written before the call.
-template <class T, int NKS, int NFO>
-__device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const uint32_t* cterm, const T* cfrag) {
+// the wave's own 64 columns of jl must be written before the call.  Output
+// tiles are taken in pairs, so that four independent accumulations keep the
+// matrix pipeline busy.
+template <class T, int NKS, int NFO, int NTERM>
+__device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const KernelArgs& a) {
   static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
+  using L = ColourLds<T, NFO * NKS * 64, NTERM>;
+  const uint32_t* terms = L::term();
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
   const int wbase = tid - lane;
   T result = T(0);
@@ -75,7 +112,7 @@ __device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const ui
         const int nt = __builtin_amdgcn_readfirstlane(cstep[2 * s]);
         const int off = __builtin_amdgcn_readfirstlane(cstep[2 * s + 1]);
         for (int t = 0; t < nt; ++t) {
-          const uint32_t e = cterm[4 * (off + t) + g];
+          const uint32_t e = terms[4 * (off + t) + g];
           const cx<T> v = jl[int(e & 0xffffu) * 256 + ev];
           const T cf = T(int(int16_t(uint16_t(e >> 16))));
           xr[s] += cf * v.r;
@@ -83,23 +120,33 @@ __device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const ui
         }
       }
     }
-    // The fragments are the same for every chunk and helicity; hide that from
-    // the optimiser so they stream from cache instead of being hoisted into
-    // (and spilled from) registers.
-    const T* frag = cfrag;
-    asm volatile("" : "+s"(frag));
+    // The fragments are the same for every chunk and helicity; an opaque base
+    // keeps them streaming (from LDS or L2) instead of being hoisted into
+    // registers.
+    const int base = opaque_int(0);
+    const T* frag = kFragInLds<T> ? L::frag() : static_cast<const T*>(a.cfrag);
     T part = T(0);
 #pragma unroll
-    for (int fo = 0; fo < NFO; ++fo) {
-      typename Mfma<T>::acc zr = {T(0), T(0), T(0), T(0)}, zi = {T(0), T(0), T(0), T(0)};
+    for (int fo = 0; fo < NFO; fo += 2) {
+      const bool two = fo + 1 < NFO;
+      typename Mfma<T>::acc zr0 = {T(0), T(0), T(0), T(0)}, zi0 = zr0, zr1 = zr0, zi1 = zr0;
 #pragma unroll
       for (int s = 0; s < NKS; ++s) {
-        const T av = frag[(fo * NKS + s) * 64 + lane];
-        zr = Mfma<T>::step(av, xr[s], zr);
-        zi = Mfma<T>::step(av, xi[s], zi);
+        const T a0 = frag[base + (fo * NKS + s) * 64 + lane];
+        zr0 = Mfma<T>::step(a0, xr[s], zr0);
+        zi0 = Mfma<T>::step(a0, xi[s], zi0);
+        if (two) {
+          const T a1 = frag[base + ((fo + 1) * NKS + s) * 64 + lane];
+          zr1 = Mfma<T>::step(a1, xr[s], zr1);
+          zi1 = Mfma<T>::step(a1, xi[s], zi1);
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part += zr[r] * xr[4 * fo + r] + zi[r] * xi[4 * fo + r];
+      for (int r = 0; r < 4; ++r) part += zr0[r] * xr[4 * fo + r] + zi0[r] * xi[4 * fo + r];
+      if (two) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part += zr1[r] * xr[4 * fo + 4 + r] + zi1[r] * xi[4 * fo + 4 + r];
+      }
     }
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);

@@ -24,6 +24,7 @@ struct GenEntry {
   const int8_t* hel_canon;    // full helicity product the kernel's loop nest sums, or null
   int n_hel_canon;            // its rows (n_legs entries each)
   int persistent;             // 1: persistent grid with a workspace slot per block (ordering templates)
+  int cterm_cap;              // capacity of the kernel's LDS term table (words)
 };
 
 // The launch arguments of one request's segment in a fused launch.

@@ -389,6 +389,7 @@ KernelArgs heget::detail::base_args(heget_process_t p) {
   a.cstep = p->d_cstep;
   a.cterm = p->d_cterm;
   a.cfrag = p->d_cfrag;
+  a.cterm_words = p->cterm_words;
   a.work = p->d_work;
   a.work_stride = p->work_stride;
   return a;
@@ -565,6 +566,11 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
       release(p);
       return st;
     }
+    if (int(t.cterm.size()) > entry->cterm_cap) {
+      release(p);
+      return fail(HEGET_E_IR, "colour term table larger than the kernel's");
+    }
+    p->cterm_words = int(t.cterm.size());
     std::vector<float> f32(t.cfrag.begin(), t.cfrag.end());
     const void* frag = prec == HEGET_FP64 ? static_cast<const void*>(t.cfrag.data()) : f32.data();
     const size_t fb = t.cfrag.size() * (prec == HEGET_FP64 ? sizeof(double) : sizeof(float));

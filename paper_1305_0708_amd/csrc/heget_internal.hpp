@@ -25,6 +25,7 @@ struct heget_process {
   int* d_cstep = nullptr;    // MFMA colour form: k-step table, term table, colour fragments
   uint32_t* d_cterm = nullptr;
   void* d_cfrag = nullptr;
+  int cterm_words = 0;
   double* d_part = nullptr;  // integrate partials, grown on demand and reused
   int64_t part_cap = 0;
   std::vector<int8_t> hel;   // host copy of the current table

@@ -36,6 +36,7 @@ struct KernelArgs {
   const int* cstep;          // [nks][2]: terms per flow in k-step s, offset of its term rows
   const uint32_t* cterm;     // [sum nterm][4]: (ordering | coefficient << 16) per lane group
   const void* cfrag;         // [nfo][nks][64] colour-matrix A fragments, double or float
+  int32_t cterm_words;       // length of cterm
   const BatchTable* batch;   // fused launches of the serving engine, else null
   void* work;                // persistent kernels: gridDim.x slots of work_stride complex values
   int64_t work_stride;       //   (ordering amplitudes [n_orderings][n_hel][256] per block)
