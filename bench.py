@@ -125,7 +125,11 @@ def phase_space_leg(torch, proc, steps, warmup):
 
 
 SERVE_SEED = 0x48454749
-SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g", "ud_udhh_4b")   # the four configurations
+# the four configurations; the engine runs mixed precision, where C2 uses its
+# 24-flow DDM-basis kernel (same |M|^2; the 120-flow FP32 MFMA kernel is kept
+# off the GPU for now), the unbatched FP64 baseline the 120-flow MFMA kernel
+SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g_ddm", "ud_udhh_4b")
+SERVE_BASELINE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g", "ud_udhh_4b")
 SERVE_WEIGHTS = (40, 30, 20, 10)
 SERVE_SQRT_S = (200.0, 1000.0, 1000.0, 2000.0)
 
@@ -137,7 +141,7 @@ def serve_leg(n_requests, rate=200.0):
     from paper_1305_0708_amd import processes, serve
     reqs = serve.poisson_mix(SERVE_SEED, n_requests, rate, SERVE_WEIGHTS, SERVE_SQRT_S)
     mixed = [H.Process(processes.by_name(n), precision="mixed") for n in SERVE_PROCESSES]
-    fp64 = [H.Process(processes.by_name(n), precision="fp64") for n in SERVE_PROCESSES]
+    fp64 = [H.Process(processes.by_name(n), precision="fp64") for n in SERVE_BASELINE_PROCESSES]
     warm = [serve.Request(0.0, k, 4096, 1, SERVE_SQRT_S[k]) for k in range(4)]
     srv = H.Server(mixed, arena_bytes=1 << 30, slots_per_process=2, max_batch_blocks=4096, max_chunk_blocks=1024)
     serve.replay_engine(srv, warm)
@@ -150,7 +154,8 @@ def serve_leg(n_requests, rate=200.0):
                 "max_busy_slots": st["max_busy_slots"], "arena_high_water_bytes": st["arena_high_water"]})
     base.update({"precision": "fp64", "kind": "unbatched: one heget_integrate at a time in arrival order"})
     return {"workload": f"{n_requests} Poisson requests at {rate:g}/s over "
-                        f"{'/'.join(SERVE_PROCESSES)} in proportions {'/'.join(map(str, SERVE_WEIGHTS))}, "
+                        f"{'/'.join(SERVE_PROCESSES)} (baseline {'/'.join(SERVE_BASELINE_PROCESSES)}) "
+                        f"in proportions {'/'.join(map(str, SERVE_WEIGHTS))}, "
                         "n log-uniform in [2^10, 2^20), sqrt_s = nominal x 2^U(-1/2,1/2)",
             "engine": eng, "baseline": base}
 

@@ -53,35 +53,22 @@ struct Mfma<float> {
   }
 };
 
-// LDS homes of the term table and (FP32) of the colour fragments: one static
-// allocation per kernel, filled once per block by colour_stage.
-template <class T, int NFRAG, int NTERM>
+// LDS home of the term table: one static allocation per kernel, filled once
+// per block by colour_stage.  (The colour fragments stream from L2.)
+template <class T, int NTERM>
 struct ColourLds {
-  static __device__ __forceinline__ T* frag() {
-    __shared__ T buf[NFRAG];
-    return buf;
-  }
   static __device__ __forceinline__ uint32_t* term() {
     __shared__ uint32_t buf[NTERM];
     return buf;
   }
 };
 
-// Fragments in LDS for FP32 (61 KB); FP64 (123 KB) streams them from L2.
-template <class T>
-constexpr bool kFragInLds = sizeof(T) == 4;
-
-// Copy the term table (and the FP32 fragments) to LDS; every thread of the
-// block calls it, before its first colour form.
+// Copy the term table to LDS; every thread of the block calls it, before its
+// first colour form.
 template <class T, int NKS, int NFO, int NTERM>
 __device__ inline void colour_stage(const KernelArgs& a) {
-  uint32_t* tl = ColourLds<T, NFO * NKS * 64, NTERM>::term();
+  uint32_t* tl = ColourLds<T, NTERM>::term();
   for (int i = threadIdx.x; i < a.cterm_words; i += blockDim.x) tl[i] = a.cterm[i];
-  if constexpr (kFragInLds<T>) {
-    T* fl = ColourLds<T, NFO * NKS * 64, NTERM>::frag();
-    const T* src = static_cast<const T*>(a.cfrag);
-    for (int i = threadIdx.x; i < NFO * NKS * 64; i += blockDim.x) fl[i] = src[i];
-  }
   __syncthreads();
 }
 
@@ -95,8 +82,7 @@ __device__ inline void colour_stage(const KernelArgs& a) {
 template <class T, int NKS, int NFO, int NTERM>
 __device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const KernelArgs& a) {
   static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
-  using L = ColourLds<T, NFO * NKS * 64, NTERM>;
-  const uint32_t* terms = L::term();
+  const uint32_t* terms = ColourLds<T, NTERM>::term();
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
   const int wbase = tid - lane;
   T result = T(0);
@@ -121,10 +107,9 @@ __device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const Ke
       }
     }
     // The fragments are the same for every chunk and helicity; an opaque base
-    // keeps them streaming (from LDS or L2) instead of being hoisted into
-    // registers.
+    // keeps them streaming from L2 instead of being hoisted into registers.
     const int base = opaque_int(0);
-    const T* frag = kFragInLds<T> ? L::frag() : static_cast<const T*>(a.cfrag);
+    const T* frag = static_cast<const T*>(a.cfrag);
     T part = T(0);
 #pragma unroll
     for (int fo = 0; fo < NFO; fo += 2) {
