@@ -354,6 +354,13 @@ class Gen:
             f, g, members = it.data
             expr = " + ".join(_coef_expr(cc, f"amp{a}") for a, cc in members)
             w(f"{ind}const cx<T> K{f}_{g} = {expr};")
+        elif it.kind == "bsum":
+            f, g, members = it.data
+            comps = [" + ".join(_coef_expr(cc, f"bra{a}.c[{m}]") for a, cc in members) for m in range(4)]
+            w(f"{ind}const wf<T> bj{f}_{g} = {{{{{', '.join(comps)}}}}};")
+        elif it.kind == "kdot":
+            f, g, ket = it.data
+            w(f"{ind}const cx<T> K{f}_{g} = spinor_dot(bj{f}_{g}, {self._nest_arg(ket)});")
         elif it.kind == "jamp":
             f, parts = it.data
             terms = [(" * ".join([f"w{s}" for s in facs] + [f"K{f}_{g}"])) for g, facs in parts]

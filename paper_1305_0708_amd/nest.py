@@ -209,17 +209,44 @@ def schedule(proc):
             fac[c.out] = f
             kind[c.out] = OUT_KIND[c.op]
     inner = len(pl.order) - 1
+    # split FFV amplitudes: bra level and ket argument, to combine bras before the product
+    split = {}
+    for it in items:
+        if it.kind == "bra":
+            split[proc.calls[it.data[0]].out] = [it.level, None, it]
+    for it in items:
+        if it.kind == "dot":
+            split[proc.calls[it.data[0]].out][1] = it.data[1]
+    combined = set()      # amplitudes whose every jamp term goes through a combined bra
+    jamp_items = []
     for fl, terms in enumerate(proc.jamp):
         groups = {}
         for a, coef in terms:
             groups.setdefault(amp_fac[a], []).append((a, coef))
         parts = []
         for gi, (fk, members) in enumerate(sorted(groups.items())):
-            klev = max(amp_lev[a] for a, _ in members)
-            items.append(Item("ksum", klev, (fl, gi, tuple(members)), flops.CADD * max(len(members) - 1, 0)))
+            kets = {split[a][1] if a in split else None for a, _ in members}
+            if len(kets) == 1 and None not in kets and len(members) > 1:
+                # sum_a c_a <bra_a|ket> = <sum_a c_a bra_a|ket>
+                blev = max(split[a][0] for a, _ in members)
+                ket = kets.pop()
+                jamp_items.append(Item("bsum", blev, (fl, gi, tuple(members)), 4 * flops.CADD * (len(members) - 1)))
+                jamp_items.append(Item("kdot", max(amp_lev[a] for a, _ in members), (fl, gi, ket),
+                                       flops.OP_FLOPS["spinor_dot"]))
+                combined.update(a for a, _ in members)
+            else:
+                klev = max(amp_lev[a] for a, _ in members)
+                jamp_items.append(Item("ksum", klev, (fl, gi, tuple(members)), flops.CADD * max(len(members) - 1, 0)))
             parts.append((gi, tuple(s for s, _ in fk)))
         nmul = sum(len(fs) for _, fs in parts)
-        items.append(Item("jamp", inner, (fl, tuple(parts)), nmul * flops.CMUL + flops.CADD * max(len(parts) - 1, 0)))
+        jamp_items.append(Item("jamp", inner, (fl, tuple(parts)),
+                               nmul * flops.CMUL + flops.CADD * max(len(parts) - 1, 0)))
+    # the products of amplitudes used only through combined bras are not needed
+    needed = {a for it in jamp_items if it.kind == "ksum" for a, _ in it.data[2]}
+    items = [it for it in items
+             if not (it.kind == "dot" and proc.calls[it.data[0]].out in combined
+                     and proc.calls[it.data[0]].out not in needed)]
+    items += jamp_items
     mult, m = {-1: 1}, 1
     for i, L in enumerate(pl.order):
         m *= len(pl.choices[L])

@@ -37,9 +37,11 @@ def test_schedule_is_complete_and_ordered(name):
             k, fi = it.data
             seen_amps.append(p.calls[k].out)
             assert level_of[fi[1]] <= it.level
+        elif it.kind == "bsum":
+            seen_amps.extend(a for a, _ in it.data[2])      # products formed with the combined bra
     assert sorted(seen_calls) == list(range(len(p.calls)))
-    assert sorted(seen_amps) == list(range(p.n_amps))
-    ks = [it for it in sc.items if it.kind == "ksum"]
+    assert set(seen_amps) == set(range(p.n_amps))
+    ks = [it for it in sc.items if it.kind in ("ksum", "bsum")]
     used = sorted(a for it in ks for a, _ in it.data[2])
     assert used == sorted(a for terms in p.jamp for a, _ in terms)
     assert {it.data[0] for it in sc.items if it.kind == "jamp"} == set(range(p.n_flows))
