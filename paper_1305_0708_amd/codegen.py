@@ -28,6 +28,7 @@ from . import ir, nest
 from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
+UNROLL_INNER_COMBINATIONS = 8
 
 
 def _c(x):
@@ -301,12 +302,22 @@ class Gen:
         w(f"{ind}// helicity loop nest, outermost leg first: {sc.order}")
         for it in by_level.get(-1, []):
             self._nest_item(w, it, ind)
+        # the innermost loops (up to 8 combinations) are unrolled: constant
+        # helicities there let the compiler specialise the external states and
+        # interleave the independent iterations
+        unrolled, combos = set(), 1
+        for lvl in reversed(range(len(sc.order))):
+            n = len(sc.choices[sc.order[lvl]])
+            if combos * n > UNROLL_INNER_COMBINATIONS:
+                break
+            combos *= n
+            unrolled.add(lvl)
         for lvl, L in enumerate(sc.order):
             ch = sc.choices[L]
             if len(ch) == 1:
                 w(f"{ind}const int hh{L} = {ch[0]};")
             else:
-                w(f"{ind}#pragma unroll 1")
+                w(f"{ind}#pragma unroll{'' if lvl in unrolled else ' 1'}")
                 w(f"{ind}for (int c{L} = 0; c{L} < {len(ch)}; ++c{L}) {{")
                 ind += "  "
                 if ch == (-1, 1):
