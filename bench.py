@@ -27,20 +27,32 @@ SEED = 0x48454746
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 
-# HBM traffic of one amplitude-kernel launch in the integrate step (FP64, 2^20
-# events), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per
-# dispatch, steady-state launches) scaled by what the same counters read for a
-# plain 1 GiB device copy in the same runs (FETCH_SIZE read 524,299.5 KiB for
-# 1,048,576 KiB fetched -> x2.0; WRITE_SIZE read 1,048,576 KiB -> x1.0).
-# Tied to the kernel source it was taken on: a different digest reports null.
-TRAFFIC_FP64 = {"source_digest": "29c95eea18961f489eb8aa1c700e92afb43eb85e91540637da3cac88605c53d4",
-                "fetch_kib": 369.0, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0}
+# Counter measurements of one amplitude-kernel launch in the integrate step
+# (FP64, 2^20 events), tied to the kernel source they were taken on (a
+# different digest reports them as null / falls back to the flop model):
+#  * HBM traffic from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE;
+#    KiB per dispatch, steady-state launches), scaled by what the same counters
+#    read for a plain 1 GiB device copy in the same runs (FETCH_SIZE read
+#    524,299.5 KiB for 1,048,576 KiB fetched -> x2.0; WRITE_SIZE read
+#    1,048,576 KiB -> x1.0);
+#  * FP64 flops executed per event, 2 FMA + MUL + ADD + TRANS from the
+#    SQ_INSTS_VALU_*_F64 counters per wave (one event per lane): the arithmetic
+#    the compiled kernel does, after the compiler has dropped the operations on
+#    the structural zeros of fixed-helicity massless spinors that the IR flop
+#    model still counts.
+COUNTERS_FP64 = {"source_digest": "025256a910918ef879c1995fbf82a7dc5529c685522880899edd8d8b767aefb4",
+                 "fetch_kib": 119574.5, "fetch_scale": 2.0, "write_kib": 855300.2, "write_scale": 1.0,
+                 "flop_per_event": 47645}
+
+
+def counters_valid(proc_ir):
+    from paper_1305_0708_amd import codegen
+    return codegen.source_digest(proc_ir) == COUNTERS_FP64["source_digest"]
 
 
 def measured_traffic(proc_ir):
-    from paper_1305_0708_amd import codegen
-    t = TRAFFIC_FP64
-    if codegen.source_digest(proc_ir) != t["source_digest"]:
+    t = COUNTERS_FP64
+    if not counters_valid(proc_ir):
         return None
     return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -223,7 +235,11 @@ def main():
     wall64f, kern64f, _ = time_path(torch, fp64f, args.steps, args.warmup)
     wallmxf, kernmxf, _ = time_path(torch, mixedf, args.steps, args.warmup)
 
-    flop_event = flops.per_event(proc_ir)
+    model_flop_event = flops.per_event(proc_ir)
+    if counters_valid(proc_ir):
+        flop_event, flop_source = COUNTERS_FP64["flop_per_event"], "executed FP64 flops from SQ_INSTS_VALU_*_F64"
+    else:
+        flop_event, flop_source = model_flop_event, "IR flop model (counters taken on another kernel source)"
     achieved = flop_event * N_EVENTS / kern64 / 1e12
     value = N_EVENTS / wall64
     line = {
@@ -246,9 +262,10 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(proc_ir),
                      "traffic_unit": "bytes per launch",
                      "kernel": "amp_gg_ttbar_6f<double>", "kernel_ms": kern64 * 1e3,
-                     "flop_per_event": flop_event},
+                     "flop_per_event": flop_event, "flop_source": flop_source,
+                     "model_flop_per_event": model_flop_event},
         "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,
-                  "achieved_tflops": flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
+                  "model_tflops": model_flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
                   "sigma_pb": rmx["sigma_pb"]},
         "helicity_filtered": {"helicities": nk, "fp64_value": N_EVENTS / wall64f,
                               "mixed_value": N_EVENTS / wallmxf, "fp64_kernel_ms": kern64f * 1e3,
