@@ -319,3 +319,63 @@ def test_helicity_table_path_matches_nest(torch, oracle, name):
     err = rel_err(nest, table)
     print(f"{name}: nest vs table max rel diff {err.max():.2e}")
     assert np.median(err) < 1e-14
+
+
+def _boost(mom, beta):
+    """Lorentz boost of every momentum by velocity beta (3-vector, |beta| < 1)"""
+    b = np.asarray(beta, dtype=float)
+    b2 = b @ b
+    g = 1.0 / math.sqrt(1.0 - b2)
+    E, p = mom[..., 0], mom[..., 1:]
+    bp = p @ b
+    out = mom.copy()
+    out[..., 0] = g * (E + bp)
+    out[..., 1:] = p + (((g - 1.0) * bp / b2 + g * E)[..., None]) * b
+    return out
+
+
+@pytest.mark.parametrize("name,general", [("ud_udhh_4b", True), ("gg_4g", False), ("ee_mumu", True)])
+def test_lorentz_invariance_on_gpu(torch, oracle, name, general):
+    """|M|^2 is a Lorentz scalar: the GPU result on boosted and rotated events
+    equals the GPU result on the originals.  gg -> gggg is boosted along the
+    beam and rotated about it only, which keeps its generation cut
+    (pT, Delta R) unchanged."""
+    _, nout, rs, _, seed, _ = CASES[name]
+    mom = oracle.generate(seed ^ 0xB005, 1024, nout, rs)
+    rng = np.random.default_rng(17)
+    if general:
+        beta = rng.normal(size=3)
+        beta *= 0.9 / np.linalg.norm(beta)
+        moved = random_rotation(_boost(mom, beta), 4)
+    else:
+        moved = _boost(mom, [0.0, 0.0, 0.7])
+        phi = 0.83
+        R = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+        moved[..., 1:3] = moved[..., 1:3] @ R.T
+    p = make(name)
+    a = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+    b = p.eval(momenta=to_soa(torch, moved)).cpu().numpy()
+    assert np.array_equal(a == 0, b == 0)
+    nz = a != 0
+    assert nz.sum() > 500
+    err = rel_err(b[nz], a[nz])
+    print(f"{name}: frame change max rel diff {err.max():.2e}, median {np.median(err):.2e}")
+    # the boost amplifies rounding (energies grow up to x4.4 at beta = 0.9); the gauge
+    # cancellations of ud -> udhh -> 4b leave a frame-dependent FP64 rounding of about
+    # 1e-12 per event (the oracle spreads as much under the same frame change)
+    med, worst = (1e-11, 1e-9) if name == "ud_udhh_4b" else (1e-13, 1e-11)
+    assert np.median(err) < med
+    assert err.max() < worst
+
+
+def test_bose_symmetry_on_gpu(torch, oracle):
+    """gg -> gggg: exchanging final-state gluons leaves |M|^2 unchanged."""
+    _, nout, rs, _, seed, _ = CASES["gg_4g"]
+    mom = oracle.generate(seed ^ 0xB05E, 1024, nout, rs)
+    perm = mom[:, [0, 1, 4, 2, 5, 3], :]
+    p = make("gg_4g")
+    a = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+    b = p.eval(momenta=to_soa(torch, np.ascontiguousarray(perm))).cpu().numpy()
+    assert np.array_equal(a == 0, b == 0)
+    nz = a != 0
+    assert rel_err(b[nz], a[nz]).max() < 1e-12
