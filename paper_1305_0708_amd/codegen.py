@@ -29,6 +29,10 @@ from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
 UNROLL_INNER_COMBINATIONS = 8
+# per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
+# event kinematics: 64 words are 128 KiB per 256-lane block in FP64
+STASH_WORDS = 64
+_KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8}
 
 
 def _c(x):
@@ -58,6 +62,7 @@ class Gen:
     def __init__(self, proc: ir.Process):
         self.p = proc
         self._scope, self._opaque = None, set()
+        self._kin = {}       # event kinematics formed before the helicity loops: name -> type
         self.nl = proc.n_legs
         self.nout = proc.n_legs - 2
         self.ordered = proc.orderings is not None
@@ -221,13 +226,16 @@ class Gen:
         for k, leg in enumerate(self.p.legs):
             if leg.kind == F and leg.particle == P_ZERO:
                 w(f"  const MLF<T> e{k} = mlf_pre<T>(p[{k}]);")
+                self._kin[f"e{k}"] = "MLF<T>"
             elif leg.kind == F:
                 fn = "ixxxxx" if _flowing_in(leg) else "oxxxxx"
                 for lam, tag in ((-1, "m"), (1, "p")):
                     w(f"  const wf<T> e{k}{tag} = cvtw<T>({fn}<double, false>(tv<double>(p[{k}]), "
                       f"pe{leg.particle}.m, {lam}, {leg.flow}));")
+                    self._kin[f"e{k}{tag}"] = "wf<T>"
             elif leg.kind == V:
                 w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
+                self._kin[f"P{k}"] = "vec<T>"
 
     def _external(self, k, leg, name, hel=None):
         hel = hel or f"hh[{k}]"
@@ -255,17 +263,21 @@ class Gen:
                 w(f"{ind}const mom qs{n} = {' + '.join(qname(x) for x in sub)};")
                 if sub in self.need_q:
                     w(f"{ind}const vec<T> Qs{n} = tv<T>(qs{n});")
+                    self._kin[f"Qs{n}"] = "vec<T>"
             if (sub, c.prop) not in done_d:
                 done_d.add((sub, c.prop))
                 pid = c.prop
                 w(f"{ind}const cx<T> d{n}_{pid} = cvt<T>(inv_denominator(qs{n}, cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
+                self._kin[f"d{n}_{pid}"] = "cx<T>"
 
     # ---------------------------------------------------------- straight-line
     def _emit_straight(self, w):
         p = self.p
+        self._kin = {}
         for k in range(self.nl):
             if (k,) in self.need_q:
                 w(f"  const vec<T> Qs{k} = tv<T>(q{k});")
+                self._kin[f"Qs{k}"] = "vec<T>"
         self._current_momenta(w, "  ", lambda x: f"q{x}")
         self._ext_pre(w)
         w("  double me2 = 0.0;")
@@ -312,6 +324,15 @@ class Gen:
                 break
             combos *= n
             unrolled.add(lvl)
+        loads = self._stash_plan(sc, unrolled)
+        if loads:
+            words = sum(_KIN_WORDS[self._kin[nm]] for L in loads.values() for nm, _ in L)
+            w(f"{ind}// kinematics used only inside the helicity loops wait in LDS and are read")
+            w(f"{ind}// back in the loop that first needs them, instead of occupying registers")
+            w(f"{ind}__shared__ T stash[{words}][256];")
+            for L in loads.values():
+                for nm, off in L:
+                    w(f"{ind}stash_put(stash, {off}, {nm});")
         for lvl, L in enumerate(sc.order):
             ch = sc.choices[L]
             if len(ch) == 1:
@@ -326,6 +347,8 @@ class Gen:
                     w(f"{ind}const int hh{L} = c{L} - 1;")
                 else:
                     raise NotImplementedError(f"helicity states {ch}")
+            for nm, off in loads.get(lvl, []):
+                w(f"{ind}const {self._kin[nm]} {nm} = stash_get<{self._kin[nm]}>(stash, {off});")
             for it in by_level.get(lvl, []):
                 self._nest_item(w, it, ind)
         self._colour(w, lambda f: f"J{f}", ind)
@@ -333,6 +356,45 @@ class Gen:
             if len(sc.choices[L]) > 1:
                 ind = ind[:-2]
                 w(f"{ind}}}")
+
+    def _stash_plan(self, sc, unrolled):
+        """Which event kinematics go to the LDS stash, and the loop level that
+        reads each back: a value qualifies when every item using it sits inside
+        a real (not unrolled) helicity loop or depends on one.  Values that feed
+        items depending only on unrolled legs stay in registers (the compiler
+        hoists those items out of the loops).  Outer loops first, up to
+        STASH_WORDS words.  Returns {level: [(name, word offset), ...]}."""
+        import re
+        real = [lvl for lvl, L in enumerate(sc.order) if len(sc.choices[L]) > 1 and lvl not in unrolled]
+        if not real or not self._kin:
+            return {}
+        first_real, last_real = real[0], real[-1]
+        real_hh = {f"hh{sc.order[lvl]}" for lvl in real}
+        varying = set()
+        uses = {}
+        for it in sc.items:
+            buf = []
+            self._nest_item(buf.append, it, "")
+            code = "\n".join(buf)
+            toks = set(re.findall(r"[A-Za-z_]\w*", code))
+            defined = set(re.findall(r"const \S+ (\w+) =", code))
+            rv = bool(toks & (varying | real_hh))
+            if rv:
+                varying |= defined
+            for nm in toks & self._kin.keys():
+                uses.setdefault(nm, []).append((it.level, rv))
+        cand = []
+        for nm, us in uses.items():
+            if all(rv and lvl >= first_real for lvl, rv in us):
+                cand.append((min(min(lvl for lvl, _ in us), last_real), nm))
+        loads, off = {}, 0
+        for lvl, nm in sorted(cand, key=lambda c: (c[0], list(self._kin).index(c[1]))):
+            n = _KIN_WORDS[self._kin[nm]]
+            if off + n > STASH_WORDS:
+                continue
+            loads.setdefault(lvl, []).append((nm, off))
+            off += n
+        return loads
 
     @staticmethod
     def _nest_arg(a):

@@ -59,6 +59,30 @@ __device__ __forceinline__ void store_momenta(const KernelArgs& a, int64_t i, co
   }
 }
 
+// Per-lane LDS stash of an event value made of words of type T (column
+// threadIdx.x of a [words][256] array: consecutive lanes hit consecutive
+// banks).  stash_get builds its address from an opaque offset, so a read placed
+// inside a loop stays in that loop: the value is not kept in registers across
+// the outer loops.  Each lane reads back only what it wrote itself.
+template <class T, class V>
+__device__ __forceinline__ void stash_put(T (*s)[256], int off, const V& v) {
+  static_assert(sizeof(V) % sizeof(T) == 0, "a stashed value is a whole number of words");
+  T w[sizeof(V) / sizeof(T)];
+  __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+  for (int j = 0; j < int(sizeof(V) / sizeof(T)); ++j) s[off + j][threadIdx.x] = w[j];
+}
+template <class V, class T>
+__device__ __forceinline__ V stash_get(T (*s)[256], int off) {
+  const int b = opaque_int(off);
+  T w[sizeof(V) / sizeof(T)];
+#pragma unroll
+  for (int j = 0; j < int(sizeof(V) / sizeof(T)); ++j) w[j] = s[b + j][threadIdx.x];
+  V v;
+  __builtin_memcpy(&v, w, sizeof(V));
+  return v;
+}
+
 // Deterministic per-block partial sums (w, w^2, accepted) for the cross
 // section: a fixed butterfly inside each 64-lane wavefront, then the waves in
 // order.  Every thread of the block must call it; blk is the block's index
