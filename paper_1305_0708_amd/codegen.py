@@ -32,7 +32,7 @@ UNROLL_INNER_COMBINATIONS = 8
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
-_KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8}
+_KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8, "VPol<T>": 5}
 
 
 def _c(x):
@@ -236,8 +236,13 @@ class Gen:
             elif leg.kind == V:
                 w(f"  const vec<T> P{k} = tv<T>(p[{k}]);")
                 self._kin[f"P{k}"] = "vec<T>"
+                if leg.particle == P_ZERO:
+                    w(f"  const VPol<T> V{k} = vpol_pre<T>(p[{k}]);")
+                    self._kin[f"V{k}"] = "VPol<T>"
 
-    def _external(self, k, leg, name, hel=None):
+    def _external(self, k, leg, name, hel=None, nest=False):
+        """external wavefunction; in the helicity nest a massless vector is
+        built from its precomputed polarisation factors (helicities +-1 only)"""
         hel = hel or f"hh[{k}]"
         if leg.kind == F:
             if leg.particle == P_ZERO:
@@ -246,6 +251,8 @@ class Gen:
             return f"const wf<T> {name} = {hel} > 0 ? e{k}p : e{k}m;"
         if leg.kind == V:
             nsv = -1 if leg.incoming else 1
+            if nest and leg.particle == P_ZERO:
+                return f"const wf<T> {name} = vxxxxx0<T>(V{k}, {hel}, {nsv});"
             return f"const wf<T> {name} = vxxxxx<T>(P{k}, T(pe{leg.particle}.m), {hel}, {nsv});"
         return f"const cx<T> {name} = sxxxxx<T>();"
 
@@ -406,7 +413,7 @@ class Gen:
         p = self.p
         if it.kind == "ext":
             (L,) = it.data
-            w(ind + self._external(L, p.legs[L], f"w{L}", f"hh{L}"))
+            w(ind + self._external(L, p.legs[L], f"w{L}", f"hh{L}", nest=True))
         elif it.kind == "call":
             k, args = it.data
             self._call(w, p.calls[k], ind, args=[self._nest_arg(a) for a in args])

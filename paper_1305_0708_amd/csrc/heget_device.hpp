@@ -357,6 +357,44 @@ __device__ __forceinline__ wf<T> vxxxxx(vec<T> k, T m, int lam, int nsv) {
   return v;
 }
 
+// Helicity-independent part of a massless vector's transverse polarisations:
+// (1/sqrt2) x (cos th cos ph, cos th sin ph, sin th, sin ph, cos ph), formed
+// in FP64 from the FP64 momentum exactly as vxxxxx forms them.
+template <class T>
+struct VPol {
+  T a, b, c, d, e;
+};
+template <class T>
+__device__ __forceinline__ VPol<T> vpol_pre(mom p) {
+  const double pt2 = p.x * p.x + p.y * p.y;
+  const double pt = sqrt(pt2);
+  const double pp = sqrt(pt2 + p.z * p.z);
+  double ct = 1.0, st = 0.0, cp = 1.0, sp = 0.0;
+  if (pp > 0.0) {
+    ct = p.z / pp;
+    st = pt / pp;
+  }
+  if (pt > 0.0) {
+    cp = p.x / pt;
+    sp = p.y / pt;
+  }
+  const double h = 0.70710678118654752440;
+  return {T(h * ct * cp), T(h * ct * sp), T(h * st), T(h * sp), T(h * cp)};
+}
+// eps(k, lam), lam = +-1, of a massless vector from its precomputed factors
+// (the same vector as vxxxxx(k, 0, lam, nsv))
+template <class T>
+__device__ __forceinline__ wf<T> vxxxxx0(const VPol<T>& q, int lam, int nsv) {
+  const T l = T(lam);
+  const T s = nsv > 0 ? T(-1) : T(1);
+  wf<T> v;
+  v.c[0] = mk<T>(T(0), T(0));
+  v.c[1] = mk<T>(-l * q.a, s * q.d);
+  v.c[2] = mk<T>(-l * q.b, -s * q.e);
+  v.c[3] = mk<T>(l * q.c, T(0));
+  return v;
+}
+
 // Scalar external line: the component is 1.
 template <class T>
 __device__ __forceinline__ cx<T> sxxxxx() { return mk<T>(T(1), T(0)); }
