@@ -32,6 +32,9 @@ UNROLL_INNER_COMBINATIONS = 8
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
+# tabulate calls fed only by external wavefunctions whose loop does not vary
+# them, up to this many table words per lane (in the arithmetic type)
+TABLE_WORDS = 32
 _KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8, "VPol<T>": 5}
 
 
@@ -331,7 +334,8 @@ class Gen:
                 break
             combos *= n
             unrolled.add(lvl)
-        loads = self._stash_plan(sc, unrolled)
+        tables = self._tables(sc, unrolled)
+        loads = self._stash_plan(sc, unrolled, tables)
         if loads:
             words = sum(_KIN_WORDS[self._kin[nm]] for L in loads.values() for nm, _ in L)
             w(f"{ind}// kinematics used only inside the helicity loops wait in LDS and are read")
@@ -340,6 +344,7 @@ class Gen:
             for L in loads.values():
                 for nm, off in L:
                     w(f"{ind}stash_put(stash, {off}, {nm});")
+        self._emit_tables(w, sc, tables, ind)
         for lvl, L in enumerate(sc.order):
             ch = sc.choices[L]
             if len(ch) == 1:
@@ -357,14 +362,94 @@ class Gen:
             for nm, off in loads.get(lvl, []):
                 w(f"{ind}const {self._kin[nm]} {nm} = stash_get<{self._kin[nm]}>(stash, {off});")
             for it in by_level.get(lvl, []):
-                self._nest_item(w, it, ind)
+                if id(it) in tables:
+                    w(ind + self._table_select(it, tables[id(it)]))
+                else:
+                    self._nest_item(w, it, ind)
         self._colour(w, lambda f: f"J{f}", ind)
         for L in reversed(sc.order):
             if len(sc.choices[L]) > 1:
                 ind = ind[:-2]
                 w(f"{ind}}}")
 
-    def _stash_plan(self, sc, unrolled):
+    def _tables(self, sc, unrolled):
+        """Calls evaluated in a real helicity loop whose value does not vary
+        with some enclosing real loop, and whose inputs are all external
+        wavefunctions: they are evaluated once per combination of their own
+        legs' helicities before the loops (a table) and picked by the loop
+        counters where the nest needs them.  Returns {id(item): legs}, the
+        legs outermost first."""
+        p = self.p
+        pos = {L: i for i, L in enumerate(sc.order)}
+        real = {lvl for lvl, L in enumerate(sc.order) if len(sc.choices[L]) > 1 and lvl not in unrolled}
+        mult, m = {}, 1
+        for lvl, L in enumerate(sc.order):
+            m *= len(sc.choices[L])
+            mult[lvl] = m
+        cand = []
+        for it in sc.items:
+            if it.kind != "call" or it.level not in real:
+                continue
+            k, args = it.data
+            legs = [a[1] for a in args if a is not nest.ONE]
+            if any(a is not nest.ONE and (a[0] != "w" or a[1] >= self.nl) for a in args):
+                continue
+            legs = sorted(set(legs), key=lambda L: pos[L])
+            if not legs or any(pos[L] not in real or sc.choices[L] != (-1, 1) for L in legs):
+                continue
+            enclosing = {sc.order[lvl] for lvl in real if lvl <= it.level}
+            if enclosing <= set(legs):
+                continue
+            entries = 2 ** len(legs)
+            words = entries * (2 if ir.OUT_KIND[p.calls[k].op] == S else 8)
+            saved = (mult[it.level] - entries) * it.flops
+            cand.append((saved, words, id(it), legs))
+        out, used = {}, 0
+        for saved, words, key, legs in sorted(cand, key=lambda c: -c[0]):
+            if saved > 0 and used + words <= TABLE_WORDS:
+                out[key] = legs
+                used += words
+        return out
+
+    def _emit_tables(self, w, sc, tables, ind):
+        if not tables:
+            return
+        import itertools
+        p = self.p
+        w(f"{ind}// calls fed by external states only, tabulated over their own legs' helicities")
+        done = set()
+        for it in sc.items:
+            if id(it) not in tables:
+                continue
+            legs = tables[id(it)]
+            for L in legs:
+                for h, tag in ((-1, "m"), (1, "p")):
+                    if (L, h) not in done:
+                        done.add((L, h))
+                        w(ind + self._external(L, p.legs[L], f"x{L}{tag}", str(h), nest=True))
+            k, args = it.data
+            o = p.calls[k].out
+            for j, hs in enumerate(itertools.product((-1, 1), repeat=len(legs))):
+                tag = {L: ("m" if h < 0 else "p") for L, h in zip(legs, hs)}
+                buf = []
+                self._call(buf.append, p.calls[k], ind,
+                           args=["mk<T>(T(1), T(0))" if a is nest.ONE else f"x{a[1]}{tag[a[1]]}" for a in args])
+                line = buf[0]
+                head = f"{ind}const wf<T> w{o} = " if f"const wf<T> w{o} = " in line else f"{ind}const cx<T> w{o} = "
+                assert line.startswith(head), line
+                w(line.replace(f" w{o} = ", f" t{o}_{j} = ", 1))
+
+    def _table_select(self, it, legs):
+        o = self.p.calls[it.data[0]].out
+
+        def sel(k, j):
+            if k == len(legs):
+                return f"t{o}_{j}"
+            return f"(c{legs[k]} ? {sel(k + 1, 2 * j + 1)} : {sel(k + 1, 2 * j)})"
+        kind = "cx<T>" if ir.OUT_KIND[self.p.calls[it.data[0]].op] == S else "wf<T>"
+        return f"const {kind} w{o} = {sel(0, 0)};"
+
+    def _stash_plan(self, sc, unrolled, tables=None):
         """Which event kinematics go to the LDS stash, and the loop level that
         reads each back: a value qualifies when every item using it sits inside
         a real (not unrolled) helicity loop or depends on one.  Values that feed
@@ -379,12 +464,18 @@ class Gen:
         real_hh = {f"hh{sc.order[lvl]}" for lvl in real}
         varying = set()
         uses = {}
+        tables = tables or {}
         for it in sc.items:
             buf = []
             self._nest_item(buf.append, it, "")
             code = "\n".join(buf)
             toks = set(re.findall(r"[A-Za-z_]\w*", code))
             defined = set(re.findall(r"const \S+ (\w+) =", code))
+            if id(it) in tables:
+                varying |= defined
+                for nm in toks & self._kin.keys():
+                    uses.setdefault(nm, []).append((-1, False))
+                continue
             rv = bool(toks & (varying | real_hh))
             if rv:
                 varying |= defined
