@@ -40,9 +40,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts.
-COUNTERS_FP64 = {"source_digest": "025256a910918ef879c1995fbf82a7dc5529c685522880899edd8d8b767aefb4",
-                 "fetch_kib": 119574.5, "fetch_scale": 2.0, "write_kib": 855300.2, "write_scale": 1.0,
-                 "flop_per_event": 47645}
+COUNTERS_FP64 = {"source_digest": "b532f2ae43aa0f9451d78c3a7676f781ffbe1cbcdabab30eddee72d14b2c2693",
+                 "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
+                 "flop_per_event": 41174}
 
 
 def counters_valid(proc_ir):

@@ -28,13 +28,9 @@ from . import ir, nest
 from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
-UNROLL_INNER_COMBINATIONS = 8
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
-# tabulate calls fed only by external wavefunctions whose loop does not vary
-# them, up to this many table words per lane (in the arithmetic type)
-TABLE_WORDS = 32
 _KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8, "VPol<T>": 5}
 
 
@@ -327,13 +323,7 @@ class Gen:
         # the innermost loops (up to 8 combinations) are unrolled: constant
         # helicities there let the compiler specialise the external states and
         # interleave the independent iterations
-        unrolled, combos = set(), 1
-        for lvl in reversed(range(len(sc.order))):
-            n = len(sc.choices[sc.order[lvl]])
-            if combos * n > UNROLL_INNER_COMBINATIONS:
-                break
-            combos *= n
-            unrolled.add(lvl)
+        unrolled = nest.unrolled_levels(sc)
         tables = self._tables(sc, unrolled)
         loads = self._stash_plan(sc, unrolled, tables)
         if loads:
@@ -344,7 +334,7 @@ class Gen:
             for L in loads.values():
                 for nm, off in L:
                     w(f"{ind}stash_put(stash, {off}, {nm});")
-        self._emit_tables(w, sc, tables, ind)
+        self._emit_tables(w, sc, tables, ind, -1)
         for lvl, L in enumerate(sc.order):
             ch = sc.choices[L]
             if len(ch) == 1:
@@ -366,6 +356,7 @@ class Gen:
                     w(ind + self._table_select(it, tables[id(it)]))
                 else:
                     self._nest_item(w, it, ind)
+            self._emit_tables(w, sc, tables, ind, lvl)
         self._colour(w, lambda f: f"J{f}", ind)
         for L in reversed(sc.order):
             if len(sc.choices[L]) > 1:
@@ -373,55 +364,19 @@ class Gen:
                 w(f"{ind}}}")
 
     def _tables(self, sc, unrolled):
-        """Calls evaluated in a real helicity loop whose value does not vary
-        with some enclosing real loop, and whose inputs are all external
-        wavefunctions: they are evaluated once per combination of their own
-        legs' helicities before the loops (a table) and picked by the loop
-        counters where the nest needs them.  Returns {id(item): legs}, the
-        legs outermost first."""
-        p = self.p
-        pos = {L: i for i, L in enumerate(sc.order)}
-        real = {lvl for lvl, L in enumerate(sc.order) if len(sc.choices[L]) > 1 and lvl not in unrolled}
-        mult, m = {}, 1
-        for lvl, L in enumerate(sc.order):
-            m *= len(sc.choices[L])
-            mult[lvl] = m
-        cand = []
-        for it in sc.items:
-            if it.kind != "call" or it.level not in real:
-                continue
-            k, args = it.data
-            legs = [a[1] for a in args if a is not nest.ONE]
-            if any(a is not nest.ONE and (a[0] != "w" or a[1] >= self.nl) for a in args):
-                continue
-            legs = sorted(set(legs), key=lambda L: pos[L])
-            if not legs or any(pos[L] not in real or sc.choices[L] != (-1, 1) for L in legs):
-                continue
-            enclosing = {sc.order[lvl] for lvl in real if lvl <= it.level}
-            if enclosing <= set(legs):
-                continue
-            entries = 2 ** len(legs)
-            words = entries * (2 if ir.OUT_KIND[p.calls[k].op] == S else 8)
-            saved = (mult[it.level] - entries) * it.flops
-            cand.append((saved, words, id(it), legs))
-        out, used = {}, 0
-        for saved, words, key, legs in sorted(cand, key=lambda c: -c[0]):
-            if saved > 0 and used + words <= TABLE_WORDS:
-                out[key] = legs
-                used += words
-        return out
+        return {key: (t[0], t[1]) for key, t in nest.tables(self.p, sc, unrolled).items()}
 
-    def _emit_tables(self, w, sc, tables, ind):
-        if not tables:
-            return
+    def _emit_tables(self, w, sc, tables, ind, level):
+        """the tables formed at this loop level (-1: before the loops)"""
         import itertools
         p = self.p
-        w(f"{ind}// calls fed by external states only, tabulated over their own legs' helicities")
+        mine = [it for it in sc.items if id(it) in tables and tables[id(it)][0] == level]
+        if not mine:
+            return
+        w(f"{ind}// calls tabulated over the helicities of deeper external legs")
         done = set()
-        for it in sc.items:
-            if id(it) not in tables:
-                continue
-            legs = tables[id(it)]
+        for it in mine:
+            legs = tables[id(it)][1]
             for L in legs:
                 for h, tag in ((-1, "m"), (1, "p")):
                     if (L, h) not in done:
@@ -432,14 +387,21 @@ class Gen:
             for j, hs in enumerate(itertools.product((-1, 1), repeat=len(legs))):
                 tag = {L: ("m" if h < 0 else "p") for L, h in zip(legs, hs)}
                 buf = []
-                self._call(buf.append, p.calls[k], ind,
-                           args=["mk<T>(T(1), T(0))" if a is nest.ONE else f"x{a[1]}{tag[a[1]]}" for a in args])
+                argv = []
+                for a in args:
+                    if a is nest.ONE:
+                        argv.append("mk<T>(T(1), T(0))")
+                    elif a[1] in tag:
+                        argv.append(f"x{a[1]}{tag[a[1]]}")
+                    else:
+                        argv.append(f"w{a[1]}")
+                self._call(buf.append, p.calls[k], ind, args=argv)
                 line = buf[0]
-                head = f"{ind}const wf<T> w{o} = " if f"const wf<T> w{o} = " in line else f"{ind}const cx<T> w{o} = "
-                assert line.startswith(head), line
+                assert f" w{o} = " in line, line
                 w(line.replace(f" w{o} = ", f" t{o}_{j} = ", 1))
 
-    def _table_select(self, it, legs):
+    def _table_select(self, it, table):
+        legs = table[1]
         o = self.p.calls[it.data[0]].out
 
         def sel(k, j):
@@ -473,8 +435,9 @@ class Gen:
             defined = set(re.findall(r"const \S+ (\w+) =", code))
             if id(it) in tables:
                 varying |= defined
+                tlev = tables[id(it)][0]
                 for nm in toks & self._kin.keys():
-                    uses.setdefault(nm, []).append((-1, False))
+                    uses.setdefault(nm, []).append((tlev, tlev >= 0))
                 continue
             rv = bool(toks & (varying | real_hh))
             if rv:

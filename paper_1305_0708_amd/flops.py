@@ -108,11 +108,14 @@ def colour_mfma_flops_executed(proc):
 def per_event(proc, n_hel=None):
     """flops of one event: the helicity sum plus the per-event denominators.
     With the full helicity product (n_hel None) a straight-line IR runs as the
-    helicity loop nest (nest.plan); a table of n_hel rows runs row by row."""
+    helicity loop nest (nest.schedule, less what its call tables save); a
+    table of n_hel rows runs row by row."""
     n_cur = sum(1 for c in proc.calls if c.op not in AMP_OPS and c.op not in ("vadd", "vsub"))
     if n_hel is None and not proc.orderings:
         from . import nest
-        return nest.schedule(proc).flops_per_event + n_cur * (7 + 8)
+        sc = nest.schedule(proc)
+        saved = sum(t[2] for t in nest.tables(proc, sc, nest.unrolled_levels(sc)).values())
+        return sc.flops_per_event - saved + n_cur * (7 + 8)
     if n_hel is None:
         # ordering template: per ordering, the momenta and denominators once and
         # the helicity nest; per helicity, the colour form over all orderings

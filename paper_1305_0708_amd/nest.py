@@ -121,6 +121,11 @@ def plan(proc):
     return Plan(order, choices, call_level, {L: pos[L] for L in range(nl)}, _cost(order, *args), bra_level)
 
 
+# innermost loops unrolled up to this many helicity combinations
+UNROLL_INNER_COMBINATIONS = 8
+# tables of calls: at most this many words per lane (in the arithmetic type)
+TABLE_WORDS = 48
+
 # ------------------------------------------------------------------ schedule
 ONE = None   # an argument slot replaced by the scalar 1 (its value deferred as a factor)
 
@@ -255,6 +260,65 @@ def schedule(proc):
     colour = nf * 4 + (nf * (nf - 1) // 2) * 4 + 2
     total = sum(it.flops * mult[it.level] for it in items) + colour * mult[inner]
     return Schedule(pl.order, pl.choices, items, total)
+
+
+def unrolled_levels(sc):
+    """the innermost loop levels, up to UNROLL_INNER_COMBINATIONS helicity
+    combinations, that the kernel unrolls (constant helicities there)"""
+    unrolled, combos = set(), 1
+    for lvl in reversed(range(len(sc.order))):
+        n = len(sc.choices[sc.order[lvl]])
+        if combos * n > UNROLL_INNER_COMBINATIONS:
+            break
+        combos *= n
+        unrolled.add(lvl)
+    return unrolled
+
+
+def tables(proc, sc, unrolled):
+    """Calls evaluated in a real (not unrolled) helicity loop whose value does
+    not vary with some loop between it and its inputs.  A call whose inputs
+    are values of the loops down to level k plus external states of deeper
+    legs is evaluated at level k for every combination of those legs'
+    helicities (a table; k = -1 is before the loops) and picked by the loop
+    counters where the nest needs it.  Tables are ranked by the flops they
+    save, up to TABLE_WORDS words per lane.
+    Returns {id(item): (k, legs outermost first, flops saved per event)}."""
+    nl = proc.n_legs
+    pos = {L: i for i, L in enumerate(sc.order)}
+    real = {lvl for lvl, L in enumerate(sc.order) if len(sc.choices[L]) > 1 and lvl not in unrolled}
+    mult, m = {-1: 1}, 1
+    for lvl, L in enumerate(sc.order):
+        m *= len(sc.choices[L])
+        mult[lvl] = m
+    slot_level = {L: pos[L] for L in range(nl)}
+    for it in sc.items:
+        if it.kind == "call" and proc.calls[it.data[0]].op not in AMP_OPS:
+            slot_level[proc.calls[it.data[0]].out] = it.level
+    cand = []
+    for it in sc.items:
+        if it.kind != "call" or it.level not in real:
+            continue
+        k, args = it.data
+        if any(a is not ONE and a[0] != "w" for a in args):
+            continue
+        slots = [a[1] for a in args if a is not ONE]
+        tlev = max((slot_level[x] for x in slots if x >= nl), default=-1)
+        legs = sorted({x for x in slots if x < nl and pos[x] > tlev}, key=lambda L: pos[L])
+        if not legs or any(pos[L] not in real or sc.choices[L] != (-1, 1) for L in legs):
+            continue
+        entries = 2 ** len(legs)
+        saved = (mult[it.level] - mult[tlev] * entries) * it.flops
+        if saved <= 0:
+            continue
+        words = entries * (2 if OUT_KIND[proc.calls[k].op] == S else 8)
+        cand.append((saved, words, id(it), tlev, legs))
+    out, used = {}, 0
+    for saved, words, key, tlev, legs in sorted(cand, key=lambda c: -c[0]):
+        if used + words <= TABLE_WORDS:
+            out[key] = (tlev, legs, saved)
+            used += words
+    return out
 
 
 # ------------------------------------------------- ordering templates (C2)
