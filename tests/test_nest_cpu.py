@@ -56,3 +56,51 @@ def test_nest_does_less_work(name):
 def test_ordering_templates_have_no_nest():
     with pytest.raises(ValueError):
         nest.plan(processes.by_name("gg_4g"))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_tables_are_valid(name):
+    """A tabulated call: every input is an external state of a tabulated leg
+    (deeper than the table's level, in a real two-state loop) or a value ready
+    at the table's level; the call's own loop varies with something the table
+    does not, so the table saves evaluations; the budget holds."""
+    p = processes.by_name(name)
+    sc = nest.schedule(p)
+    un = nest.unrolled_levels(sc)
+    pos = {L: i for i, L in enumerate(sc.order)}
+    ready = {k: pos[k] for k in range(p.n_legs)}
+    for it in sc.items:
+        if it.kind == "call" and p.calls[it.data[0]].op not in ir.AMP_OPS:
+            ready[p.calls[it.data[0]].out] = it.level
+    items = {id(it): it for it in sc.items}
+    words = 0
+    for key, (tlev, legs, saved) in nest.tables(p, sc, un).items():
+        it = items[key]
+        assert it.kind == "call" and saved > 0
+        assert tlev < it.level and it.level not in un
+        for L in legs:
+            assert tlev < pos[L] <= it.level and pos[L] not in un and sc.choices[L] == (-1, 1)
+        for a in it.data[1]:
+            if a is nest.ONE:
+                continue
+            assert a[1] in legs or ready[a[1]] <= tlev
+        words += 2 ** len(legs) * 8
+    assert words <= nest.TABLE_WORDS
+
+
+def test_c1_tables_and_stash_in_the_generated_kernel():
+    """C1: the gg -> g* current is tabulated before the loops over both gluon
+    helicities and the top current over gluon 1 inside the b-quark loop; the
+    stash fits its budget and the flop model counts the tables."""
+    from paper_1305_0708_amd import codegen
+    p = processes.by_name("gg_ttbar_6f")
+    src = codegen.Gen(p).emit()
+    assert "jvvxxx<T, false>(x0m, Qs0, x1m, Qs1" in src
+    assert "(c0 ? (c1 ? t12_3 : t12_2) : (c1 ? t12_1 : t12_0))" in src
+    assert "(c1 ? t14_1 : t14_0)" in src
+    import re
+    m = re.search(r"__shared__ T stash\[(\d+)\]\[256\]", src)
+    assert m and int(m.group(1)) <= codegen.STASH_WORDS
+    assert src.count("stash_get<") == src.count("stash_put(")
+    sc = nest.schedule(p)
+    assert flops.per_event(p) < sc.flops_per_event
