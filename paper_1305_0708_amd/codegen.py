@@ -28,6 +28,15 @@ from . import ir, nest
 from .ir import F, V, S, AMP_OPS, LINEAR_OPS, P_ZERO, P_W, P_Z
 
 MASSIVE_VECTORS = {P_W, P_Z}
+# ordering templates: recompute the momenta and denominators a call needs in
+# the loop of the call instead of carrying them from the loop that first formed them
+TEMPLATE_KIN_PER_LEVEL = True
+# ordering templates: per-lane LDS words (in the arithmetic type) for currents
+# that outer helicity loops form and inner loops read (shared with the colour
+# form's amplitude rows, which are used after the orderings).  FP64 only: the
+# FP32 kernels hold these currents in registers without spilling, and there
+# the opaque reads cost more than they save.
+TEMPLATE_STASH_WORDS = 48
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
@@ -151,10 +160,11 @@ class Gen:
         for k, leg in enumerate(p.legs):
             w(f"  const mom q{k} = {'p[%d]' % k if leg.incoming else '-p[%d]' % k};")
         if self.ordered:
-            w(f"  // the event's momenta in LDS: read per ordering and loop, not held in registers")
+            w(f"  // the event's momenta flowing into the diagram, in LDS: read per ordering and")
+            w(f"  // loop, not held in registers")
             w(f"  __shared__ mom pm[{self.nl}][256];")
-            w("#pragma unroll")
-            w(f"  for (int k = 0; k < {self.nl}; ++k) pm[k][threadIdx.x] = p[k];")
+            for k in range(self.nl):
+                w(f"  pm[{k}][threadIdx.x] = q{k};")
             self._emit_ordered(w)
         else:
             self._emit_straight(w)
@@ -515,6 +525,13 @@ class Gen:
         if any(leg.kind == F for leg in p.legs):
             raise NotImplementedError("ordering templates support vector and scalar legs")
         mf = p.uses_colour_mfma()
+        self._template_stash_plan()
+        rows = 2 * no if mf else 0
+        if self._tstash_words or rows:
+            w("  // per-lane LDS rows (column = lane): the helicity nest's stash of outer")
+            w("  // currents while the orderings run (FP64), then the amplitude rows of the colour form")
+            w(f"  constexpr bool kStash = {'sizeof(T) == 8' if self._tstash_words else 'false'};")
+            w(f"  __shared__ T lds_rows[kStash ? {max(rows, self._tstash_words)} : {max(rows, 1)}][256];")
         w("  // this block's workspace slot: A[o][h][256] of its events")
         w("  cx<T>* const work = static_cast<cx<T>*>(a.work) + size_t(blockIdx.x) * size_t(a.work_stride);")
         w("  const int nh = a.n_hel;")
@@ -525,7 +542,14 @@ class Gen:
         ind = "      "
         self._bind_positions(w, ind)
         w(f"{ind}if (a.hel_nest) {{")
-        self._emit_template_nest(w, ind + "  ")
+        if self._tstash_words:
+            w(f"{ind}  if constexpr (kStash) {{")
+            self._emit_template_nest(w, ind + "    ")
+            w(f"{ind}  }} else {{")
+            self._emit_template_nest(w, ind + "    ", use_stash=False)
+            w(f"{ind}  }}")
+        else:
+            self._emit_template_nest(w, ind + "  ")
         w(f"{ind}}} else {{")
         w(f"{ind}  for (int h = 0; h < nh; ++h) {{")
         w(f"{ind}    const int8_t* hh = a.hel + h * {nl};")
@@ -548,16 +572,18 @@ class Gen:
         w("  double me2 = 0.0;")
         if mf:
             nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
-            w(f"  __shared__ cx<T> jl[{no}][256];")
             w("  // the MFMA colour form needs every lane of the wavefront: failed lanes take part with zeros")
             w("  if (__any(pass)) {")
             w("    for (int h = 0; h < nh; ++h) {")
-            w(f"      for (int o = 0; o < {no}; ++o)")
-            w("        jl[o][threadIdx.x] = pass ? work[(size_t(o) * nh + h) * 256 + threadIdx.x] : cx<T>{T(0), T(0)};")
+            w(f"      for (int o = 0; o < {no}; ++o) {{")
+            w("        const cx<T> v = pass ? work[(size_t(o) * nh + h) * 256 + threadIdx.x] : cx<T>{T(0), T(0)};")
+            w("        lds_rows[2 * o][threadIdx.x] = v.r;")
+            w("        lds_rows[2 * o + 1][threadIdx.x] = v.i;")
+            w("      }")
             w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
             w("      __builtin_amdgcn_wave_barrier();")
             w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
-            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}>(&jl[0][0], a.cstep, a));")
+            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}>(&lds_rows[0][0], a.cstep, a));")
             w("      __builtin_amdgcn_wave_barrier();")
             w("    }")
             w("  }")
@@ -598,8 +624,9 @@ class Gen:
                     self._pos_nsv[k] = f"nsv{k}"
 
     def _pmom(self, k, w, ind):
-        """physical momentum of position k in the current loop scope (an LDS
-        read behind an opaque leg index, so that it is not hoisted)"""
+        """momentum flowing into the diagram at position k in the current loop
+        scope (an LDS read behind an opaque leg index, so that it is not
+        hoisted); the LDS copy holds +p for incoming and -p for outgoing legs"""
         key = (k, self._scope)
         if key not in self._opaque:
             self._opaque.add(key)
@@ -608,6 +635,10 @@ class Gen:
 
     def _qterm(self, k, w, ind):
         """momentum of position k flowing into the diagram"""
+        return self._pmom(k, w, ind)
+
+    def _physical(self, k, w, ind):
+        """physical momentum of position k"""
         name = self._pmom(k, w, ind)
         sg = self._pos_sign[k]
         if sg == "+":
@@ -651,15 +682,54 @@ class Gen:
         p = self.p
         leg = p.legs[p.orderings[0][k]]
         if leg.kind == V:
-            return (f"const wf<T> w{k} = vxxxxx<T>(tv<T>({self._pmom(k, self._w, self._ind)}), T(pe{leg.particle}.m), "
+            return (f"const wf<T> w{k} = vxxxxx<T>(tv<T>({self._physical(k, self._w, self._ind)}), T(pe{leg.particle}.m), "
                     f"hp{k}, {self._pos_nsv[k]});")
         return f"const cx<T> w{k} = sxxxxx<T>();"
 
-    def _emit_template_nest(self, w, ind):
+    def _template_stash_plan(self):
+        """Which currents of the template nest wait in LDS: a current formed in
+        one loop and read in deeper loops is written once where it is formed
+        and read back at the top of every deeper loop that uses it, so it does
+        not occupy registers across the loops in between.  Outer currents
+        first, up to TEMPLATE_STASH_WORDS words per lane."""
+        import re
+        self._tstash_loads, self._tstash_puts, self._tstash_words = {}, {}, 0
+        rec = []
+        self._bind_positions(lambda line: None, "")
+        self._emit_template_nest(lambda line: None, "", record=rec)
+        items = {}
+        for lvl, idx, line in rec:
+            items.setdefault((lvl, idx), []).append(line)
+        defs, uses = {}, {}
+        for (lvl, idx), lines in sorted(items.items()):
+            code = "\n".join(lines)
+            for nm in re.findall(r"const wf<T> (\w+) =", code):
+                defs[nm] = (lvl, idx)
+            for t in set(re.findall(r"[A-Za-z_]\w*", code)):
+                uses.setdefault(t, set()).add(lvl)
+        cand = []
+        for nm, (lvl, idx) in defs.items():
+            deeper = sorted(l for l in uses.get(nm, ()) if l > lvl)
+            if deeper:
+                cand.append((lvl, -len(deeper), nm, idx, deeper))
+        off = 0
+        for lvl, _, nm, idx, deeper in sorted(cand):
+            if off + 8 > TEMPLATE_STASH_WORDS:
+                break
+            self._tstash_puts.setdefault((lvl, idx), []).append((nm, off))
+            for l in deeper:
+                self._tstash_loads.setdefault(l, []).append((nm, off))
+            off += 8
+        self._tstash_words = off
+
+    def _emit_template_nest(self, w, ind, record=None, use_stash=True):
         """one ordering's helicity sum as a loop nest over the positions
         (nest.template_schedule); the row of the workspace is the helicity
         combination's index in the canonical table of the legs"""
         p = self.p
+        stash = record is None and use_stash
+        loads = getattr(self, "_tstash_loads", {}) if stash else {}
+        puts = getattr(self, "_tstash_puts", {}) if stash else {}
         nl = self.nl
         sc = nest.template_schedule(p)
         by_level = {}
@@ -688,8 +758,17 @@ class Gen:
             w(f"{ind}const int r{lvl} = {prev} + (c{k} << ({nl - 1} - lk{k}));")
             prev = f"r{lvl}"
             self._scope = lvl
-            for it in by_level.get(lvl, []):
+            if TEMPLATE_KIN_PER_LEVEL:
+                self._done = set()
+            for nm, off in loads.get(lvl, []):
+                w(f"{ind}const wf<T> {nm} = stash_get<wf<T>>(lds_rows, {off});")
+            for idx, it in enumerate(by_level.get(lvl, [])):
+                if record is not None:
+                    self._template_item(lambda line, lvl=lvl, idx=idx: record.append((lvl, idx, line)), it, ind, prev)
+                    continue
                 self._template_item(w, it, ind, prev)
+                for nm, off in puts.get((lvl, idx), []):
+                    w(f"{ind}stash_put(lds_rows, {off}, {nm});")
         for _ in sc.order:
             ind = ind[:-2]
             w(f"{ind}}}")

@@ -73,14 +73,15 @@ __device__ inline void colour_stage(const KernelArgs& a) {
 }
 
 // Returns Re(J^dagger C J) for the calling lane's event, where J_f = sum_o
-// coef * A_o over the flow-map terms and A_o = jl[o * 256 + threadIdx.x] are
-// the ordering amplitudes the block staged in LDS (row stride 256 events).
+// coef * A_o over the flow-map terms and A_o = (jl[2o][lane], jl[2o + 1][lane])
+// (real and imaginary rows of 256 events) are the ordering amplitudes the
+// block staged in LDS.
 // Every lane of the wavefront must call it (the MFMAs need the full wave) and
 // the wave's own 64 columns of jl must be written before the call.  Output
 // tiles are taken in pairs, so that four independent accumulations keep the
 // matrix pipeline busy.
 template <class T, int NKS, int NFO, int NTERM>
-__device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const KernelArgs& a) {
+__device__ inline T colour_form_mfma(const T* jl, const int* cstep, const KernelArgs& a) {
   static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
   const uint32_t* terms = ColourLds<T, NTERM>::term();
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
@@ -99,10 +100,11 @@ __device__ inline T colour_form_mfma(const cx<T>* jl, const int* cstep, const Ke
         const int off = __builtin_amdgcn_readfirstlane(cstep[2 * s + 1]);
         for (int t = 0; t < nt; ++t) {
           const uint32_t e = terms[4 * (off + t) + g];
-          const cx<T> v = jl[int(e & 0xffffu) * 256 + ev];
+          const int o = int(e & 0xffffu);
+          const T vr = jl[(2 * o) * 256 + ev], vi = jl[(2 * o + 1) * 256 + ev];
           const T cf = T(int(int16_t(uint16_t(e >> 16))));
-          xr[s] += cf * v.r;
-          xi[s] += cf * v.i;
+          xr[s] += cf * vr;
+          xi[s] += cf * vi;
         }
       }
     }
