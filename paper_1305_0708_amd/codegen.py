@@ -37,6 +37,8 @@ TEMPLATE_KIN_PER_LEVEL = True
 # FP32 kernels hold these currents in registers without spilling, and there
 # the opaque reads cost more than they save.
 TEMPLATE_STASH_WORDS = 48
+# MFMA colour form: 16-event chunks of a wave per pass (each fragment load serves them all)
+COLOUR_CHUNKS = 2
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
@@ -583,7 +585,8 @@ class Gen:
             w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
             w("      __builtin_amdgcn_wave_barrier();")
             w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
-            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}>(&lds_rows[0][0], a.cstep, a));")
+            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
+              f"(&lds_rows[0][0], a.cstep, a));")
             w("      __builtin_amdgcn_wave_barrier();")
             w("    }")
             w("  }")

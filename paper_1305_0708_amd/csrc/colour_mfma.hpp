@@ -77,34 +77,42 @@ __device__ inline void colour_stage(const KernelArgs& a) {
 // (real and imaginary rows of 256 events) are the ordering amplitudes the
 // block staged in LDS.
 // Every lane of the wavefront must call it (the MFMAs need the full wave) and
-// the wave's own 64 columns of jl must be written before the call.  Output
-// tiles are taken in pairs, so that four independent accumulations keep the
-// matrix pipeline busy.
-template <class T, int NKS, int NFO, int NTERM>
+// the wave's own 64 columns of jl must be written before the call.  The wave's
+// 64 events are four 16-event chunks (the N side of the MFMA), taken CH at a
+// time: each colour fragment loaded serves CH chunks, and output tiles are
+// taken in pairs, so that 4 CH independent accumulations keep the matrix
+// pipeline busy.
+template <class T, int NKS, int NFO, int NTERM, int CH = 2>
 __device__ inline T colour_form_mfma(const T* jl, const int* cstep, const KernelArgs& a) {
   static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
+  static_assert(CH == 1 || CH == 2 || CH == 4, "chunks per pass divide the four chunks of a wave");
   const uint32_t* terms = ColourLds<T, NTERM>::term();
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
   const int wbase = tid - lane;
   T result = T(0);
 #pragma unroll 1
-  for (int c = 0; c < 4; ++c) {
-    const int ev = wbase + 16 * c + col;
-    T xr[4 * NFO], xi[4 * NFO];
+  for (int c0 = 0; c0 < 4; c0 += CH) {
+    T xr[CH][4 * NFO], xi[CH][4 * NFO];
 #pragma unroll
     for (int s = 0; s < 4 * NFO; ++s) {
-      xr[s] = T(0);
-      xi[s] = T(0);
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        xr[q][s] = T(0);
+        xi[q][s] = T(0);
+      }
       if (s < NKS) {
         const int nt = __builtin_amdgcn_readfirstlane(cstep[2 * s]);
         const int off = __builtin_amdgcn_readfirstlane(cstep[2 * s + 1]);
         for (int t = 0; t < nt; ++t) {
           const uint32_t e = terms[4 * (off + t) + g];
           const int o = int(e & 0xffffu);
-          const T vr = jl[(2 * o) * 256 + ev], vi = jl[(2 * o + 1) * 256 + ev];
           const T cf = T(int(int16_t(uint16_t(e >> 16))));
-          xr[s] += cf * vr;
-          xi[s] += cf * vi;
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int ev = wbase + 16 * (c0 + q) + col;
+            xr[q][s] += cf * jl[(2 * o) * 256 + ev];
+            xi[q][s] += cf * jl[(2 * o + 1) * 256 + ev];
+          }
         }
       }
     }
@@ -112,32 +120,59 @@ __device__ inline T colour_form_mfma(const T* jl, const int* cstep, const Kernel
     // keeps them streaming from L2 instead of being hoisted into registers.
     const int base = opaque_int(0);
     const T* frag = static_cast<const T*>(a.cfrag);
-    T part = T(0);
+    T part[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) part[q] = T(0);
+    // C is symmetric: output tile fo takes the k-steps from its own diagonal
+    // block on (s >= 4 fo), the later blocks with the factor 2 built into the
+    // fragments, so that sum_fo x_fo . z_fo is the whole quadratic form.
 #pragma unroll
     for (int fo = 0; fo < NFO; fo += 2) {
       const bool two = fo + 1 < NFO;
-      typename Mfma<T>::acc zr0 = {T(0), T(0), T(0), T(0)}, zi0 = zr0, zr1 = zr0, zi1 = zr0;
+      typename Mfma<T>::acc zr0[CH], zi0[CH], zr1[CH], zi1[CH];
 #pragma unroll
-      for (int s = 0; s < NKS; ++s) {
-        const T a0 = frag[base + (fo * NKS + s) * 64 + lane];
-        zr0 = Mfma<T>::step(a0, xr[s], zr0);
-        zi0 = Mfma<T>::step(a0, xi[s], zi0);
-        if (two) {
-          const T a1 = frag[base + ((fo + 1) * NKS + s) * 64 + lane];
-          zr1 = Mfma<T>::step(a1, xr[s], zr1);
-          zi1 = Mfma<T>::step(a1, xi[s], zi1);
+      for (int q = 0; q < CH; ++q) {
+        zr0[q] = typename Mfma<T>::acc{T(0), T(0), T(0), T(0)};
+        zi0[q] = zr0[q];
+        zr1[q] = zr0[q];
+        zi1[q] = zr0[q];
+      }
+#pragma unroll
+      for (int s = 4 * fo; s < NKS; ++s) {
+        // uniform fragment address (scalar registers) + the lane's offset
+        const T a0 = (frag + (base + (fo * NKS + s) * 64))[lane];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          zr0[q] = Mfma<T>::step(a0, xr[q][s], zr0[q]);
+          zi0[q] = Mfma<T>::step(a0, xi[q][s], zi0[q]);
+        }
+        if (two && s >= 4 * (fo + 1)) {
+          const T a1 = (frag + (base + ((fo + 1) * NKS + s) * 64))[lane];
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            zr1[q] = Mfma<T>::step(a1, xr[q][s], zr1[q]);
+            zi1[q] = Mfma<T>::step(a1, xi[q][s], zi1[q]);
+          }
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part += zr0[r] * xr[4 * fo + r] + zi0[r] * xi[4 * fo + r];
-      if (two) {
+      for (int q = 0; q < CH; ++q) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) part += zr1[r] * xr[4 * fo + 4 + r] + zi1[r] * xi[4 * fo + 4 + r];
+        for (int r = 0; r < 4; ++r) part[q] += zr0[q][r] * xr[q][4 * fo + r] + zi0[q][r] * xi[q][4 * fo + r];
+        if (two) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            part[q] += zr1[q][r] * xr[q][4 * fo + 4 + r] + zi1[q][r] * xi[q][4 * fo + 4 + r];
+        }
       }
     }
-    part += __shfl_xor(part, 16, 64);
-    part += __shfl_xor(part, 32, 64);
-    if (g == c) result = part;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      T pq = part[q];
+      pq += __shfl_xor(pq, 16, 64);
+      pq += __shfl_xor(pq, 32, 64);
+      if (g == c0 + q) result = pq;
+    }
   }
   return result;
 }

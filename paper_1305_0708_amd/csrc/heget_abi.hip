@@ -479,12 +479,15 @@ heget_status colour_tables(const heget_process_ir* ir, const GenEntry* e, heget_
   auto out_flow = [&](int fo, int i) {
     return prec == HEGET_FP64 ? 16 * fo + i : 16 * fo + 4 * (i % 4) + i / 4;
   };
+  // C is symmetric: tile fo reads the k-steps of its diagonal 16 x 16 block as
+  // they are and those of the later blocks doubled; earlier k-steps are not read
   t.cfrag.assign(size_t(nfo) * nks * 64, 0.0);
   for (int fo = 0; fo < nfo; ++fo)
-    for (int s = 0; s < nks; ++s)
+    for (int s = 4 * fo; s < nks; ++s)
       for (int lane = 0; lane < 64; ++lane) {
         const int i = lane & 15, k = lane >> 4;
-        t.cfrag[(size_t(fo) * nks + s) * 64 + lane] = cs(out_flow(fo, i), 4 * s + k);
+        const double f = s >= 4 * (fo + 1) ? 2.0 : 1.0;
+        t.cfrag[(size_t(fo) * nks + s) * 64 + lane] = f * cs(out_flow(fo, i), 4 * s + k);
       }
   return HEGET_OK;
 }

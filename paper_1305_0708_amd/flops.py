@@ -91,18 +91,24 @@ def colour_flops(proc):
 
 def colour_mfma_flops(proc):
     """Algorithmic flops of the MFMA colour form for one helicity of one event:
-    the flow-map sums (a complex add per term), the dense product C X^T for
-    the real and the imaginary parts (2 n_f^2 each) and the dot products
-    (2 n_f each).  The zero padding to whole 16 x 16 x 4 tiles is not counted."""
+    the flow-map sums (a complex add per term), the product of C with X^T over
+    the upper triangle of 16 x 16 blocks (C is symmetric; the diagonal blocks
+    whole), for the real and the imaginary parts, and the dot products (2 n_f
+    each).  The zero padding of the last tiles is not counted."""
     nf = proc.n_flows
     terms = sum(sum(1 for x in row if x) for row in proc.flow_map) if proc.flow_map else nf
-    return CADD * terms + 2 * (2 * nf * nf) + 2 * (2 * nf)
+    nb = (nf + 15) // 16
+    sizes = [min(16, nf - 16 * b) for b in range(nb)]
+    pairs = sum(sizes[b] * sum(sizes[b:]) for b in range(nb))
+    return CADD * terms + 2 * (2 * pairs) + 2 * (2 * nf)
 
 
 def colour_mfma_flops_executed(proc):
-    """flops the MFMA instructions execute per helicity and event, padding included"""
+    """flops the MFMA instructions execute per helicity and event, padding
+    included: tile fo runs the k-steps s >= 4 fo"""
     nks, nfo = (proc.n_flows + 3) // 4, (proc.n_flows + 15) // 16
-    return 2 * (2 * (16 * nfo) * (4 * nks))
+    steps = sum(nks - 4 * fo for fo in range(nfo))
+    return 2 * (2 * 16 * 4 * steps)
 
 
 def per_event(proc, n_hel=None):
