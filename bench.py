@@ -39,10 +39,10 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    SQ_INSTS_VALU_*_F64 counters per wave (one event per lane): the arithmetic
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
-#    model still counts.
+#    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 COUNTERS_FP64 = {"source_digest": "b532f2ae43aa0f9451d78c3a7676f781ffbe1cbcdabab30eddee72d14b2c2693",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
-                 "flop_per_event": 41174}
+                 "flop_per_event": 41174, "flop_per_event_mixed": 38126}
 
 
 def counters_valid(proc_ir):
@@ -242,8 +242,11 @@ def main():
     model_flop_event = flops.per_event(proc_ir)
     if counters_valid(proc_ir):
         flop_event, flop_source = COUNTERS_FP64["flop_per_event"], "executed FP64 flops from SQ_INSTS_VALU_*_F64"
+        mixed_flop_event = COUNTERS_FP64["flop_per_event_mixed"]
+        mixed_flop_source = "executed FP32 flops from SQ_INSTS_VALU_*_F32"
     else:
         flop_event, flop_source = model_flop_event, "IR flop model (counters taken on another kernel source)"
+        mixed_flop_event, mixed_flop_source = model_flop_event, flop_source
     achieved = flop_event * N_EVENTS / kern64 / 1e12
     value = N_EVENTS / wall64
     line = {
@@ -269,7 +272,8 @@ def main():
                      "flop_per_event": flop_event, "flop_source": flop_source,
                      "model_flop_per_event": model_flop_event},
         "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,
-                  "model_tflops": model_flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
+                  "tflops": mixed_flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
+                  "flop_per_event": mixed_flop_event, "flop_source": mixed_flop_source,
                   "sigma_pb": rmx["sigma_pb"]},
         "helicity_filtered": {"helicities": nk, "fp64_value": N_EVENTS / wall64f,
                               "mixed_value": N_EVENTS / wallmxf, "fp64_kernel_ms": kern64f * 1e3,

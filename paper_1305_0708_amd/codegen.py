@@ -534,6 +534,8 @@ class Gen:
             w("  // currents while the orderings run (FP64), then the amplitude rows of the colour form")
             w(f"  constexpr bool kStash = {'sizeof(T) == 8' if self._tstash_words else 'false'};")
             w(f"  __shared__ T lds_rows[kStash ? {max(rows, self._tstash_words)} : {max(rows, 1)}][256];")
+        for k, L in sorted(self._fixed_vector_positions().items()):
+            w(f"  const VPol<T> VP{k} = vpol_pre<T>(p[{L}]);   // position {k} is leg {L} in every ordering")
         w("  // this block's workspace slot: A[o][h][256] of its events")
         w("  cx<T>* const work = static_cast<cx<T>*>(a.work) + size_t(blockIdx.x) * size_t(a.work_stride);")
         w("  const int nh = a.n_hel;")
@@ -681,10 +683,27 @@ class Gen:
                   f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
                 done.add(f"d{n}_{pid}")
 
-    def _position_external(self, k):
+    def _fixed_vector_positions(self):
+        """positions that hold the same massless vector leg in every ordering"""
+        p = self.p
+        out = {}
+        for k in range(self.nl):
+            cand = {o[k] for o in p.orderings}
+            if len(cand) == 1:
+                L = cand.pop()
+                if p.legs[L].kind == V and p.legs[L].particle == P_ZERO:
+                    out[k] = L
+        return out
+
+    def _position_external(self, k, nest=False):
+        """the external state at position k; in the helicity nest (helicities
+        +-1) a position that always holds the same massless vector leg uses the
+        event's precomputed polarisation factors"""
         p = self.p
         leg = p.legs[p.orderings[0][k]]
         if leg.kind == V:
+            if nest and k in self._fixed_vector_positions():
+                return f"const wf<T> w{k} = vxxxxx0<T>(VP{k}, hp{k}, {self._pos_nsv[k]});"
             return (f"const wf<T> w{k} = vxxxxx<T>(tv<T>({self._physical(k, self._w, self._ind)}), T(pe{leg.particle}.m), "
                     f"hp{k}, {self._pos_nsv[k]});")
         return f"const cx<T> w{k} = sxxxxx<T>();"
@@ -788,7 +807,7 @@ class Gen:
         if it.kind == "ext":
             (k,) = it.data
             self._w, self._ind = w, ind
-            w(ind + self._position_external(k))
+            w(ind + self._position_external(k, nest=True))
         elif it.kind == "call":
             k, _ = it.data
             self._lazy_kinematics(w, ind, p.calls[k], self._done)
