@@ -42,6 +42,14 @@ COLOUR_CHUNKS = 2
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
+# per-lane LDS words (arithmetic type) of the inner table of the FP32 kernels:
+# the values of the unrolled innermost loops that depend on no real loop,
+# formed once before the loops for every combination of the unrolled
+# helicities and read from LDS inside them (the FP64 kernels leave them to the
+# compiler, which hoists them into registers: faster there); the stash takes
+# what is left of NEST_LDS_WORDS
+INNER_TABLE_WORDS = 64
+NEST_LDS_WORDS = 72
 _KIN_WORDS = {"vec<T>": 4, "cx<T>": 2, "MLF<T>": 8, "wf<T>": 8, "VPol<T>": 5}
 
 
@@ -322,13 +330,25 @@ class Gen:
     def _emit_nest(self, w):
         """the full helicity product as one loop per leg (nest.schedule): each
         wavefunction, call, bra, amplitude core and jamp sits in the
-        innermost loop its inputs need"""
+        innermost loop its inputs need; an FP32 variant with the inner table
+        where the process has one"""
+        sc = nest.schedule(self.p)
+        if self._inner_table_plan(sc, nest.unrolled_levels(sc), INNER_TABLE_WORDS)[0]:
+            w("    if constexpr (sizeof(T) == 4) {")
+            self._emit_nest_body(w, INNER_TABLE_WORDS, "  ")
+            w("    } else {")
+            self._emit_nest_body(w, 0, "  ")
+            w("    }")
+        else:
+            self._emit_nest_body(w, 0, "")
+
+    def _emit_nest_body(self, w, inner_words, extra):
         p = self.p
         sc = nest.schedule(p)
         by_level = {}
         for it in sc.items:
             by_level.setdefault(it.level, []).append(it)
-        ind = "    "
+        ind = "    " + extra
         w(f"{ind}// helicity loop nest, outermost leg first: {sc.order}")
         for it in by_level.get(-1, []):
             self._nest_item(w, it, ind)
@@ -337,7 +357,8 @@ class Gen:
         # interleave the independent iterations
         unrolled = nest.unrolled_levels(sc)
         tables = self._tables(sc, unrolled)
-        loads = self._stash_plan(sc, unrolled, tables)
+        inner, hoisted, iwords = self._inner_table_plan(sc, unrolled, inner_words)
+        loads = self._stash_plan(sc, unrolled, tables, inner_words=iwords)
         if loads:
             words = sum(_KIN_WORDS[self._kin[nm]] for L in loads.values() for nm, _ in L)
             w(f"{ind}// kinematics used only inside the helicity loops wait in LDS and are read")
@@ -347,6 +368,8 @@ class Gen:
                 for nm, off in L:
                     w(f"{ind}stash_put(stash, {off}, {nm});")
         self._emit_tables(w, sc, tables, ind, -1)
+        if inner:
+            self._emit_inner_table(w, sc, unrolled, inner, hoisted, iwords, ind)
         for lvl, L in enumerate(sc.order):
             ch = sc.choices[L]
             if len(ch) == 1:
@@ -366,6 +389,12 @@ class Gen:
             for it in by_level.get(lvl, []):
                 if id(it) in tables:
                     w(ind + self._table_select(it, tables[id(it)]))
+                elif id(it) in hoisted:
+                    for nm, (typ, off, legs) in inner.items():
+                        if hoisted[id(it)] == nm:
+                            n = _KIN_WORDS[typ]
+                            idx = " + ".join(f"{1 << (len(legs) - 1 - j)} * c{L}" for j, L in enumerate(legs))
+                            w(f"{ind}const {typ} {nm} = stash_get<{typ}>(itab, {off} + {n} * ({idx}));")
                 else:
                     self._nest_item(w, it, ind)
             self._emit_tables(w, sc, tables, ind, lvl)
@@ -423,7 +452,86 @@ class Gen:
         kind = "cx<T>" if ir.OUT_KIND[self.p.calls[it.data[0]].op] == S else "wf<T>"
         return f"const {kind} w{o} = {sel(0, 0)};"
 
-    def _stash_plan(self, sc, unrolled, tables=None):
+    def _hoistable(self, sc, unrolled):
+        """items of the unrolled levels that depend on no real loop, with the
+        names they define and the names of all items' uses"""
+        import re
+        real = [lvl for lvl, L in enumerate(sc.order) if len(sc.choices[L]) > 1 and lvl not in unrolled]
+        real_hh = {f"hh{sc.order[lvl]}" for lvl in real}
+        varying, info = set(), []
+        for it in sc.items:
+            buf = []
+            self._nest_item(buf.append, it, "")
+            code = "\n".join(buf)
+            toks = set(re.findall(r"[A-Za-z_]\w*", code))
+            defined = re.findall(r"const (\S+) (\w+) =", code)
+            rv = bool(toks & (varying | real_hh))
+            if rv:
+                varying |= {nm for _, nm in defined}
+            info.append((it, rv, defined, toks))
+        return info
+
+    def _inner_table_plan(self, sc, unrolled, budget):
+        """The inner table: values defined by hoistable items (unrolled level,
+        no real loop) and used by items that are not hoistable, one entry per
+        combination of the unrolled helicities up to the value's level.
+        Returns ({name: (type, word offset, legs)}, {id(item): name}, words)."""
+        if not budget or not unrolled:
+            return {}, {}, 0
+        info = self._hoistable(sc, unrolled)
+        hoist = {id(it) for it, rv, _, _ in info if it.level in unrolled and not rv and it.kind in ("ext", "call")}
+        used_outside = set()
+        for it, rv, defined, toks in info:
+            if id(it) not in hoist:
+                used_outside |= toks
+        inner, hoisted, off = {}, {}, 0
+        for it, rv, defined, toks in info:
+            if id(it) not in hoist:
+                continue
+            for typ, nm in defined:
+                if nm in used_outside and typ in _KIN_WORDS:
+                    legs = [sc.order[lvl] for lvl in sorted(unrolled) if lvl <= it.level]
+                    n = _KIN_WORDS[typ] * 2 ** len(legs)
+                    if off + n > budget:
+                        return {}, {}, 0
+                    inner[nm] = (typ, off, legs)
+                    hoisted[id(it)] = nm
+                    off += n
+        # the other hoistable items are formed only in the table's loops
+        for it, rv, defined, toks in info:
+            if id(it) in hoist and id(it) not in hoisted:
+                hoisted[id(it)] = None
+        return inner, hoisted, off
+
+    def _emit_inner_table(self, w, sc, unrolled, inner, hoisted, words, ind):
+        """the inner table's loops before the nest: the hoistable items for
+        every combination of the unrolled helicities, the table values to LDS"""
+        items = {id(it): it for it in sc.items}
+        w(f"{ind}// values of the unrolled loops that no outer loop changes, for every combination")
+        w(f"{ind}// of the unrolled helicities, in LDS (read back inside the loops)")
+        w(f"{ind}__shared__ T itab[{words}][256];")
+        ind0 = ind
+        for lvl in sorted(unrolled):
+            L = sc.order[lvl]
+            w(f"{ind}#pragma unroll")
+            w(f"{ind}for (int c{L} = 0; c{L} < 2; ++c{L}) {{")
+            ind += "  "
+            w(f"{ind}const int hh{L} = 2 * c{L} - 1;")
+            for it in sc.items:
+                if it.level == lvl and id(it) in hoisted:
+                    self._nest_item(w, it, ind)
+                    nm = hoisted[id(it)]
+                    if nm is not None:
+                        typ, off, legs = inner[nm]
+                        n = _KIN_WORDS[typ]
+                        idx = " + ".join(f"{1 << (len(legs) - 1 - j)} * c{L2}" for j, L2 in enumerate(legs))
+                        w(f"{ind}stash_put(itab, {off} + {n} * ({idx}), {nm});")
+        for _ in sorted(unrolled):
+            ind = ind[:-2]
+            w(f"{ind}}}")
+        assert ind == ind0
+
+    def _stash_plan(self, sc, unrolled, tables=None, inner_words=0):
         """Which event kinematics go to the LDS stash, and the loop level that
         reads each back: a value qualifies when every item using it sits inside
         a real (not unrolled) helicity loop or depends on one.  Values that feed
@@ -461,9 +569,10 @@ class Gen:
             if all(rv and lvl >= first_real for lvl, rv in us):
                 cand.append((min(min(lvl for lvl, _ in us), last_real), nm))
         loads, off = {}, 0
+        budget = min(STASH_WORDS, NEST_LDS_WORDS - inner_words) if inner_words else STASH_WORDS
         for lvl, nm in sorted(cand, key=lambda c: (c[0], list(self._kin).index(c[1]))):
             n = _KIN_WORDS[self._kin[nm]]
-            if off + n > STASH_WORDS:
+            if off + n > budget:
                 continue
             loads.setdefault(lvl, []).append((nm, off))
             off += n
