@@ -479,7 +479,10 @@ class Gen:
         if not budget or not unrolled:
             return {}, {}, 0
         info = self._hoistable(sc, unrolled)
-        hoist = {id(it) for it, rv, _, _ in info if it.level in unrolled and not rv and it.kind in ("ext", "call")}
+        # calls only: external states are cheap to form again inside the loops
+        hoist = {id(it) for it, rv, _, _ in info if it.level in unrolled and not rv and it.kind == "call"}
+        self._inner_pre = {id(it) for it, rv, _, _ in info
+                           if it.level in unrolled and not rv and it.kind in ("ext", "call")}
         used_outside = set()
         for it, rv, defined, toks in info:
             if id(it) not in hoist:
@@ -518,9 +521,9 @@ class Gen:
             ind += "  "
             w(f"{ind}const int hh{L} = 2 * c{L} - 1;")
             for it in sc.items:
-                if it.level == lvl and id(it) in hoisted:
+                if it.level == lvl and id(it) in self._inner_pre:
                     self._nest_item(w, it, ind)
-                    nm = hoisted[id(it)]
+                    nm = hoisted.get(id(it))
                     if nm is not None:
                         typ, off, legs = inner[nm]
                         n = _KIN_WORDS[typ]
