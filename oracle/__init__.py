@@ -13,6 +13,9 @@ lives in the C++ sources next to this file:
   with explicit Dirac matrices and brute-force SU(3) colour sums.
 * ``gluons.cpp``     -- colour-ordered Berends-Giele recursion for n gluons and
   the trace-basis colour matrix by brute force.
+* ``phase_space_tree.py`` -- (numpy) the resonance phase space of the paper's
+  Appendix A at a fixed collision energy: nested two-body decays with
+  Breit-Wigner mapped invariant masses.
 
 Parity unpinned: the size of the H^3 contribution in u d -> u d H H and the
 Yukawa normalisation are definitional (same written convention on both sides);
@@ -64,6 +67,7 @@ def lib():
         dp, ip = P(ctypes.c_double), P(ctypes.c_int)
         L.or_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
         L.or_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, dp]
+        L.or_uniforms_bulk.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, dp]
         L.or_rambo.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp]
         L.or_rambo.restype = ctypes.c_double
         L.or_phase_space_volume.argtypes = [ctypes.c_double, ctypes.c_int]
@@ -106,6 +110,13 @@ def philox4x32_10(ctr, key):
 def uniforms(seed, event, n):
     u = np.zeros(n)
     lib().or_uniforms(seed, event, n, _dp(u))
+    return u
+
+
+def uniforms_bulk(seed, n_events, n, counter_offset=0):
+    """u[i][k]: the first n uniforms of events counter_offset + i"""
+    u = np.zeros((n_events, n))
+    lib().or_uniforms_bulk(seed, counter_offset, n_events, n, _dp(u))
     return u
 
 

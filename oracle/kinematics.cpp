@@ -61,6 +61,11 @@ extern "C" void or_uniforms(uint64_t seed, uint64_t event, int n_u, double* u) {
   }
 }
 
+extern "C" void or_uniforms_bulk(uint64_t seed, uint64_t counter_offset, int64_t n_events, int n_u, double* u) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n_events; ++i) or_uniforms(seed, counter_offset + uint64_t(i), n_u, u + i * n_u);
+}
+
 extern "C" double or_phase_space_volume(double sqrt_s, int n) {
   const double s = sqrt_s * sqrt_s;
   return std::pow(2.0 * orc::PI, 4 - 3 * n) * std::pow(0.5 * orc::PI, n - 1) * std::pow(s, n - 2) /

@@ -59,6 +59,8 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
  * uniforms u = (floor(x / 2^12) + 1/2) 2^-52 from x = w0 2^32 + w1 and
  * x = w2 2^32 + w3 (exact in FP64, strictly inside (0,1)). */
 void or_uniforms(uint64_t seed, uint64_t event, int n_u, double* u);
+/* the same for events counter_offset .. counter_offset + n_events - 1: u[i][n_u] */
+void or_uniforms_bulk(uint64_t seed, uint64_t counter_offset, int64_t n_events, int n_u, double* u);
 
 /* RAMBO (Kleiss, Stirling, Ellis 1986): n massless momenta in the centre-of-mass
  * frame at energy sqrt_s from 4n uniforms (per particle: cos theta, phi, two

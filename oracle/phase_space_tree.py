@@ -1,0 +1,130 @@
+"""Oracle (test infrastructure only): the resonance phase space of the paper's
+Appendix A (Eq. ps2-resonance and the Breit-Wigner mapping of Sec. B of the
+appendix) at a fixed collision energy.
+
+The collision system (mass sqrt_s, at rest) and every resonance decay into two
+daughters, each a final massless particle or another resonance:
+
+    dPhi_n = dPhi_2(root) * prod_k [ds_k / (2 pi)] dPhi_2(R_k -> its daughters at s_k),
+
+with dPhi_2(M; m1, m2) = lambda^(1/2)(M^2, m1^2, m2^2) / (8 pi M^2) for isotropic
+decay angles in the parent's rest frame.  A resonance's invariant mass follows
+either the Breit-Wigner mapping
+
+    s_k = m^2 + m Gamma tan(theta),  ds_k = [(s_k - m^2)^2 + (m Gamma)^2] / (m Gamma) dtheta,
+
+with theta uniform over the window |s_k - m^2| / (m Gamma) < min(window, m / Gamma)
+intersected with the kinematic range, or a flat distribution over the range
+(optionally windowed the same way).  Kinematic range of the first daughter of
+a node of mass M: [0, (M - minimal mass of the second)^2]; of the second:
+[0, (M - sqrt(s_first))^2] (every final particle is massless).
+
+Uniforms: the same Philox4x32-10 stream as RAMBO (two per counter block, the
+event index in the counter); per node in index order, first one uniform for the
+invariant mass of each daughter that is a resonance (first daughter first),
+then cos(theta) = 2u - 1 and phi = 2 pi u' of the node's decay.
+
+Written with numpy over events; no code shared with the library.
+"""
+import math
+
+import numpy as np
+
+from . import uniforms_bulk
+
+
+def n_uniforms(nodes):
+    return sum(sum(1 for d in nd[3:5] if d < 0) + 2 for nd in nodes)
+
+
+def _sample_s(u, lo, hi, m, g, mapping, window):
+    """invariant mass s in [lo, hi] (arrays) by the node's mapping; returns (s,
+    ds / (2 pi) weight, valid)"""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    if mapping == "bw" or (mapping == "flat" and window is not None and g > 0):
+        w = min(window, m / g) if window is not None else m / g
+        lo = np.maximum(lo, m * m - w * m * g)
+        hi = np.minimum(hi, m * m + w * m * g)
+    valid = hi > lo
+    if mapping == "bw":
+        mg = m * g
+        t_lo = np.arctan((lo - m * m) / mg)
+        t_hi = np.arctan((hi - m * m) / mg)
+        t = t_lo + u * (t_hi - t_lo)
+        s = m * m + mg * np.tan(t)
+        jac = (t_hi - t_lo) * ((s - m * m) ** 2 + mg * mg) / mg
+    else:
+        s = lo + u * (hi - lo)
+        jac = hi - lo
+    s = np.where(valid, s, np.maximum(lo, 0.0))
+    return s, np.where(valid, jac / (2.0 * math.pi), 0.0), valid
+
+
+def _boost(P, M, q):
+    """q (rest frame of P, of mass M) to the frame where P is given; arrays [n,4]"""
+    E = P[:, 0]
+    pq = P[:, 1] * q[:, 1] + P[:, 2] * q[:, 2] + P[:, 3] * q[:, 3]
+    q0 = (E * q[:, 0] + pq) / M
+    f = (q[:, 0] + q0) / (E + M)
+    out = np.empty_like(q)
+    out[:, 0] = q0
+    out[:, 1:] = q[:, 1:] + f[:, None] * P[:, 1:]
+    return out
+
+
+def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0):
+    """nodes[k] = (mass, width, mapping, d0, d1, window): node 0 is the collision
+    (mass and width ignored), d >= 0 a final leg, d < 0 node -1 - d; mapping
+    "bw" or "flat", window None (flat over the kinematic range) or the factor
+    of min(window, m / Gamma).  Returns momenta [n][n_legs][4] (legs 0, 1 the
+    beams along +-z) and the phase-space weight [n] (0 where a window is empty)."""
+    K = len(nodes)
+    u = uniforms_bulk(seed, n_events, n_uniforms(nodes), counter_offset)
+    n = n_events
+    mom = np.zeros((n, n_legs, 4))
+    h = 0.5 * sqrt_s
+    mom[:, 0] = [h, 0.0, 0.0, h]
+    mom[:, 1] = [h, 0.0, 0.0, -h]
+    weight = np.ones(n)
+    mass = {0: np.full(n, float(sqrt_s))}            # node -> invariant mass sqrt(s)
+    lab = {0: np.tile([sqrt_s, 0.0, 0.0, 0.0], (n, 1))}
+    iu = 0
+    for k in range(K):
+        m_k, g_k, mp_k, d0, d1, win_k = nodes[k]
+        M = mass[k]
+        dm = {}
+        # invariant masses of resonant daughters: first, then second
+        for j, d in enumerate((d0, d1)):
+            if d >= 0:
+                dm[j] = np.zeros(n)
+                continue
+            other_mass = dm[0] if j == 1 else np.zeros(n)   # the second's minimal mass is 0
+            hi = (M - other_mass) ** 2
+            node = nodes[-1 - d]
+            s, wj, valid = _sample_s(u[:, iu], np.zeros(n), hi, node[0], node[1], node[2], node[5])
+            iu += 1
+            weight *= wj
+            dm[j] = np.sqrt(s)
+            mass[-1 - d] = dm[j]
+        m0, m1 = dm[0], dm[1]
+        lam = (M * M - (m0 + m1) ** 2) * (M * M - (m0 - m1) ** 2)
+        lam = np.maximum(lam, 0.0)
+        pst = np.sqrt(lam) / (2.0 * M)
+        weight *= np.sqrt(lam) / (8.0 * math.pi * M * M)
+        ct = 2.0 * u[:, iu] - 1.0
+        phi = 2.0 * math.pi * u[:, iu + 1]
+        iu += 2
+        st = np.sqrt(1.0 - ct * ct)
+        nvec = np.stack([st * np.cos(phi), st * np.sin(phi), ct], axis=1)
+        e0 = (M * M + m0 * m0 - m1 * m1) / (2.0 * M)
+        e1 = (M * M + m1 * m1 - m0 * m0) / (2.0 * M)
+        q0 = np.concatenate([e0[:, None], pst[:, None] * nvec], axis=1)
+        q1 = np.concatenate([e1[:, None], -pst[:, None] * nvec], axis=1)
+        for d, q in ((d0, q0), (d1, q1)):
+            ql = _boost(lab[k], M, q) if k > 0 else q
+            if d >= 0:
+                mom[:, d] = ql
+            else:
+                lab[-1 - d] = ql
+    return mom, weight

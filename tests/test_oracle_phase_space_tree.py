@@ -1,0 +1,103 @@
+"""Pins of the oracle's resonance phase space (the paper's Appendix A at a fixed
+collision energy) against what the mathematics fixes: momentum conservation
+and mass shells, the closed-form n-body volume that every parametrisation of
+the same phase space must reproduce, the Breit-Wigner Jacobian per event, and
+two mappings of the same windowed region agreeing."""
+import math
+
+import numpy as np
+import pytest
+
+MT, WT, MW, WW = 175.0, 1.55, 80.4, 2.085
+ROOTS = 1000.0
+
+
+def c1_tree(mapping="bw", window=20.0):
+    """g g -> t t~, t -> b W+ (-> e+ nu), t~ -> b~ W- (-> mu- nu~); legs as in the C1 process"""
+    return [(0.0, 0.0, None, -2, -3, None),
+            (MT, WT, mapping, 2, -4, window),
+            (MT, WT, mapping, 5, -5, window),
+            (MW, WW, mapping, 3, 4, window),
+            (MW, WW, mapping, 6, 7, window)]
+
+
+def flat_tree_c1():
+    return [(0.0, 0.0, None, -2, -3, None),
+            (0.0, 0.0, "flat", 2, -4, None),
+            (0.0, 0.0, "flat", 5, -5, None),
+            (0.0, 0.0, "flat", 3, 4, None),
+            (0.0, 0.0, "flat", 6, 7, None)]
+
+
+def msq(p):
+    return p[..., 0] ** 2 - (p[..., 1:] ** 2).sum(-1)
+
+
+@pytest.fixture(scope="module")
+def T(oracle):
+    from oracle import phase_space_tree
+    return phase_space_tree
+
+
+def test_uniform_count(T):
+    assert T.n_uniforms(c1_tree()) == 14
+
+
+def test_conservation_shells_and_windows(T):
+    mom, w = T.generate(7, 20000, ROOTS, c1_tree(), 8)
+    assert np.abs(mom[:, 2:].sum(1) - [ROOTS, 0, 0, 0]).max() < 1e-11 * ROOTS
+    assert np.abs(msq(mom[:, 2:])).max() < 1e-12 * ROOTS ** 2
+    assert np.all(w > 0)
+    for legs, m, g in (((2, 3, 4), MT, WT), ((5, 6, 7), MT, WT), ((3, 4), MW, WW), ((6, 7), MW, WW)):
+        s = msq(mom[:, list(legs)].sum(1))
+        assert np.all(np.abs(s - m * m) <= 20.0 * m * g * (1 + 1e-12))
+
+
+def test_two_body_weight_is_exact(T):
+    """one decay of the collision into two massless particles: dPhi_2 = 1/(8 pi) per event"""
+    mom, w = T.generate(3, 1000, ROOTS, [(0.0, 0.0, None, 2, 3, None)], 4)
+    assert np.allclose(w, 1.0 / (8.0 * math.pi), rtol=1e-15, atol=0)
+    assert np.abs(mom[:, 2, 1:] + mom[:, 3, 1:]).max() < 1e-12 * ROOTS
+
+
+@pytest.mark.parametrize("tree,n", [
+    ([(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, 4, None)], 3),
+    ([(0.0, 0.0, None, -2, -3, None), (0.0, 0.0, "flat", 2, 3, None), (0.0, 0.0, "flat", 4, 5, None)], 4),
+    ([(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None), (0.0, 0.0, "flat", 4, 5, None)], 4),
+    (flat_tree_c1(), 6),
+])
+def test_flat_tree_reproduces_the_n_body_volume(oracle, T, tree, n):
+    """any factorisation of the massless n-body phase space has the volume
+    (2 pi)^(4 - 3n) (pi / 2)^(n - 1) s^(n - 2) / ((n - 1)! (n - 2)!)"""
+    N = 300000
+    _, w = T.generate(0x5EED + n, N, ROOTS, tree, n + 2)
+    mean, err = w.mean(), w.std() / math.sqrt(N)
+    ref = oracle.phase_space_volume(ROOTS, n)
+    assert abs(mean - ref) < 4.0 * err, (mean, err, ref)
+    assert err < 0.02 * ref
+
+
+def test_breit_wigner_jacobian_per_event(T):
+    """root -> (2, R), R -> (3, 4) with the Breit-Wigner mapping: per event
+    w * 2 pi / (dPhi_2(root) dPhi_2(R)) / [(s - m^2)^2 + (m Gamma)^2] = (t_hi - t_lo) / (m Gamma)"""
+    m, g, win = MW, WW, 20.0
+    tree = [(0.0, 0.0, None, 2, -2, None), (m, g, "bw", 3, 4, win)]
+    mom, w = T.generate(5, 5000, ROOTS, tree, 5)
+    s = msq(mom[:, 3] + mom[:, 4])
+    S = ROOTS ** 2
+    dphi_root = (S - s) / (8.0 * math.pi * S)          # lambda^(1/2)(S, 0, s) / (8 pi S)
+    dphi_r = 1.0 / (8.0 * math.pi)
+    lo, hi = max(0.0, m * m - win * m * g), min(S, m * m + win * m * g)
+    span = (math.atan((hi - m * m) / (m * g)) - math.atan((lo - m * m) / (m * g))) / (m * g)
+    got = w * 2.0 * math.pi / (dphi_root * dphi_r) / ((s - m * m) ** 2 + (m * g) ** 2)
+    assert np.allclose(got, span, rtol=1e-9, atol=0)
+
+
+def test_mappings_of_one_window_agree(T):
+    """the Breit-Wigner and the flat mapping of the same windowed region
+    estimate the same volume"""
+    N = 200000
+    _, wb = T.generate(21, N, ROOTS, c1_tree("bw"), 8)
+    _, wf = T.generate(22, N, ROOTS, c1_tree("flat"), 8)
+    eb, ef = wb.std() / math.sqrt(N), wf.std() / math.sqrt(N)
+    assert abs(wb.mean() - wf.mean()) < 4.0 * math.hypot(eb, ef), (wb.mean(), eb, wf.mean(), ef)
