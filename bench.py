@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "00409a2247ec30c4ad3e644752fd935bae8e9322c09036a78e88724d695a5173",
+COUNTERS_FP64 = {"source_digest": "155543b0804a6b7c377b7de3a6c22fd0d3f4d752f7d9d34616bdab700ac848c8",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 

@@ -119,6 +119,21 @@ typedef struct {
   int32_t prop;      /* HEGET_P_* of the propagator of a current (0 for amplitudes) */
 } heget_call;
 
+/* Resonance phase space (the paper's Appendix A, Eqs. for the Breit-Wigner
+ * parametrisation, at a fixed collision energy): the collision system and every
+ * resonance decay into two daughters (isotropic in the parent's rest frame);
+ * dPhi_n = dPhi_2(collision) prod_k ds_k / (2 pi) dPhi_2(resonance k at s_k).
+ * A resonance's s_k follows the Breit-Wigner mapping s = m^2 + m Gamma tan(theta),
+ * theta uniform over |s - m^2| / (m Gamma) < min(ps_window, m / Gamma) intersected
+ * with the kinematic range, or a flat distribution over the kinematic range.
+ * Every final particle is massless. */
+enum { HEGET_PS_FLAT = 0, HEGET_PS_BREIT_WIGNER = 1 };
+typedef struct {
+  int32_t particle;     /* HEGET_P_* giving the resonance's mass and width (node 0, the collision: ignored) */
+  int32_t mapping;      /* HEGET_PS_FLAT or HEGET_PS_BREIT_WIGNER (node 0: ignored) */
+  int32_t daughter[2];  /* final leg index (2 .. n_legs-1), or -1 - k for node k > this node */
+} heget_ps_node;
+
 /* Slots 0 .. n_legs-1 hold the external wavefunctions; every current writes a
  * new slot >= n_legs that is read only by later calls. */
 typedef struct {
@@ -154,6 +169,14 @@ typedef struct {
    * one non-zero entry.  Templates with n_flows >= 32 contract the colour
    * matrix on MFMA (Sec. 5.4's colour sum as a batched dense product). */
   const int8_t* flow_map;             /* [n_flows][n_orderings] */
+  /* Phase space of generated events: n_ps_nodes = 0 for RAMBO (flat massless
+   * n-body, constant weight), else the resonance tree ps_nodes[0 .. n_ps_nodes-1]
+   * (node 0 = the collision; every final leg and every other node the daughter
+   * of exactly one node) with the window factor ps_window (> 0; the paper's
+   * default is 20).  Part of the kernel's structure (compiled in). */
+  int32_t n_ps_nodes;
+  const heget_ps_node* ps_nodes;
+  double ps_window;
 } heget_process_ir;
 
 typedef struct heget_process* heget_process_t;
@@ -193,17 +216,22 @@ heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, 
 
 /* Phase-space generation alone: the momenta heget_eval would generate for
  * (seed, counter_offset .. counter_offset + n - 1, sqrt_s), written to the
- * device FP64 SoA momenta_out [n_legs][4][n] (the Philox -> RAMBO step of the
- * integrand, Sec. 3; 32 bytes per leg per event, an HBM-bound kernel).
- * Asynchronous on `stream`.  n = 0 is a no-op (momenta_out may then be NULL).
- * Errors: HEGET_E_INVALID (null handle, null output with n > 0, n < 0, sqrt_s <= 0),
- * HEGET_E_UNSUPPORTED (more than 10 final-state legs), HEGET_E_HIP. */
+ * device FP64 SoA momenta_out [n_legs][4][n] (the Philox -> phase-space step of
+ * the integrand, Sec. 3; 32 bytes per leg per event, an HBM-bound kernel), and,
+ * if weights_out (device FP64 [n]) is not NULL, each event's phase-space weight
+ * dPhi_n (GeV^(2n-4); RAMBO: the constant n-body volume; resonance tree: the
+ * product of the tree's two-body volumes and mapping Jacobians, 0 where a
+ * window is empty).  Asynchronous on `stream`.  n = 0 is a no-op (the outputs
+ * may then be NULL).  Errors: HEGET_E_INVALID (null handle, null momenta_out
+ * with n > 0, n < 0, sqrt_s <= 0), HEGET_E_UNSUPPORTED (RAMBO with more than 10
+ * final-state legs), HEGET_E_HIP. */
 heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_t counter_offset, double sqrt_s,
-                            double* momenta_out, void* stream);
+                            double* momenta_out, double* weights_out, void* stream);
 
-/* Monte Carlo cross section from n RAMBO events generated from `seed`
- * (counters 0 .. n-1): sigma = (1/N) sum_i w_i with w_i = Phi_n * pass_i * F_i
- * / (2 s 4 n_a n_b S), reduced on the device in a fixed order.  Synchronises
+/* Monte Carlo cross section from n events generated from `seed` (counters
+ * 0 .. n-1) by the process's phase space (RAMBO or its resonance tree):
+ * sigma = (1/N) sum_i w_i with w_i = dPhi_n,i * pass_i * F_i / (2 s 4 n_a n_b S),
+ * reduced on the device in a fixed order.  Synchronises
  * `stream`; fills *out.  The handle keeps a small buffer of per-block partial
  * sums (24 bytes per 256 events), allocated on the first call and grown when a
  * larger n arrives; calls on one handle must not overlap.

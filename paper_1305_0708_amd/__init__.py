@@ -56,11 +56,15 @@ class _IRBuffers:
         self.orders = (ctypes.c_int8 * max(len(flat_o), 1))(*flat_o)
         flat_m = [int(x) for r in (proc.flow_map or []) for x in r]
         self.flow_map = (ctypes.c_int8 * max(len(flat_m), 1))(*flat_m)
+        tree = proc.ps_tree or []
+        self.ps_nodes = (L.heget_ps_node * max(len(tree), 1))(*[
+            L.heget_ps_node(part, mapping, (ctypes.c_int32 * 2)(d0, d1)) for part, mapping, d0, d1 in tree])
         self.ir = L.heget_process_ir(
             proc.n_legs, self.legs, self.sm, len(proc.couplings), self.cpl, len(calls), self.calls,
             proc.n_amps, proc.n_flows, self.jamp, self.colour, float(den), len(hels), self.hel,
             proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr,
-            len(orders), self.orders if orders else None, self.flow_map if flat_m else None)
+            len(orders), self.orders if orders else None, self.flow_map if flat_m else None,
+            len(tree), self.ps_nodes if tree else None, float(proc.ps_window))
 
 
 class Process:
@@ -124,16 +128,21 @@ class Process:
                                    ptr(me2_out), ptr(momenta_out), self._stream(stream)))
         return (me2_out, momenta_out) if want_momenta else me2_out
 
-    def generate(self, n, seed=0, counter_offset=0, sqrt_s=None, momenta_out=None, stream=None):
-        """The momenta heget_eval generates (Philox -> RAMBO), as a float64
-        CUDA tensor [n_legs][4][n], without evaluating |M|^2."""
+    def generate(self, n, seed=0, counter_offset=0, sqrt_s=None, momenta_out=None, want_weights=False,
+                 stream=None):
+        """The momenta heget_eval generates (Philox -> the process's phase
+        space), as a float64 CUDA tensor [n_legs][4][n], without evaluating
+        |M|^2; with want_weights also each event's phase-space weight [n]."""
         import torch
         sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
         if momenta_out is None:
             momenta_out = torch.empty((self.n_legs, 4, max(n, 0)), dtype=torch.float64, device="cuda")
+        weights = torch.empty(max(n, 0), dtype=torch.float64, device="cuda") if want_weights else None
         check(self._lib.heget_generate(self._h, n, seed, counter_offset, float(sqrt_s),
-                                       ctypes.c_void_p(momenta_out.data_ptr()), self._stream(stream)))
-        return momenta_out
+                                       ctypes.c_void_p(momenta_out.data_ptr()),
+                                       ctypes.c_void_p(weights.data_ptr()) if weights is not None else None,
+                                       self._stream(stream)))
+        return (momenta_out, weights) if want_weights else momenta_out
 
     def integrate(self, n, seed=0, sqrt_s=None, stream=None):
         sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s

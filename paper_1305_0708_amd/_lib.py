@@ -39,6 +39,10 @@ class heget_call(ctypes.Structure):
                 ("coupling", ctypes.c_int32), ("prop", ctypes.c_int32)]
 
 
+class heget_ps_node(ctypes.Structure):
+    _fields_ = [("particle", ctypes.c_int32), ("mapping", ctypes.c_int32), ("daughter", ctypes.c_int32 * 2)]
+
+
 class heget_process_ir(ctypes.Structure):
     _fields_ = [("n_legs", ctypes.c_int32), ("legs", ctypes.POINTER(heget_leg)),
                 ("sm", heget_sm),
@@ -51,7 +55,9 @@ class heget_process_ir(ctypes.Structure):
                 ("n_a_n_b", ctypes.c_int32), ("symmetry", ctypes.c_int32),
                 ("cut_enabled", ctypes.c_int32), ("cut_pt", ctypes.c_double), ("cut_dr", ctypes.c_double),
                 ("n_orderings", ctypes.c_int32), ("orderings", ctypes.POINTER(ctypes.c_int8)),
-                ("flow_map", ctypes.POINTER(ctypes.c_int8))]
+                ("flow_map", ctypes.POINTER(ctypes.c_int8)),
+                ("n_ps_nodes", ctypes.c_int32), ("ps_nodes", ctypes.POINTER(heget_ps_node)),
+                ("ps_window", ctypes.c_double)]
 
 
 class heget_result(ctypes.Structure):
@@ -98,7 +104,7 @@ def load(path=None):
     L.heget_process_destroy.restype = ctypes.c_int
     L.heget_eval.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp, vp]
     L.heget_eval.restype = ctypes.c_int
-    L.heget_generate.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp]
+    L.heget_generate.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp, vp]
     L.heget_generate.restype = ctypes.c_int
     L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.POINTER(heget_result), vp]

@@ -132,11 +132,16 @@ class Gen:
         w("namespace heget {")
         w("namespace {")
         w("")
+        tree = p.ps_tree is not None
+        if tree:
+            self._emit_ps_tree(w)
         w("template <class T>")
         w(f"__device__ __forceinline__ void body_{p.name}(const KernelArgs& a, int64_t blk) {{")
         w("  const int64_t i = blk * blockDim.x + threadIdx.x;")
         w("  const bool active = i < a.n;")
         w(f"  mom p[{self.nl}];")
+        if tree:
+            w("  double psw = 1.0;   // phase-space weight of a generated event (resonance tree)")
         w("  if (active) {")
         w("    if (a.mom_in) {")
         w("#pragma unroll")
@@ -148,17 +153,21 @@ class Gen:
         w("      const double h = 0.5 * a.sqrt_s;")
         w("      p[0] = {h, 0.0, 0.0, h};")
         w("      p[1] = {h, 0.0, 0.0, -h};")
-        w(f"      rambo<{self.nout}>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);")
+        if tree:
+            w(f"      psw = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), p);")
+        else:
+            w(f"      rambo<{self.nout}>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);")
         w("    }")
         w("    if (a.mom_out) store_momenta<%d>(a, i, p);" % self.nl)
         w("  } else {")
         w("#pragma unroll")
         w(f"    for (int k = 0; k < {self.nl}; ++k) p[k] = {{1.0, 0.0, 0.0, 1.0}};")
         w("  }")
+        live = "active && psw > 0.0" if tree else "active"
         if p.cut_enabled:
-            w(f"  const bool pass = active && (!a.cut_enabled || pass_pt_dr<{self.nout}>(p + 2, a.cut_pt, a.cut_dr));")
+            w(f"  const bool pass = {live} && (!a.cut_enabled || pass_pt_dr<{self.nout}>(p + 2, a.cut_pt, a.cut_dr));")
         else:
-            w("  const bool pass = active;")
+            w(f"  const bool pass = {live};")
         w("  // couplings and propagator data (uniform)")
         for k, c in enumerate(p.couplings):
             w(f"  const cx<T> g{k}_0 = mk<T>(T(a.cpl[{4 * k}]), T(a.cpl[{4 * k + 1}]));")
@@ -179,7 +188,7 @@ class Gen:
         else:
             self._emit_straight(w)
         w("  if (a.me2_out && active) a.me2_out[i] = me2;")
-        w("  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor : 0.0, pass);")
+        w(f"  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor{' * psw' if tree else ''} : 0.0, pass);")
         w("}")
         w("")
         if self.ordered:
@@ -220,6 +229,17 @@ class Gen:
         w("  }")
         w("}")
         w("")
+        if tree:
+            w("// the phase-space step alone (heget_generate): momenta and per-event weights")
+            w(f"__global__ __launch_bounds__(256) void gen_{p.name}(KernelArgs a) {{")
+            w("  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;")
+            w("  if (i >= a.n) return;")
+            w(f"  mom p[{self.nl}];")
+            w(f"  const double w = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), p);")
+            w(f"  store_momenta<{self.nl}>(a, i, p);")
+            w("  if (a.psw_out) a.psw_out[i] = w;")
+            w("}")
+            w("")
         w("}  // namespace")
         w("")
         mf = p.uses_colour_mfma()
@@ -234,11 +254,57 @@ class Gen:
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
-          f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}}};')
+          f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}, '
+          f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
         return "\n".join(L) + "\n"
+
+    def _emit_ps_tree(self, w):
+        """the process's resonance phase space as straight-line device code:
+        per node in index order, the invariant masses of its resonant
+        daughters (first daughter first), then its two-body decay"""
+        p = self.p
+        tree = p.ps_tree
+        nu = sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
+        w(f"// phase space: the collision and its resonances decay in two bodies (tree of {len(tree)} nodes);")
+        w("// fills p[0 .. n_legs-1] and returns the event's weight dPhi_n")
+        w(f"__device__ __forceinline__ double ps_tree_{p.name}(const KernelArgs& a, uint64_t event, mom* p) {{")
+        w(f"  double u[{nu}];")
+        w(f"  ps_uniforms<{nu}>(a.seed, event, u);")
+        w("  const double h = 0.5 * a.sqrt_s;")
+        w("  p[0] = {h, 0.0, 0.0, h};")
+        w("  p[1] = {h, 0.0, 0.0, -h};")
+        w("  double w = 1.0;")
+        w("  const double M0 = a.sqrt_s;")
+        w("  const mom P0 = {a.sqrt_s, 0.0, 0.0, 0.0};")
+        iu = 0
+        for k, (_, _, d0, d1) in enumerate(tree):
+            dm = {}
+            for j, d in enumerate((d0, d1)):
+                if d >= 0:
+                    dm[j] = "0.0"
+                    continue
+                nd = -1 - d
+                part, mapping = tree[nd][0], tree[nd][1]
+                hi = f"(M{k} - {dm[0]}) * (M{k} - {dm[0]})" if j == 1 else f"M{k} * M{k}"
+                bw = "true" if mapping == ir.PS_BREIT_WIGNER else "false"
+                w(f"  double s{nd};")
+                w(f"  w *= ps_mass(u[{iu}], 0.0, {hi}, a.prop[{part}].m, a.prop[{part}].w, {bw}, "
+                  f"{_c(p.ps_window)}, s{nd});")
+                w(f"  const double M{nd} = sqrt(s{nd});")
+                w(f"  mom P{nd};")
+                dm[j] = f"M{nd}"
+                iu += 1
+            outs = [f"p[{d}]" if d >= 0 else f"P{-1 - d}" for d in (d0, d1)]
+            w(f"  w *= ps_decay(u[{iu}], u[{iu + 1}], P{k}, M{k}, {dm[0]}, {dm[1]}, {'true' if k == 0 else 'false'}, "
+              f"{outs[0]}, {outs[1]});")
+            iu += 2
+        assert iu == nu
+        w("  return w;")
+        w("}")
+        w("")
 
     def _ext_pre(self, w):
         """helicity-independent pieces of the external wavefunctions"""

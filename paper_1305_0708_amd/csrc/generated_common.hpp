@@ -25,6 +25,7 @@ struct GenEntry {
   int n_hel_canon;            // its rows (n_legs entries each)
   int persistent;             // 1: persistent grid with a workspace slot per block (ordering templates)
   int cterm_cap;              // capacity of the kernel's LDS term table (words)
+  const void* generate;       // the process's own phase-space kernel (resonance tree), or null (RAMBO)
 };
 
 // The launch arguments of one request's segment in a fused launch.

@@ -108,6 +108,17 @@ uint64_t fingerprint(const heget_process_ir* ir) {
   H.i32(ir->flow_map ? 1 : 0);
   if (ir->flow_map)
     for (int k = 0; k < ir->n_flows * ir->n_orderings; ++k) H.i32(ir->flow_map[k]);
+  if (ir->n_ps_nodes > 0) {
+    H.i32(ir->n_ps_nodes);
+    for (int k = 0; k < ir->n_ps_nodes; ++k) {
+      const heget_ps_node& nd = ir->ps_nodes[k];
+      H.i32(nd.particle);
+      H.i32(nd.mapping);
+      H.i32(nd.daughter[0]);
+      H.i32(nd.daughter[1]);
+    }
+    H.f64(ir->ps_window);
+  }
   return H.h;
 }
 
@@ -138,7 +149,7 @@ heget_status validate(const heget_process_ir* ir) {
     if (l.kind < 0 || l.kind > 2 || l.particle < 0 || l.particle >= HEGET_N_PARTICLES)
       return fail(HEGET_E_IR, "leg " + std::to_string(k) + ": bad kind or particle");
     if (k >= 2 && l.particle != HEGET_P_ZERO)
-      return fail(HEGET_E_UNSUPPORTED, "final-state legs must be massless (RAMBO phase space)");
+      return fail(HEGET_E_UNSUPPORTED, "final-state legs must be massless (RAMBO and resonance-tree phase space)");
   }
   if (ir->n_couplings < 1 || !ir->couplings) return fail(HEGET_E_IR, "no couplings");
   for (int k = 0; k < ir->n_couplings; ++k)
@@ -210,6 +221,34 @@ heget_status validate(const heget_process_ir* ir) {
       if (x < 0 || x >= ir->n_legs || seen[x]) return fail(HEGET_E_IR, "orderings must be permutations of the legs");
       seen[x] = 1;
     }
+  }
+  if (ir->n_ps_nodes < 0 || ir->n_ps_nodes > 16 || (ir->n_ps_nodes > 0 && !ir->ps_nodes))
+    return fail(HEGET_E_IR, "phase-space tree: 0..16 nodes");
+  if (ir->n_ps_nodes > 0) {
+    if (!(ir->ps_window > 0) || !std::isfinite(ir->ps_window))
+      return fail(HEGET_E_IR, "phase-space tree: window must be > 0");
+    std::vector<int> leg_seen(ir->n_legs, 0), node_seen(ir->n_ps_nodes, 0);
+    for (int k = 0; k < ir->n_ps_nodes; ++k) {
+      const heget_ps_node& nd = ir->ps_nodes[k];
+      if (k > 0 && (nd.particle < 0 || nd.particle >= HEGET_N_PARTICLES ||
+                    (nd.mapping != HEGET_PS_FLAT && nd.mapping != HEGET_PS_BREIT_WIGNER)))
+        return fail(HEGET_E_IR, "phase-space node " + std::to_string(k) + ": bad particle or mapping");
+      for (int d : nd.daughter) {
+        if (d >= 0) {
+          if (d < 2 || d >= ir->n_legs) return fail(HEGET_E_IR, "phase-space tree: daughter is not a final leg");
+          ++leg_seen[d];
+        } else {
+          const int j = -1 - d;
+          if (j <= k || j >= ir->n_ps_nodes)
+            return fail(HEGET_E_IR, "phase-space tree: a daughter node must come after its parent");
+          ++node_seen[j];
+        }
+      }
+    }
+    for (int L = 2; L < ir->n_legs; ++L)
+      if (leg_seen[L] != 1) return fail(HEGET_E_IR, "phase-space tree: every final leg is a daughter exactly once");
+    for (int k = 1; k < ir->n_ps_nodes; ++k)
+      if (node_seen[k] != 1) return fail(HEGET_E_IR, "phase-space tree: every node but the first is a daughter once");
   }
   return HEGET_OK;
 }
@@ -308,7 +347,9 @@ double heget::detail::phase_space_volume(double sqrt_s, int n) {
 
 double heget::detail::weight_factor(heget_process_t p, double sqrt_s) {
   const double s = sqrt_s * sqrt_s;
-  return phase_space_volume(sqrt_s, p->n_legs - 2) / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
+  // a resonance tree's weight is per event (multiplied in the kernel)
+  const double volume = p->entry->generate ? 1.0 : phase_space_volume(sqrt_s, p->n_legs - 2);
+  return volume / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
 }
 
 void heget::detail::fill_result(const double h[3], int64_t n, heget_result* out) {
@@ -338,6 +379,7 @@ __global__ __launch_bounds__(256) void generate_momenta(KernelArgs a) {
   p[1] = {h, 0.0, 0.0, -h};
   heget::rambo<NOUT>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);
   heget::store_momenta<NOUT + 2>(a, i, p);
+  if (a.psw_out) a.psw_out[i] = a.weight_factor;   // RAMBO: the constant n-body volume
 }
 
 template <int NOUT>
@@ -504,6 +546,15 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   *out = nullptr;
   if (prec != HEGET_FP64 && prec != HEGET_MIXED) return fail(HEGET_E_INVALID, "unknown precision");
   if (heget_status s = validate(ir)) return s;
+  {
+    PropEntry prop[HEGET_N_PARTICLES];
+    prop_table(ir->sm, prop);
+    for (int k = 1; k < ir->n_ps_nodes; ++k) {
+      const heget_ps_node& nd = ir->ps_nodes[k];
+      if (nd.mapping == HEGET_PS_BREIT_WIGNER && !(prop[nd.particle].m > 0 && prop[nd.particle].w > 0))
+        return fail(HEGET_E_IR, "phase-space node " + std::to_string(k) + ": Breit-Wigner needs a mass and a width");
+    }
+  }
   const uint64_t fp = fingerprint(ir);
   const GenEntry* entry = nullptr;
   for (const GenEntry* e : heget::registry())
@@ -624,14 +675,14 @@ heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, 
 }
 
 heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_t counter_offset, double sqrt_s,
-                            double* momenta_out, void* stream) {
+                            double* momenta_out, double* weights_out, void* stream) {
   g_err.clear();
   if (!p) return fail(HEGET_E_INVALID, "null handle");
   if (n < 0) return fail(HEGET_E_INVALID, "n < 0");
   if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
   if (n > 0 && !momenta_out) return fail(HEGET_E_INVALID, "null momenta_out");
-  const void* fn = nullptr;
-  switch (p->n_legs - 2) {
+  const void* fn = p->entry->generate;   // the process's resonance tree, else RAMBO by final-state count
+  if (!fn) switch (p->n_legs - 2) {
     case 2: fn = generate_kernel<2>(); break;
     case 3: fn = generate_kernel<3>(); break;
     case 4: fn = generate_kernel<4>(); break;
@@ -646,14 +697,15 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
   if (n == 0) return HEGET_OK;
   const int64_t grid = (n + 255) / 256;
   if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
-  KernelArgs a;
-  std::memset(&a, 0, sizeof(a));
+  KernelArgs a = base_args(p);
   a.n = n;
   a.mom_stride = n;
   a.seed = seed;
   a.counter_offset = counter_offset;
   a.sqrt_s = sqrt_s;
   a.mom_out = momenta_out;
+  a.psw_out = weights_out;
+  a.weight_factor = heget::detail::phase_space_volume(sqrt_s, p->n_legs - 2);
   void* args[] = {&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(256), args, 0, static_cast<hipStream_t>(stream)));
   return HEGET_OK;

@@ -29,7 +29,10 @@ struct KernelArgs {
   const double* cpl;         // 4 doubles per coupling: g0 (re, im), g1 (re, im)
   const PropEntry* prop;     // indexed by particle id
   double cut_pt, cut_dr;
-  double weight_factor;      // phase-space weight x flux x averages x 1/S (integrate)
+  double weight_factor;      // integrate: flux x averages x 1/S, times the RAMBO volume (a resonance
+                             // tree's per-event weight multiplies in the kernel); generate: the
+                             // RAMBO volume written to psw_out
+  double* psw_out;           // generate: per-event phase-space weight [n], or null
   double* partials;          // integrate: [gridDim.x][3] (sum w, sum w^2, accepted), or null
   const int8_t* ord;         // ordering table [n_orderings][n_legs] of colour-ordered processes
   // MFMA colour form (ordering templates with many flows; see colour_mfma.hpp)

@@ -77,6 +77,80 @@ __device__ __forceinline__ void rambo(uint64_t seed, uint64_t event, double sqrt
   }
 }
 
+// ---------------------------------------------------------------- resonance tree
+// The paper's Appendix A phase space at a fixed collision energy: nested
+// two-body decays, dPhi_n = dPhi_2(collision) prod_k ds_k / (2 pi) dPhi_2(R_k),
+// the invariant mass of a resonance Breit-Wigner mapped (s = m^2 + m Gamma
+// tan theta, theta uniform over |s - m^2| / (m Gamma) < min(window, m / Gamma)
+// within the kinematic range) or flat over its kinematic range.  The process's
+// tree is compiled into a generated device function built from these pieces.
+
+// The first N uniforms of an event (two per Philox counter block, blocks 0, 1, ...).
+template <int N>
+__device__ __forceinline__ void ps_uniforms(uint64_t seed, uint64_t event, double* u) {
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+#pragma unroll
+  for (int j = 0; 2 * j < N; ++j) {
+    uint32_t c[4] = {uint32_t(event), uint32_t(event >> 32), uint32_t(j), 0u};
+    philox4x32_10(c, k0, k1);
+    u[2 * j] = unit_open(c[0], c[1]);
+    if (2 * j + 1 < N) u[2 * j + 1] = unit_open(c[2], c[3]);
+  }
+}
+
+// Invariant mass s of a resonance within [lo, hi]; returns its ds / (2 pi)
+// weight, 0 (and s = max(lo, 0)) when the window leaves no room.
+__device__ __forceinline__ double ps_mass(double u, double lo, double hi, double m, double g, bool bw,
+                                          double window, double& s) {
+  const double inv2pi = 0.15915494309189533577;
+  if (bw) {
+    const double w = fmin(window, m / g);
+    lo = fmax(lo, m * m - w * m * g);
+    hi = fmin(hi, m * m + w * m * g);
+  }
+  if (!(hi > lo)) {
+    s = fmax(lo, 0.0);
+    return 0.0;
+  }
+  if (bw) {
+    const double mg = m * g;
+    const double t_lo = atan((lo - m * m) / mg), t_hi = atan((hi - m * m) / mg);
+    s = m * m + mg * tan(t_lo + u * (t_hi - t_lo));
+    return (t_hi - t_lo) * ((s - m * m) * (s - m * m) + mg * mg) / mg * inv2pi;
+  }
+  s = lo + u * (hi - lo);
+  return (hi - lo) * inv2pi;
+}
+
+// q, given in the rest frame of P (mass M), in the frame where P is given
+__device__ __forceinline__ mom ps_boost(const mom& P, double M, const mom& q) {
+  const double pq = P.x * q.x + P.y * q.y + P.z * q.z;
+  const double e = (P.e * q.e + pq) / M;
+  const double f = (q.e + e) / (P.e + M);
+  return {e, q.x + f * P.x, q.y + f * P.y, q.z + f * P.z};
+}
+
+// Two-body decay of P (mass M) into masses m0, m1, isotropic in P's rest frame
+// (cos theta = 2 uc - 1, phi = 2 pi uphi); returns dPhi_2 = lambda^(1/2) / (8 pi M^2).
+// P at rest (the collision) is not boosted.
+__device__ __forceinline__ double ps_decay(double uc, double uphi, const mom& P, double M, double m0, double m1,
+                                           bool at_rest, mom& q0, mom& q1) {
+  const double pi = 3.14159265358979323846;
+  const double lam = fmax((M * M - (m0 + m1) * (m0 + m1)) * (M * M - (m0 - m1) * (m0 - m1)), 0.0);
+  const double rl = sqrt(lam);
+  const double pst = rl / (2.0 * M);
+  const double ct = 2.0 * uc - 1.0;
+  const double st = sqrt(1.0 - ct * ct);
+  double sf, cf;
+  sincos(2.0 * pi * uphi, &sf, &cf);
+  const double nx = st * cf, ny = st * sf;
+  const double e0 = (M * M + m0 * m0 - m1 * m1) / (2.0 * M), e1 = (M * M + m1 * m1 - m0 * m0) / (2.0 * M);
+  const mom a = {e0, pst * nx, pst * ny, pst * ct}, b = {e1, -pst * nx, -pst * ny, -pst * ct};
+  q0 = at_rest ? a : ps_boost(P, M, a);
+  q1 = at_rest ? b : ps_boost(P, M, b);
+  return rl / (8.0 * pi * M * M);
+}
+
 // every final particle has pT > pt_min and every final pair Delta R > dr_min
 template <int NOUT>
 __device__ __forceinline__ bool pass_pt_dr(const mom* p, double pt_min, double dr_min) {

@@ -14,6 +14,7 @@ thresholds are runtime data and are not part of the kernel's fingerprint.
 from dataclasses import dataclass, field
 from fractions import Fraction
 from typing import List, Optional, Tuple
+import math
 import struct
 
 # leg kinds
@@ -87,6 +88,38 @@ class Call:
     prop: int = P_ZERO   # propagator particle of a current
 
 
+PS_FLAT, PS_BREIT_WIGNER = 0, 1
+
+
+def validate_ps_tree(tree, legs, window):
+    """the resonance tree: node 0 the collision, every final leg and every
+    other node the daughter of exactly one node, daughters after their parent,
+    massless final legs"""
+    nl, K = len(legs), len(tree)
+    if not 1 <= K <= 16:
+        raise ValueError("phase-space tree: 1..16 nodes")
+    if not (window > 0 and math.isfinite(window)):
+        raise ValueError("phase-space tree: window must be > 0")
+    seen_legs, seen_nodes = [], []
+    for k, (particle, mapping, d0, d1) in enumerate(tree):
+        if k > 0 and (mapping not in (PS_FLAT, PS_BREIT_WIGNER) or not 0 <= particle < 5):
+            raise ValueError(f"phase-space node {k}: bad mapping or particle")
+        for d in (d0, d1):
+            if d >= 0:
+                if not 2 <= d < nl:
+                    raise ValueError(f"phase-space node {k}: daughter {d} is not a final leg")
+                seen_legs.append(d)
+            else:
+                j = -1 - d
+                if not k < j < K:
+                    raise ValueError(f"phase-space node {k}: daughter node {j} must come after it")
+                seen_nodes.append(j)
+    if sorted(seen_legs) != list(range(2, nl)) or sorted(seen_nodes) != list(range(1, K)):
+        raise ValueError("phase-space tree: every final leg and node 1.. must be a daughter exactly once")
+    if any(legs[L].particle != P_ZERO for L in range(2, nl)):
+        raise ValueError("phase-space tree: final legs must be massless")
+
+
 @dataclass
 class Process:
     name: str
@@ -115,6 +148,12 @@ class Process:
     # integer coefficients; None means one flow per ordering.  With it the
     # colour matrix is n_flows x n_flows in the flows' basis.
     flow_map: Optional[List[List[int]]] = None
+    # Optional resonance phase space (the paper's Appendix A at fixed sqrt_s):
+    # nodes (particle, mapping, daughter0, daughter1); node 0 is the collision,
+    # a daughter >= 0 is a final leg, -1 - k is node k (k > the parent's index).
+    # None: RAMBO.  ps_window: the Breit-Wigner window factor (paper: 20).
+    ps_tree: Optional[List[Tuple[int, int, int, int]]] = None
+    ps_window: float = 20.0
 
     def uses_colour_mfma(self):
         """The colour quadratic form runs on MFMA for ordering templates with
@@ -196,6 +235,8 @@ class Process:
             for row in self.jamp[1:]:
                 if row != self.jamp[0]:
                     raise ValueError("ordering template: every jamp row is the same combination")
+        if self.ps_tree is not None:
+            validate_ps_tree(self.ps_tree, self.legs, self.ps_window)
         return self
 
     # -------------------------------------------------------------- fingerprint
@@ -249,6 +290,12 @@ class Process:
         for r in self.flow_map or []:
             for x in r:
                 i32(x)
+        if self.ps_tree:
+            i32(len(self.ps_tree))
+            for node in self.ps_tree:
+                for x in node:
+                    i32(x)
+            f64(self.ps_window)
         return bytes(b)
 
     def fingerprint(self):

@@ -67,6 +67,22 @@ def gg_ttbar_6f(sqrt_s=1000.0):
                    helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64, symmetry=1).validate()
 
 
+def gg_ttbar_6f_bw(sqrt_s=1000.0):
+    """The C1 process with the paper's resonance phase space (Appendix A) in
+    place of RAMBO: g g -> t t~ at fixed sqrt_s, t -> b W+ (-> e+ nu_e),
+    t~ -> b~ W- (-> mu- nu_mu~), each top and W mass Breit-Wigner mapped within
+    min(20, m / Gamma) widths of its pole."""
+    import dataclasses
+    BW = ir.PS_BREIT_WIGNER
+    tree = [(P_ZERO, ir.PS_FLAT, -2, -3),      # the collision -> t, t~
+            (P_TOP, BW, 2, -4),                # t -> b W+
+            (P_TOP, BW, 5, -5),                # t~ -> b~ W-
+            (P_W, BW, 3, 4),                   # W+ -> e+ nu_e
+            (P_W, BW, 6, 7)]                   # W- -> mu- nu_mu~
+    return dataclasses.replace(gg_ttbar_6f(sqrt_s), name="gg_ttbar_6f_bw", ps_tree=tree,
+                               ps_window=20.0).validate()
+
+
 def ud_udhh_4b(sqrt_s=2000.0):
     """u d -> u d H H via W W and Z Z fusion, each H -> b bbar (16 diagrams).
 
@@ -123,4 +139,5 @@ def by_name(name):
     if name in ("gg_4g", "gg_4g_ddm"):
         from .gluons import gg_ng
         return gg_ng(6, basis="trace" if name == "gg_4g" else "ddm")
-    return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "ud_udhh_4b": ud_udhh_4b}[name]()
+    return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
+            "ud_udhh_4b": ud_udhh_4b}[name]()

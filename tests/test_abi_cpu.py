@@ -46,7 +46,7 @@ def _status(fn):
     return 0
 
 
-@pytest.mark.parametrize("name", ["ee_mumu", "gg_ttbar_6f", "ud_udhh_4b", "gg_4g", "gg_4g_ddm"])
+@pytest.mark.parametrize("name", ["ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "ud_udhh_4b", "gg_4g", "gg_4g_ddm"])
 def test_fingerprint_matches_compiled_kernel(name):
     # a valid IR passes validation and the kernel lookup; without a GPU the
     # first device allocation then fails with HEGET_E_OOM (on a GPU: success)
@@ -83,8 +83,27 @@ def test_malformed_ir_rejected(mutate, expect):
 
 def test_python_validation_agrees():
     from paper_1305_0708_amd import processes
-    for name in ("ee_mumu", "gg_ttbar_6f", "ud_udhh_4b"):
+    for name in ("ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "ud_udhh_4b"):
         processes.by_name(name).validate()
+
+
+@pytest.mark.parametrize("tree", [
+    [(0, 0, -2, -3), (3, 1, 2, -4), (3, 1, 5, -5), (1, 1, 3, 4), (1, 1, 6, 6)],     # leg 6 twice, 7 never
+    [(0, 0, -2, -3), (3, 1, 2, -4), (3, 1, 5, -5), (1, 1, 3, 4), (1, 1, 6, 1)],     # a beam as daughter
+    [(0, 0, -2, -3), (3, 1, 2, -1), (3, 1, 5, -5), (1, 1, 3, 4), (1, 1, 6, 7)],     # node before its parent
+    [(0, 0, -2, -3), (3, 2, 2, -4), (3, 1, 5, -5), (1, 1, 3, 4), (1, 1, 6, 7)],     # unknown mapping
+    [(0, 0, -2, -3), (0, 1, 2, -4), (3, 1, 5, -5), (1, 1, 3, 4), (1, 1, 6, 7)],     # Breit-Wigner without mass
+])
+def test_malformed_phase_space_tree_rejected(tree):
+    """the library rejects a bad resonance tree (HEGET_E_IR) and so does the
+    Python IR; the fingerprint is taken from a valid tree"""
+    from paper_1305_0708_amd import processes
+    q = processes.gg_ttbar_6f_bw()
+    q.ps_tree = tree
+    assert _status(lambda: _create(q)) == -2
+    if tree[1][0] != 0:
+        with pytest.raises(ValueError):
+            q.validate()
 
 
 def test_colour_matrices_are_exact_fierz():
