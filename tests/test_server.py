@@ -127,3 +127,21 @@ def test_bad_requests(handles):
         srv.poll(12345)
     srv.submit(0, 5000, 9, 200.0)
     srv.close()            # drains the queued request
+
+
+def test_resonance_tree_process_alone_and_in_the_mix(handles):
+    """a process whose events come from its resonance tree (per-event weights in
+    the batch kernel) gives the same bits served as integrated alone"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    tree = H.Process(processes.by_name("gg_ttbar_6f_bw"), precision="fp64")
+    hs = list(handles) + [tree]
+    srv = H.Server(hs, arena_bytes=64 << 20, slots_per_process=2, max_batch_blocks=512, max_chunk_blocks=96)
+    reqs = [(len(hs) - 1, n, 1000 + n, 1000.0 * f) for n, f in ((5000, 1.0), (777, 0.9), (40000, 1.2))]
+    reqs += [(1, 3000, 7, 1000.0), (0, 2000, 9, 200.0)]
+    tickets = [srv.submit(proc, n, seed, rs) for proc, n, seed, rs in reqs]
+    got = [srv.poll(t) for t in tickets]
+    srv.close()
+    for (proc, n, seed, rs), g in zip(reqs, got):
+        ref = hs[proc].integrate(n, seed=seed, sqrt_s=rs)
+        assert g[0] == ref, (proc, n, g[0], ref)
