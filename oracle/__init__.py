@@ -16,6 +16,8 @@ lives in the C++ sources next to this file:
 * ``phase_space_tree.py`` -- (numpy) the resonance phase space of the paper's
   Appendix A at a fixed collision energy: nested two-body decays with
   Breit-Wigner mapped invariant masses.
+* ``vegas.py`` -- (numpy) adaptive importance sampling of the phase-space
+  uniforms (VEGAS grids, Lepage's refinement), the BASES role.
 
 Parity unpinned: the size of the H^3 contribution in u d -> u d H H and the
 Yukawa normalisation are definitional (same written convention on both sides);

@@ -79,9 +79,14 @@ def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0):
     "bw" or "flat", window None (flat over the kinematic range) or the factor
     of min(window, m / Gamma).  Returns momenta [n][n_legs][4] (legs 0, 1 the
     beams along +-z) and the phase-space weight [n] (0 where a window is empty)."""
-    K = len(nodes)
     u = uniforms_bulk(seed, n_events, n_uniforms(nodes), counter_offset)
-    n = n_events
+    return generate_from(u, sqrt_s, nodes, n_legs)
+
+
+def generate_from(u, sqrt_s, nodes, n_legs):
+    """the same from given uniforms u[n][n_uniforms(nodes)]"""
+    K = len(nodes)
+    n = u.shape[0]
     mom = np.zeros((n, n_legs, 4))
     h = 0.5 * sqrt_s
     mom[:, 0] = [h, 0.0, 0.0, h]
