@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "155543b0804a6b7c377b7de3a6c22fd0d3f4d752f7d9d34616bdab700ac848c8",
+COUNTERS_FP64 = {"source_digest": "399664768b7af939cd4ff2536f32d3c611a4ce115f6c399ad89f127278a697f2",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 
@@ -130,6 +130,26 @@ def resonance_leg(torch, H, processes, steps, warmup, r_rambo):
             "sigma_pb": r["sigma_pb"], "sigma_err_pb": r["err_pb"],
             "rel_err": r["err_pb"] / r["sigma_pb"],
             "rambo_rel_err": r_rambo["err_pb"] / r_rambo["sigma_pb"]}
+
+
+def adaptive_leg(torch, H, processes, passes=6, bins=32):
+    """heget_integrate_adaptive on the resonance-tree C1: passes of 2^20 FP64
+    events through a VEGAS grid refined after each (the BASES role of the
+    paper's Sec. 1 and 6).  Wall time per pass includes the per-pass bin sums
+    on the device, the host refinement and the call's own buffer allocation."""
+    import time
+    proc = H.Process(processes.gg_ttbar_6f_bw(), precision="fp64")
+    proc.integrate_adaptive(1 << 16, iterations=2, bins=bins, seed=SEED, sqrt_s=SQRT_S)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per, comb, chi2, _ = proc.integrate_adaptive(N_EVENTS, iterations=passes, bins=bins, seed=SEED, sqrt_s=SQRT_S)
+    wall = time.perf_counter() - t0
+    rel = [p["err_pb"] / p["sigma_pb"] for p in per]
+    return {"workload": f"gg->ttbar->6f, resonance tree, {passes} passes of 2^20 events, {bins} bins x "
+                        f"{proc.grid_dims} dims",
+            "events_per_s": passes * N_EVENTS / wall, "ms_per_pass": wall / passes * 1e3,
+            "rel_err_per_pass": [round(x, 6) for x in rel],
+            "sigma_pb": comb["sigma_pb"], "sigma_err_pb": comb["err_pb"], "chi2_per_dof": chi2}
 
 
 def phase_space_leg(torch, proc, steps, warmup):
@@ -298,6 +318,7 @@ def main():
     }
     line["phase_space"] = phase_space_leg(torch, fp64, args.steps, args.warmup)
     line["resonance_phase_space"] = resonance_leg(torch, H, processes, args.steps, args.warmup, r64)
+    line["adaptive_integration"] = adaptive_leg(torch, H, processes)
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -239,6 +239,31 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
                              void* stream);
 
+/* Adaptive Monte Carlo integration (the role of the BASES integrator in the
+ * paper's runs, Sec. 1 and 6): `iterations` passes of n events each, iteration
+ * k drawing counters k n .. (k + 1) n - 1 from `seed`; the uniforms of the
+ * process's resonance-tree phase space go through a VEGAS grid (G. P. Lepage,
+ * J. Comput. Phys. 27 (1978) 192) of `bins` bins per dimension, uniform at the
+ * start and refined after every pass from the sums of w^2 per bin (smoothing
+ * over neighbouring bins, compression ((x - 1) / ln x)^1.5, equal shares per new
+ * bin).  per_iteration (host, [iterations], may be NULL) gets each pass's
+ * result; *combined the inverse-variance average (n_generated, n_accepted,
+ * sum_w, sum_w2 summed over the passes); *chi2_per_dof (may be NULL) the
+ * passes' consistency; grid_out (host, [dims][bins + 1], may be NULL) the
+ * final grid.  Synchronises `stream`; allocates and frees its own device
+ * buffers (about 9 + dims bytes per event).  Errors: HEGET_E_INVALID (null
+ * handle or combined, n < 2, iterations < 1, bins outside 2 .. 32, sqrt_s <= 0),
+ * HEGET_E_UNSUPPORTED (a process without a resonance tree), HEGET_E_OOM,
+ * HEGET_E_HIP. */
+heget_status heget_integrate_adaptive(heget_process_t p, int64_t n, int32_t iterations, int32_t bins,
+                                      double sqrt_s, uint64_t seed, heget_result* per_iteration,
+                                      heget_result* combined, double* chi2_per_dof, double* grid_out,
+                                      void* stream);
+
+/* Uniforms per event of the process's phase space that an adaptive grid maps
+ * (the grid's dimensions; 0 for RAMBO processes), or -1 for a null handle. */
+int32_t heget_process_grid_dims(heget_process_t p);
+
 /* Number of helicity combinations the handle sums (after heget_filter_helicities). */
 int32_t heget_process_n_helicities(heget_process_t p);
 

@@ -28,7 +28,7 @@ ALPHA = 1.5
 
 
 def uniform_grid(D, B):
-    return np.tile(np.linspace(0.0, 1.0, B + 1), (D, 1))
+    return np.tile(np.arange(B + 1) / B, (D, 1))
 
 
 def map_uniforms(r, edges):

@@ -150,6 +150,28 @@ class Process:
         check(self._lib.heget_integrate(self._h, n, float(sqrt_s), seed, ctypes.byref(r), self._stream(stream)))
         return {k: getattr(r, k) for k, _ in r._fields_}
 
+    @property
+    def grid_dims(self):
+        """uniforms per event that an adaptive grid maps (0 for RAMBO processes)"""
+        return self._lib.heget_process_grid_dims(self._h)
+
+    def integrate_adaptive(self, n, iterations=5, bins=16, seed=0, sqrt_s=None, stream=None):
+        """heget_integrate_adaptive: (per-pass results, combined result, chi^2
+        per degree of freedom, final grid [dims][bins + 1] as numpy)"""
+        import numpy as np
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        per = (_lib.heget_result * iterations)()
+        comb = _lib.heget_result()
+        chi2 = ctypes.c_double()
+        dims = max(self.grid_dims, 0)
+        grid = np.zeros((dims, bins + 1))
+        gp = grid.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dims else None
+        check(self._lib.heget_integrate_adaptive(self._h, n, iterations, bins, float(sqrt_s), seed, per,
+                                                 ctypes.byref(comb), ctypes.byref(chi2), gp,
+                                                 self._stream(stream)))
+        as_dict = lambda r: {k: getattr(r, k) for k, _ in r._fields_}
+        return [as_dict(r) for r in per], as_dict(comb), chi2.value, grid
+
     def filter_helicities(self, n_probe=64, seed=12345, sqrt_s=None, rel_threshold=1e-20):
         sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
         kept = ctypes.c_int32()

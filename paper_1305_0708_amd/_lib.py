@@ -10,6 +10,7 @@ HEGET_FP64, HEGET_MIXED = 0, 1
 
 EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "heget_integrate",
             "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error", "heget_generate",
+            "heget_integrate_adaptive", "heget_process_grid_dims",
             "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
             "heget_server_destroy"]
 
@@ -109,6 +110,13 @@ def load(path=None):
     L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.POINTER(heget_result), vp]
     L.heget_integrate.restype = ctypes.c_int
+    L.heget_integrate_adaptive.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_uint64, ctypes.POINTER(heget_result),
+                                           ctypes.POINTER(heget_result), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), vp]
+    L.heget_integrate_adaptive.restype = ctypes.c_int
+    L.heget_process_grid_dims.argtypes = [vp]
+    L.heget_process_grid_dims.restype = ctypes.c_int32
     L.heget_process_n_helicities.argtypes = [vp]
     L.heget_process_n_helicities.restype = ctypes.c_int32
     L.heget_filter_helicities.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,

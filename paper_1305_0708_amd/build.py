@@ -52,7 +52,8 @@ def build(verbose=False, jobs=None, force=False):
     """Generate and compile every translation unit and link libheget.so; with
     force, recompile even objects newer than their sources."""
     os.makedirs(OBJ, exist_ok=True)
-    srcs = generate_sources() + [os.path.join(CSRC, "heget_abi.hip"), os.path.join(CSRC, "heget_server.hip")]
+    srcs = generate_sources() + [os.path.join(CSRC, "heget_abi.hip"), os.path.join(CSRC, "heget_server.hip"),
+                                 os.path.join(CSRC, "heget_adaptive.hip")]
     jobs = jobs or min(8, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda src: _compile(src, force), srcs))

@@ -154,7 +154,7 @@ class Gen:
         w("      p[0] = {h, 0.0, 0.0, h};")
         w("      p[1] = {h, 0.0, 0.0, -h};")
         if tree:
-            w(f"      psw = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), p);")
+            w(f"      psw = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), i, p);")
         else:
             w(f"      rambo<{self.nout}>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);")
         w("    }")
@@ -188,6 +188,8 @@ class Gen:
         else:
             self._emit_straight(w)
         w("  if (a.me2_out && active) a.me2_out[i] = me2;")
+        if tree:
+            w("  if (a.w_out && active) a.w_out[i] = pass ? me2 * a.weight_factor * psw : 0.0;")
         w(f"  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor{' * psw' if tree else ''} : 0.0, pass);")
         w("}")
         w("")
@@ -235,7 +237,7 @@ class Gen:
             w("  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;")
             w("  if (i >= a.n) return;")
             w(f"  mom p[{self.nl}];")
-            w(f"  const double w = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), p);")
+            w(f"  const double w = ps_tree_{p.name}(a, a.counter_offset + uint64_t(i), i, p);")
             w(f"  store_momenta<{self.nl}>(a, i, p);")
             w("  if (a.psw_out) a.psw_out[i] = w;")
             w("}")
@@ -255,11 +257,18 @@ class Gen:
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
           f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}, '
-          f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}}};')
+          f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}, {self.ps_dims()}}};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
         return "\n".join(L) + "\n"
+
+    def ps_dims(self):
+        """uniforms per event of the resonance tree (0 without one)"""
+        tree = self.p.ps_tree
+        if tree is None:
+            return 0
+        return sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
 
     def _emit_ps_tree(self, w):
         """the process's resonance phase space as straight-line device code:
@@ -270,13 +279,14 @@ class Gen:
         nu = sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
         w(f"// phase space: the collision and its resonances decay in two bodies (tree of {len(tree)} nodes);")
         w("// fills p[0 .. n_legs-1] and returns the event's weight dPhi_n")
-        w(f"__device__ __forceinline__ double ps_tree_{p.name}(const KernelArgs& a, uint64_t event, mom* p) {{")
+        w(f"__device__ __forceinline__ double ps_tree_{p.name}(const KernelArgs& a, uint64_t event, int64_t i, mom* p) {{")
         w(f"  double u[{nu}];")
         w(f"  ps_uniforms<{nu}>(a.seed, event, u);")
         w("  const double h = 0.5 * a.sqrt_s;")
         w("  p[0] = {h, 0.0, 0.0, h};")
         w("  p[1] = {h, 0.0, 0.0, -h};")
-        w("  double w = 1.0;")
+        w("  // adaptive integration: the uniforms through the grid, its Jacobian in the weight")
+        w(f"  double w = a.grid ? grid_map<{nu}>(a, i, u) : 1.0;")
         w("  const double M0 = a.sqrt_s;")
         w("  const mom P0 = {a.sqrt_s, 0.0, 0.0, 0.0};")
         iu = 0

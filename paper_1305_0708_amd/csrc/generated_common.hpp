@@ -26,6 +26,7 @@ struct GenEntry {
   int persistent;             // 1: persistent grid with a workspace slot per block (ordering templates)
   int cterm_cap;              // capacity of the kernel's LDS term table (words)
   const void* generate;       // the process's own phase-space kernel (resonance tree), or null (RAMBO)
+  int ps_dims;                // uniforms per event of the resonance tree (0: RAMBO)
 };
 
 // The launch arguments of one request's segment in a fused launch.

@@ -395,9 +395,7 @@ __global__ __launch_bounds__(256) void reduce_partials(const double* partials, i
 }  // namespace
 
 
-namespace {
-
-heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
+heget_status heget::detail::launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
   if (a.n == 0) return HEGET_OK;
   const int block = 256;
   int64_t grid = (a.n + block - 1) / block;
@@ -408,8 +406,6 @@ heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream) {
   HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(block), args, 0, stream));
   return HEGET_OK;
 }
-
-}  // namespace
 
 bool heget::detail::is_full_product(const GenEntry* e, const int8_t* table, int n_hel, int n_legs) {
   return e->hel_canon && e->n_hel_canon == n_hel &&
@@ -452,6 +448,7 @@ size_t heget::detail::complex_bytes(heget_process_t p) {
 namespace {
 
 using heget::detail::base_args;
+using heget::detail::launch;
 
 void release(heget_process* p) {
   if (!p) return;

@@ -60,6 +60,10 @@ double phase_space_volume(double sqrt_s, int n);
 // Per-event weight factor of heget_integrate: Phi_n / (2 s) x 1/4 x 1/(n_a n_b) x 1/S.
 double weight_factor(heget_process_t p, double sqrt_s);
 
+// Launches the process's amplitude kernel over a.n events (256 per block; a
+// persistent kernel's grid capped at its workspace slots).  HEGET_OK for n = 0.
+heget_status launch(heget_process_t p, KernelArgs& a, hipStream_t stream);
+
 // heget_result from the reduced (sum w, sum w^2, accepted) of n generated events.
 void fill_result(const double h[3], int64_t n, heget_result* out);
 

@@ -98,6 +98,25 @@ __device__ __forceinline__ void ps_uniforms(uint64_t seed, uint64_t event, doubl
   }
 }
 
+// Adaptive integration: the event's N uniforms through the grid of KernelArgs
+// (bins of [e_j, e_(j+1)] per dimension, u -> e_j + (u B - j)(e_(j+1) - e_j));
+// returns the Jacobian prod B (e_(j+1) - e_j) and records the bins of event i.
+template <int N, class A>
+__device__ __forceinline__ double grid_map(const A& a, int64_t i, double* u) {
+  const int B = a.grid_bins;
+  double jac = 1.0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const double t = u[d] * B;
+    const int j = min(int(t), B - 1);
+    const double lo = a.grid[d * (B + 1) + j], hi = a.grid[d * (B + 1) + j + 1];
+    u[d] = lo + (t - j) * (hi - lo);
+    jac *= B * (hi - lo);
+    if (a.grid_bin_out) a.grid_bin_out[int64_t(d) * a.n + i] = uint8_t(j);
+  }
+  return jac;
+}
+
 // Invariant mass s of a resonance within [lo, hi]; returns its ds / (2 pi)
 // weight, 0 (and s = max(lo, 0)) when the window leaves no room.
 __device__ __forceinline__ double ps_mass(double u, double lo, double hi, double m, double g, bool bw,

@@ -114,3 +114,12 @@ def test_colour_matrices_are_exact_fierz():
     # flows (T^a T^b)_ij and (T^b T^a)_ij: sum_col |(ab)_ij|^2 = Tr(a b b a)
     assert c1[0][0] == fierz_trace_product([[1, 2, 2, 1]])
     assert c1[0][1] == fierz_trace_product([[1, 2, 1, 2]])
+
+
+def test_adaptive_entry_points_reject_a_null_handle(lib):
+    """argument errors come back before any device call"""
+    from paper_1305_0708_amd import _lib
+    comb = _lib.heget_result()
+    assert lib.heget_integrate_adaptive(None, 1024, 2, 8, 1000.0, 1, None, comb, None, None, None) \
+        == _lib.HEGET_E_INVALID
+    assert lib.heget_process_grid_dims(None) == -1
