@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "399664768b7af939cd4ff2536f32d3c611a4ce115f6c399ad89f127278a697f2",
+COUNTERS_FP64 = {"source_digest": "a308ae3a2f9505f4ae23a322cb62867e208fff0b298cd9fc296ab81db45c17ef",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 
@@ -136,10 +136,11 @@ def adaptive_leg(torch, H, processes, passes=6, bins=32):
     """heget_integrate_adaptive on the resonance-tree C1: passes of 2^20 FP64
     events through a VEGAS grid refined after each (the BASES role of the
     paper's Sec. 1 and 6).  Wall time per pass includes the per-pass bin sums
-    on the device, the host refinement and the call's own buffer allocation."""
+    and grid refinement on the device and the call's final synchronisation
+    (the handle's buffers are allocated by the warm-up call)."""
     import time
     proc = H.Process(processes.gg_ttbar_6f_bw(), precision="fp64")
-    proc.integrate_adaptive(1 << 16, iterations=2, bins=bins, seed=SEED, sqrt_s=SQRT_S)   # warm-up
+    proc.integrate_adaptive(N_EVENTS, iterations=2, bins=bins, seed=SEED, sqrt_s=SQRT_S)   # warm-up, buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     per, comb, chi2, _ = proc.integrate_adaptive(N_EVENTS, iterations=passes, bins=bins, seed=SEED, sqrt_s=SQRT_S)
@@ -220,7 +221,8 @@ def main():
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
     ap.add_argument("--profile-proc", default="gg_ttbar_6f",
                     help="process of --profile-leg: gg_ttbar_6f (default), gg_4g, gg_4g_ddm, ud_udhh_4b, ee_mumu, "
-                         "or 'generate' for the phase-space kernel of gg_ttbar_6f alone")
+                         "'generate' for the phase-space kernel of gg_ttbar_6f alone, or 'adaptive' for the "
+                         "adaptive integration of its resonance-tree form (FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -243,6 +245,9 @@ def main():
             proc = H.Process(proc_ir, precision=args.profile_leg)
             out = phase_space_leg(torch, proc, args.steps, args.warmup)
             print(json.dumps(out), flush=True)
+            return
+        if args.profile_proc == "adaptive":
+            print(json.dumps(adaptive_leg(torch, H, processes)), flush=True)
             return
         pir = processes.by_name(args.profile_proc)
         proc = H.Process(pir, precision=args.profile_leg)

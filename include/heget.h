@@ -247,11 +247,15 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
  * start and refined after every pass from the sums of w^2 per bin (smoothing
  * over neighbouring bins, compression ((x - 1) / ln x)^1.5, equal shares per new
  * bin).  per_iteration (host, [iterations], may be NULL) gets each pass's
- * result; *combined the inverse-variance average (n_generated, n_accepted,
- * sum_w, sum_w2 summed over the passes); *chi2_per_dof (may be NULL) the
+ * result; *combined the inverse-variance average (a pass with zero error takes
+ * no weight; if every pass has zero error, the plain mean with error 0;
+ * n_generated, n_accepted, sum_w, sum_w2 summed over the passes); *chi2_per_dof (may be NULL) the
  * passes' consistency; grid_out (host, [dims][bins + 1], may be NULL) the
- * final grid.  Synchronises `stream`; allocates and frees its own device
- * buffers (about 9 + dims bytes per event).  Errors: HEGET_E_INVALID (null
+ * final grid.  The passes run back to back on `stream` (the grid refined on
+ * the device between them); the call synchronises `stream` once, at the end.
+ * The handle keeps the device buffers (about 9 + dims bytes per event),
+ * allocated on the first call and grown when a larger n arrives; calls on one
+ * handle must not overlap.  Errors: HEGET_E_INVALID (null
  * handle or combined, n < 2, iterations < 1, bins outside 2 .. 32, sqrt_s <= 0),
  * HEGET_E_UNSUPPORTED (a process without a resonance tree), HEGET_E_OOM,
  * HEGET_E_HIP. */

@@ -461,6 +461,7 @@ void release(heget_process* p) {
   if (p->d_cterm) (void)hipFree(p->d_cterm);
   if (p->d_cfrag) (void)hipFree(p->d_cfrag);
   if (p->d_work) (void)hipFree(p->d_work);
+  if (p->d_adapt) (void)hipFree(p->d_adapt);
   delete p;
 }
 

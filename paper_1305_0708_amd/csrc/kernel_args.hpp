@@ -35,10 +35,12 @@ struct KernelArgs {
   double* psw_out;           // generate: per-event phase-space weight [n], or null
   // adaptive integration (resonance-tree processes): the uniforms of the phase
   // space go through a grid of grid_bins bins per dimension ([dims][grid_bins + 1]
-  // edges); each event's bin per dimension ([dims][n], uint8) and its weight [n]
-  // are written out for the grid's refinement.  Null grid: plain uniforms.
+  // edges); each event's bin per dimension ([dims][grid_bin_stride], uint8) and
+  // its weight [n] are written out for the grid's refinement.  Null grid: plain
+  // uniforms.
   const double* grid;
   int32_t grid_bins;
+  int64_t grid_bin_stride;
   uint8_t* grid_bin_out;
   double* w_out;
   double* partials;          // integrate: [gridDim.x][3] (sum w, sum w^2, accepted), or null

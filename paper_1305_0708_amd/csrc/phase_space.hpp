@@ -101,18 +101,29 @@ __device__ __forceinline__ void ps_uniforms(uint64_t seed, uint64_t event, doubl
 // Adaptive integration: the event's N uniforms through the grid of KernelArgs
 // (bins of [e_j, e_(j+1)] per dimension, u -> e_j + (u B - j)(e_(j+1) - e_j));
 // returns the Jacobian prod B (e_(j+1) - e_j) and records the bins of event i.
+// Every edge is loaded before the first bin is stored: the byte stores may
+// alias the grid as far as the compiler knows, and would otherwise serialise
+// the loads behind them.
 template <int N, class A>
 __device__ __forceinline__ double grid_map(const A& a, int64_t i, double* u) {
   const int B = a.grid_bins;
+  int j[N];
+  double lo[N], hi[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    j[d] = min(int(u[d] * B), B - 1);
+    lo[d] = a.grid[d * (B + 1) + j[d]];
+    hi[d] = a.grid[d * (B + 1) + j[d] + 1];
+  }
   double jac = 1.0;
 #pragma unroll
   for (int d = 0; d < N; ++d) {
-    const double t = u[d] * B;
-    const int j = min(int(t), B - 1);
-    const double lo = a.grid[d * (B + 1) + j], hi = a.grid[d * (B + 1) + j + 1];
-    u[d] = lo + (t - j) * (hi - lo);
-    jac *= B * (hi - lo);
-    if (a.grid_bin_out) a.grid_bin_out[int64_t(d) * a.n + i] = uint8_t(j);
+    u[d] = lo[d] + (u[d] * B - j[d]) * (hi[d] - lo[d]);
+    jac *= B * (hi[d] - lo[d]);
+  }
+  if (a.grid_bin_out) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) a.grid_bin_out[d * a.grid_bin_stride + i] = uint8_t(j[d]);
   }
   return jac;
 }

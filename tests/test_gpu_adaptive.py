@@ -121,3 +121,14 @@ def test_argument_errors(torch, proc):
     rc = L.heget_integrate_adaptive(rambo._h, 1024, 2, 8, ROOTS, 1, None, comb, None, None, None)
     assert rc == _lib.HEGET_E_UNSUPPORTED
     assert math.isfinite(proc.integrate(256, seed=1, sqrt_s=ROOTS)["sigma_gev2"])
+
+
+def test_repeated_calls_give_the_same_bits(torch, proc):
+    """the handle's buffers grow for a larger n and are reused for a smaller
+    one; a call's results depend only on its arguments"""
+    args = dict(iterations=3, bins=12, seed=SEED + 3, sqrt_s=ROOTS)
+    first = proc.integrate_adaptive(3000, **args)
+    proc.integrate_adaptive(9001, **args)
+    again = proc.integrate_adaptive(3000, **args)
+    assert first[0] == again[0] and first[1] == again[1] and first[2] == again[2]
+    assert np.array_equal(first[3], again[3])
