@@ -234,7 +234,8 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
  * reduced on the device in a fixed order.  Synchronises
  * `stream`; fills *out.  The handle keeps a small buffer of per-block partial
  * sums (24 bytes per 256 events), allocated on the first call and grown when a
- * larger n arrives; calls on one handle must not overlap.
+ * larger n arrives, and 24 bytes of pinned host memory for the reduced sums;
+ * calls on one handle must not overlap.
  * Errors: HEGET_E_INVALID, HEGET_E_OOM, HEGET_E_HIP. */
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
                              void* stream);

@@ -462,6 +462,7 @@ void release(heget_process* p) {
   if (p->d_cfrag) (void)hipFree(p->d_cfrag);
   if (p->d_work) (void)hipFree(p->d_work);
   if (p->d_adapt) (void)hipFree(p->d_adapt);
+  if (p->h_res) (void)hipHostFree(p->h_res);
   delete p;
 }
 
@@ -726,8 +727,12 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
       return fail(HEGET_E_OOM, "partials allocation failed");
     p->part_cap = nblocks * 3 + 3;
   }
+  if (!p->h_res && hipHostMalloc(reinterpret_cast<void**>(&p->h_res), 3 * sizeof(double), hipHostMallocDefault) !=
+                       hipSuccess) {
+    p->h_res = nullptr;
+    return fail(HEGET_E_OOM, "pinned result allocation failed");
+  }
   double* d_part = p->d_part;
-  const double s = sqrt_s * sqrt_s;
   KernelArgs a = base_args(p);
   a.n = n;
   a.mom_stride = n;
@@ -736,16 +741,16 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
   a.weight_factor = heget::detail::weight_factor(p, sqrt_s);
   a.partials = d_part;
   heget_status rc = launch(p, a, st);
-  double h[3] = {0, 0, 0};
   if (rc == HEGET_OK) {
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, d_part + 3 * nblocks);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h, d_part + 3 * nblocks, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->h_res, d_part + 3 * nblocks, 3 * sizeof(double),
+                                            hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
   }
   if (rc != HEGET_OK) return rc;
-  heget::detail::fill_result(h, n, out);
+  heget::detail::fill_result(p->h_res, n, out);
   return HEGET_OK;
 }
 

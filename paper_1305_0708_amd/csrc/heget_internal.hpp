@@ -28,6 +28,7 @@ struct heget_process {
   int cterm_words = 0;
   double* d_part = nullptr;  // integrate partials, grown on demand and reused
   int64_t part_cap = 0;
+  double* h_res = nullptr;   // integrate: pinned host copy of the reduced (sum w, sum w^2, accepted)
   void* d_adapt = nullptr;   // adaptive integration buffers, grown on demand and reused
   size_t adapt_cap = 0;
   std::vector<int8_t> hel;   // host copy of the current table
