@@ -126,7 +126,10 @@ typedef struct {
  * A resonance's s_k follows the Breit-Wigner mapping s = m^2 + m Gamma tan(theta),
  * theta uniform over |s - m^2| / (m Gamma) < min(ps_window, m / Gamma) intersected
  * with the kinematic range, or a flat distribution over the kinematic range.
- * Every final particle is massless. */
+ * A final particle has the mass of its leg's particle (HEGET_P_ZERO: massless);
+ * a node's minimal mass is the sum of the final masses below it, and the ranges
+ * are [min_first^2, (M - min_second)^2] for the first daughter of a node of
+ * mass M, [min_second^2, (M - m_first)^2] for the second. */
 enum { HEGET_PS_FLAT = 0, HEGET_PS_BREIT_WIGNER = 1 };
 typedef struct {
   int32_t particle;     /* HEGET_P_* giving the resonance's mass and width (node 0, the collision: ignored) */
@@ -170,7 +173,8 @@ typedef struct {
    * matrix on MFMA (Sec. 5.4's colour sum as a batched dense product). */
   const int8_t* flow_map;             /* [n_flows][n_orderings] */
   /* Phase space of generated events: n_ps_nodes = 0 for RAMBO (flat massless
-   * n-body, constant weight), else the resonance tree ps_nodes[0 .. n_ps_nodes-1]
+   * n-body, constant weight; every final leg must then be massless), else the
+   * resonance tree ps_nodes[0 .. n_ps_nodes-1]
    * (node 0 = the collision; every final leg and every other node the daughter
    * of exactly one node) with the window factor ps_window (> 0; the paper's
    * default is 20).  Part of the kernel's structure (compiled in). */

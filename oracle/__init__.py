@@ -34,6 +34,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 EE_MUMU, GG_TT_6F, GG_4G, UD_UDHH_4B = 0, 1, 2, 3
 GG_GG, GG_GGG, UU_TT, GG_TT, UU_UUHH_4B, WW_HH, ZZ_HH = 10, 11, 12, 13, 14, 16, 17
+UD_UDHHH, WW_HHH, ZZ_HHH = 4, 18, 19
 
 
 class Params(ctypes.Structure):

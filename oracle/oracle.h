@@ -46,7 +46,10 @@ enum {
   OR_GG_TT = 13,        /* g g -> t tbar, stable tops: legs g g t tbar */
   OR_UU_UUHH_4B = 14,   /* u u -> u u H H, H -> b bbar (Fermi-sign check) */
   OR_WW_HH = 16,        /* W- W+ -> H H with on-shell external W (unitarity check) */
-  OR_ZZ_HH = 17         /* Z Z -> H H with on-shell external Z */
+  OR_ZZ_HH = 17,        /* Z Z -> H H with on-shell external Z */
+  OR_UD_UDHHH = 4,      /* u d -> u d H H H by W W and Z Z fusion; legs u d u d H H H */
+  OR_WW_HHH = 18,       /* W- W+ -> H H H with on-shell external W (unitarity check) */
+  OR_ZZ_HHH = 19        /* Z Z -> H H H with on-shell external Z */
 };
 
 int or_nlegs(int proc);

@@ -15,9 +15,11 @@ either the Breit-Wigner mapping
 
 with theta uniform over the window |s_k - m^2| / (m Gamma) < min(window, m / Gamma)
 intersected with the kinematic range, or a flat distribution over the range
-(optionally windowed the same way).  Kinematic range of the first daughter of
-a node of mass M: [0, (M - minimal mass of the second)^2]; of the second:
-[0, (M - sqrt(s_first))^2] (every final particle is massless).
+(optionally windowed the same way).  Final particles have fixed masses (zero
+unless given); the minimal mass of a resonance is the sum of the masses of the
+final particles below it.  Kinematic range of the first daughter of a node of
+mass M: [its minimal mass^2, (M - minimal mass of the second)^2]; of the
+second: [its minimal mass^2, (M - mass of the first)^2].
 
 Uniforms: the same Philox4x32-10 stream as RAMBO (two per counter block, the
 event index in the counter); per node in index order, first one uniform for the
@@ -73,20 +75,30 @@ def _boost(P, M, q):
     return out
 
 
-def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0):
+def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0, leg_mass=None):
     """nodes[k] = (mass, width, mapping, d0, d1, window): node 0 is the collision
     (mass and width ignored), d >= 0 a final leg, d < 0 node -1 - d; mapping
     "bw" or "flat", window None (flat over the kinematic range) or the factor
     of min(window, m / Gamma).  Returns momenta [n][n_legs][4] (legs 0, 1 the
     beams along +-z) and the phase-space weight [n] (0 where a window is empty)."""
     u = uniforms_bulk(seed, n_events, n_uniforms(nodes), counter_offset)
-    return generate_from(u, sqrt_s, nodes, n_legs)
+    return generate_from(u, sqrt_s, nodes, n_legs, leg_mass)
 
 
-def generate_from(u, sqrt_s, nodes, n_legs):
-    """the same from given uniforms u[n][n_uniforms(nodes)]"""
+def _min_mass(nodes, leg_mass, d):
+    """minimal invariant mass of daughter d (a final leg d >= 0, or node -1 - d)"""
+    if d >= 0:
+        return leg_mass[d]
+    node = nodes[-1 - d]
+    return _min_mass(nodes, leg_mass, node[3]) + _min_mass(nodes, leg_mass, node[4])
+
+
+def generate_from(u, sqrt_s, nodes, n_legs, leg_mass=None):
+    """the same from given uniforms u[n][n_uniforms(nodes)]; leg_mass[k] the
+    mass of final leg k (default all zero)"""
     K = len(nodes)
     n = u.shape[0]
+    leg_mass = [0.0] * n_legs if leg_mass is None else [float(x) for x in leg_mass]
     mom = np.zeros((n, n_legs, 4))
     h = 0.5 * sqrt_s
     mom[:, 0] = [h, 0.0, 0.0, h]
@@ -102,12 +114,13 @@ def generate_from(u, sqrt_s, nodes, n_legs):
         # invariant masses of resonant daughters: first, then second
         for j, d in enumerate((d0, d1)):
             if d >= 0:
-                dm[j] = np.zeros(n)
+                dm[j] = np.full(n, leg_mass[d])
                 continue
-            other_mass = dm[0] if j == 1 else np.zeros(n)   # the second's minimal mass is 0
+            other_mass = dm[0] if j == 1 else np.full(n, _min_mass(nodes, leg_mass, d1))
             hi = (M - other_mass) ** 2
+            lo = np.full(n, _min_mass(nodes, leg_mass, d) ** 2)
             node = nodes[-1 - d]
-            s, wj, valid = _sample_s(u[:, iu], np.zeros(n), hi, node[0], node[1], node[2], node[5])
+            s, wj, valid = _sample_s(u[:, iu], lo, hi, node[0], node[1], node[2], node[5])
             iu += 1
             weight *= wj
             dm[j] = np.sqrt(s)

@@ -184,6 +184,47 @@ void vv_hh(const SM& sm, const Boson& B, const CVec4& E1, const Vec4& q1, const 
   out[3] = ig2 * dot(E1, contract(vector_prop(sub(q1, h2), B.num2, B.pole2), E2));
 }
 
+// i*(amplitude pieces) of V(E1,q1) V(E2,q2) -> H(h[0]) H(h[1]) H(h[2]): every
+// tree of the VVH, VVHH, HHH and HHHH vertices, 25 in all.  The vector line runs
+// from E1 to E2; along it sit one, two or three attachments, each a VVH vertex
+// carrying one Higgs or an off-shell H* that splits into the rest, or a VVHH
+// vertex carrying two.  The vector line's momentum after an attachment is q1
+// minus the Higgs momenta attached so far.
+void vv_hhh(const SM& sm, const Boson& B, const CVec4& E1, const Vec4& q1, const CVec4& E2, const Vec4& q2,
+            const Vec4* h, cd* out) {
+  const cd g3 = I1 * B.g_vvh, g4 = I1 * B.g_vvhh, s3 = I1 * sm.g_hhh, s4 = I1 * sm.g_hhhh;
+  auto sp = [&](const Vec4& q) { return scalar_prop(q, sm.mh, sm.wh); };
+  auto vp = [&](const Vec4& q) { return vector_prop(q, B.num2, B.pole2); };
+  auto line1 = [&](const Vec4& k) { return dot(E1, contract(vp(k), E2)); };   // E1 . D(k) . E2
+  const int split[3][3] = {{0, 1, 2}, {1, 0, 2}, {2, 0, 1}};                  // Higgs i alone, pair (j, k)
+  const cd e12 = dot(E1, E2);
+  const Vec4 Q = add(q1, q2);
+  int d = 0;
+  // one attachment: VVH with H* -> H H H (the quartic vertex, or H* -> H H* -> H H H),
+  // or VVHH with one Higgs and an H* -> H H
+  out[d++] = g3 * e12 * sp(Q) * s4;
+  for (const auto& ijk : split) {
+    const Vec4 hjk = add(h[ijk[1]], h[ijk[2]]);
+    out[d++] = g3 * e12 * sp(Q) * s3 * sp(hjk) * s3;
+    out[d++] = g4 * e12 * sp(hjk) * s3;
+  }
+  // two attachments
+  for (const auto& ijk : split) {
+    const int i = ijk[0], j = ijk[1], k = ijk[2];
+    const Vec4 hjk = add(h[j], h[k]);
+    out[d++] = g3 * g3 * line1(sub(q1, h[i])) * sp(hjk) * s3;   // VVH(i), VVH(H* -> j k)
+    out[d++] = g3 * g3 * line1(sub(q1, hjk)) * sp(hjk) * s3;    // VVH(H* -> j k), VVH(i)
+    out[d++] = g3 * g4 * line1(sub(q1, h[i]));                  // VVH(i), VVHH(j, k)
+    out[d++] = g4 * g3 * line1(sub(q1, hjk));                   // VVHH(j, k), VVH(i)
+  }
+  // three VVH attachments, in each order along the line
+  const int order[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (const auto& o : order) {
+    const Vec4 k1 = sub(q1, h[o[0]]), k2 = sub(k1, h[o[1]]);
+    out[d++] = g3 * g3 * g3 * dot(E1, contract(vp(k1), contract(vp(k2), E2)));
+  }
+}
+
 // ------------------------------------------------------------------ C3
 // q(p0) q'(p1) -> q(p2) q'(p3) H H, H -> b(p4) bbar(p5), b(p6) bbar(p7)
 // Quark-line "classes": which outgoing quark each incoming quark turns into,
@@ -270,6 +311,49 @@ void col_qq_qqhh(const int* c, cd* out) {
       for (int j = 0; j < 4; ++j) out[d++] = cls[k] * prs[r];
 }
 
+// u(p0) d(p1) -> u(p2) d(p3) H(p4) H(p5) H(p6) by Z Z and W W fusion: 2 x 25
+// diagrams, the W W class with the Fermi sign of its quark pairing.
+void amp_ud_udhhh(const SM& sm, const Vec4* p, const int* h, cd* M) {
+  const Spinor uin[2] = {u_in(p[0], 0, h[0]), u_in(p[1], 0, h[1])};
+  const Spinor ubout[2] = {ubar_out(p[2], 0, h[2]), ubar_out(p[3], 0, h[3])};
+  int d = 0;
+  for (const FusionClass& fc : classes_ud(sm)) {
+    const Boson B = fc.boson == 0 ? boson_w(sm) : boson_z(sm);
+    const QuarkLine* ls[2] = {&fc.l1, &fc.l2};
+    CVec4 E[2];
+    Vec4 q[2];
+    for (int k = 0; k < 2; ++k) {
+      const QuarkLine& L = *ls[k];
+      q[k] = sub(p[L.in], p[L.out]);
+      const CVec4 J = cscale(I1, current(ubout[L.out - 2], chiral(L.gl, L.gr), uin[L.in]));
+      E[k] = contract(vector_prop(q[k], B.num2, B.pole2), J);
+    }
+    cd part[25];
+    vv_hhh(sm, B, E[0], q[0], E[1], q[1], p + 4, part);
+    for (int j = 0; j < 25; ++j) M[d++] = fc.sign * part[j] / I1;
+  }
+}
+// colour: class 0 connects (0->2, 1->3), class 1 (0->3, 1->2)
+void col_qq_qqhhh(const int* c, cd* out) {
+  const double cls[2] = {double(c[2] == c[0] && c[3] == c[1]), double(c[3] == c[0] && c[2] == c[1])};
+  for (int k = 0; k < 2; ++k)
+    for (int j = 0; j < 25; ++j) out[25 * k + j] = cls[k];
+}
+
+// V(p0) V(p1) -> H(p2) H(p3) H(p4) with on-shell external vectors
+void amp_vv_hhh(const SM& sm, const Boson& B, double mv, const Vec4* p, const int* h, cd* M) {
+  const CVec4 E1 = eps_in(sm, 0, p[0], mv, h[0]);
+  const CVec4 E2 = eps_in(sm, 1, p[1], mv, h[1]);
+  cd part[25];
+  vv_hhh(sm, B, E1, p[0], E2, p[1], p + 2, part);
+  for (int j = 0; j < 25; ++j) M[j] = part[j] / I1;
+}
+void amp_ww_hhh(const SM& sm, const Vec4* p, const int* h, cd* M) { amp_vv_hhh(sm, boson_w(sm), sm.mw, p, h, M); }
+void amp_zz_hhh(const SM& sm, const Vec4* p, const int* h, cd* M) { amp_vv_hhh(sm, boson_z(sm), sm.mz, p, h, M); }
+void col_trivial25(const int*, cd* c) {
+  for (int j = 0; j < 25; ++j) c[j] = 1.0;
+}
+
 // V(p0) V(p1) -> H(p2) H(p3) with on-shell external vectors
 void amp_vv_hh(const SM& sm, const Boson& B, double mv, const Vec4* p, const int* h, cd* M) {
   const CVec4 E1 = eps_in(sm, 0, p[0], mv, h[0]);
@@ -298,6 +382,9 @@ const ProcDef* find_proc(int id) {
     table[OR_GG_TT] = {4, {V0, V0, F, F}, 3, {8, 8, 3, 3}, amp_gg_tt, col_gg_tt};
     table[OR_WW_HH] = {4, {VM, VM, S, S}, 4, {1, 1, 1, 1}, amp_ww_hh, col_trivial4};
     table[OR_ZZ_HH] = {4, {VM, VM, S, S}, 4, {1, 1, 1, 1}, amp_zz_hh, col_trivial4};
+    table[OR_UD_UDHHH] = {7, {F, F, F, F, S, S, S}, 50, {3, 3, 3, 3, 1, 1, 1}, amp_ud_udhhh, col_qq_qqhhh};
+    table[OR_WW_HHH] = {5, {VM, VM, S, S, S}, 25, {1, 1, 1, 1, 1}, amp_ww_hhh, col_trivial25};
+    table[OR_ZZ_HHH] = {5, {VM, VM, S, S, S}, 25, {1, 1, 1, 1, 1}, amp_zz_hhh, col_trivial25};
   });
   auto it = table.find(id);
   return it == table.end() ? nullptr : &it->second;

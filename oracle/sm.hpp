@@ -5,7 +5,7 @@
 //   L_f  = -e Q fbar A f - g_Z fbar Zslash (T3 P_L - Q s_W^2) f
 //          - (g_W / sqrt2) (ubar Wslash+ P_L d + h.c.)
 //   L_h  = g_W m_W H W+.W- + (g_Z m_Z / 2) H Z.Z + (g_W^2/4) H^2 W+.W-
-//          + (g_Z^2/8) H^2 Z.Z - lambda v H^3 - (m_b / v) H bbar b
+//          + (g_Z^2/8) H^2 Z.Z - lambda v H^3 - (lambda / 4) H^4 - (m_b / v) H bbar b
 //   QCD  : Peskin-Schroeder sign conventions, D = d - i g_s A^a T^a.
 // (The paper's HELAS couplings differ from these by field-sign conventions that
 //  cancel in |M|^2.)  Feynman rule = i x coefficient x identical-field factor.
@@ -24,7 +24,7 @@ struct SM {
   cd muw2, muz2;        // complex masses squared (propagator poles)
   cd numw2, numz2;      // masses squared in the unitary-gauge numerator
   cd g_wwh, g_zzh;      // Feynman rule / i for W+W-H and ZZH (metric tensor stripped)
-  double g_wwhh, g_zzhh, g_hhh, y_b;
+  double g_wwhh, g_zzhh, g_hhh, g_hhhh, y_b;
   int gauge_leg;
   explicit SM(const or_params& p) {
     e = std::sqrt(4.0 * PI * p.alpha);
@@ -61,6 +61,7 @@ struct SM {
     g_wwhh = 0.5 * gw * gw;        // 2 x g_W^2/4
     g_zzhh = 0.5 * gz * gz;        // 2 x 2 x g_Z^2/8
     g_hhh = -3.0 * mh * mh / v;    // -3! lambda v with m_H^2 = 2 lambda v^2
+    g_hhhh = -3.0 * mh * mh / (v * v);   // -4! lambda / 4 from the (lambda / 4) H^4 term
     y_b = mb_yuk / v;
     gauge_leg = p.gauge_leg;
   }

@@ -273,7 +273,8 @@ class Gen:
     def _emit_ps_tree(self, w):
         """the process's resonance phase space as straight-line device code:
         per node in index order, the invariant masses of its resonant
-        daughters (first daughter first), then its two-body decay"""
+        daughters (first daughter first; ranges from the final legs' masses
+        below each), then its two-body decay"""
         p = self.p
         tree = p.ps_tree
         nu = sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
@@ -289,19 +290,35 @@ class Gen:
         w(f"  double w = a.grid ? grid_map<{nu}>(a, i, u) : 1.0;")
         w("  const double M0 = a.sqrt_s;")
         w("  const mom P0 = {a.sqrt_s, 0.0, 0.0, 0.0};")
+        def leg_mass(L):
+            part = p.legs[L].particle
+            return "0.0" if part == P_ZERO else f"a.prop[{part}].m"
+
+        def min_mass(d):
+            """minimal invariant mass of daughter d (final leg or node) as a sum of leg masses"""
+            if d >= 0:
+                return [leg_mass(d)] if leg_mass(d) != "0.0" else []
+            node = tree[-1 - d]
+            return min_mass(node[2]) + min_mass(node[3])
+
+        def total(terms):
+            return "(" + " + ".join(terms) + ")" if terms else "0.0"
         iu = 0
         for k, (_, _, d0, d1) in enumerate(tree):
             dm = {}
             for j, d in enumerate((d0, d1)):
                 if d >= 0:
-                    dm[j] = "0.0"
+                    dm[j] = leg_mass(d)
                     continue
                 nd = -1 - d
                 part, mapping = tree[nd][0], tree[nd][1]
-                hi = f"(M{k} - {dm[0]}) * (M{k} - {dm[0]})" if j == 1 else f"M{k} * M{k}"
+                other = dm[0] if j == 1 else total(min_mass(d1))
+                hi = f"M{k} * M{k}" if other == "0.0" else f"(M{k} - {other}) * (M{k} - {other})"
+                mine = total(min_mass(d))
+                lo = "0.0" if mine == "0.0" else f"{mine} * {mine}"
                 bw = "true" if mapping == ir.PS_BREIT_WIGNER else "false"
                 w(f"  double s{nd};")
-                w(f"  w *= ps_mass(u[{iu}], 0.0, {hi}, a.prop[{part}].m, a.prop[{part}].w, {bw}, "
+                w(f"  w *= ps_mass(u[{iu}], {lo}, {hi}, a.prop[{part}].m, a.prop[{part}].w, {bw}, "
                   f"{_c(p.ps_window)}, s{nd});")
                 w(f"  const double M{nd} = sqrt(s{nd});")
                 w(f"  mom P{nd};")

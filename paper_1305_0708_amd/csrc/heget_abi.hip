@@ -148,8 +148,8 @@ heget_status validate(const heget_process_ir* ir) {
     const heget_leg& l = ir->legs[k];
     if (l.kind < 0 || l.kind > 2 || l.particle < 0 || l.particle >= HEGET_N_PARTICLES)
       return fail(HEGET_E_IR, "leg " + std::to_string(k) + ": bad kind or particle");
-    if (k >= 2 && l.particle != HEGET_P_ZERO)
-      return fail(HEGET_E_UNSUPPORTED, "final-state legs must be massless (RAMBO and resonance-tree phase space)");
+    if (k >= 2 && l.particle != HEGET_P_ZERO && ir->n_ps_nodes == 0)
+      return fail(HEGET_E_UNSUPPORTED, "RAMBO phase space needs massless final-state legs (give a resonance tree)");
   }
   if (ir->n_couplings < 1 || !ir->couplings) return fail(HEGET_E_IR, "no couplings");
   for (int k = 0; k < ir->n_couplings; ++k)

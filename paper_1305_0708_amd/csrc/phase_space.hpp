@@ -106,6 +106,7 @@ __device__ __forceinline__ void ps_uniforms(uint64_t seed, uint64_t event, doubl
 // the loads behind them.
 template <int N, class A>
 __device__ __forceinline__ double grid_map(const A& a, int64_t i, double* u) {
+#pragma clang fp contract(off)
   const int B = a.grid_bins;
   int j[N];
   double lo[N], hi[N];
@@ -128,10 +129,15 @@ __device__ __forceinline__ double grid_map(const A& a, int64_t i, double* u) {
   return jac;
 }
 
+// The tree's arithmetic is not contracted into fused multiply-adds: each
+// product and sum rounds on its own, as in a plain IEEE evaluation, so that
+// masses near a threshold (where lambda cancels) come out with the same bits.
+
 // Invariant mass s of a resonance within [lo, hi]; returns its ds / (2 pi)
 // weight, 0 (and s = max(lo, 0)) when the window leaves no room.
 __device__ __forceinline__ double ps_mass(double u, double lo, double hi, double m, double g, bool bw,
                                           double window, double& s) {
+#pragma clang fp contract(off)
   const double inv2pi = 0.15915494309189533577;
   if (bw) {
     const double w = fmin(window, m / g);
@@ -154,6 +160,7 @@ __device__ __forceinline__ double ps_mass(double u, double lo, double hi, double
 
 // q, given in the rest frame of P (mass M), in the frame where P is given
 __device__ __forceinline__ mom ps_boost(const mom& P, double M, const mom& q) {
+#pragma clang fp contract(off)
   const double pq = P.x * q.x + P.y * q.y + P.z * q.z;
   const double e = (P.e * q.e + pq) / M;
   const double f = (q.e + e) / (P.e + M);
@@ -165,6 +172,7 @@ __device__ __forceinline__ mom ps_boost(const mom& P, double M, const mom& q) {
 // P at rest (the collision) is not boosted.
 __device__ __forceinline__ double ps_decay(double uc, double uphi, const mom& P, double M, double m0, double m1,
                                            bool at_rest, mom& q0, mom& q1) {
+#pragma clang fp contract(off)
   const double pi = 3.14159265358979323846;
   const double lam = fmax((M * M - (m0 + m1) * (m0 + m1)) * (M * M - (m0 - m1) * (m0 - m1)), 0.0);
   const double rl = sqrt(lam);

@@ -93,8 +93,8 @@ PS_FLAT, PS_BREIT_WIGNER = 0, 1
 
 def validate_ps_tree(tree, legs, window):
     """the resonance tree: node 0 the collision, every final leg and every
-    other node the daughter of exactly one node, daughters after their parent,
-    massless final legs"""
+    other node the daughter of exactly one node, daughters after their parent
+    (final legs may be massive)"""
     nl, K = len(legs), len(tree)
     if not 1 <= K <= 16:
         raise ValueError("phase-space tree: 1..16 nodes")
@@ -116,8 +116,6 @@ def validate_ps_tree(tree, legs, window):
                 seen_nodes.append(j)
     if sorted(seen_legs) != list(range(2, nl)) or sorted(seen_nodes) != list(range(1, K)):
         raise ValueError("phase-space tree: every final leg and node 1.. must be a daughter exactly once")
-    if any(legs[L].particle != P_ZERO for L in range(2, nl)):
-        raise ValueError("phase-space tree: final legs must be massless")
 
 
 @dataclass
@@ -237,6 +235,8 @@ class Process:
                     raise ValueError("ordering template: every jamp row is the same combination")
         if self.ps_tree is not None:
             validate_ps_tree(self.ps_tree, self.legs, self.ps_window)
+        elif any(leg.particle != P_ZERO for leg in self.legs[2:]):
+            raise ValueError("RAMBO phase space needs massless final legs (give a resonance tree)")
         return self
 
     # -------------------------------------------------------------- fingerprint

@@ -135,9 +135,81 @@ def ud_udhh_4b(sqrt_s=2000.0):
                    sm_overrides={"complex_mass": 1}).validate()
 
 
+def ud_udhhh(sqrt_s=2000.0):
+    """u d -> u d H H H via W W and Z Z fusion with external Higgs bosons (the
+    paper's test of the quartic scalar vertex, Sec. 3.5 and 4.2.8): per fusion
+    class, every tree of VVH, VVHH, HHH and HHHH that joins the two vector
+    currents to the three Higgs bosons, 25 diagrams:
+
+      one attachment   VVH -> H* -> H H H (quartic), VVH -> H* -> H H*(-> H H) (3),
+                       VVHH(H, H*(-> H H)) (3);
+      two attachments  VVH(H) then VVH(H* -> H H), VVH(H* -> H H) then VVH(H),
+                       VVH(H) then VVHH(H H), VVHH(H H) then VVH(H) (3 each);
+      three            VVH(H) VVH(H) VVH(H) in each order (6).
+
+    The W W class pairs the quark lines differently from Z Z: Fermi sign -1.
+    Colour flows: the two quark pairings, matrix [[9, 3], [3, 9]].  Phase
+    space: a flat tree u (d (H (H H))) with the Higgs mass on the final legs."""
+    legs = [Leg(F, True, +1, colour=3, name="u"), Leg(F, True, +1, colour=3, name="d"),
+            Leg(F, False, +1, colour=3, name="u"), Leg(F, False, +1, colour=3, name="d"),
+            Leg(S, False, particle=P_H, name="H"), Leg(S, False, particle=P_H, name="H"),
+            Leg(S, False, particle=P_H, name="H")]
+    cpl = [Coupling("z_ff", charge=Q_U, t3=0.5), Coupling("z_ff", charge=Q_D, t3=-0.5),
+           Coupling("w_ff"), Coupling("zzh"), Coupling("wwh"), Coupling("zzhh"), Coupling("wwhh"),
+           Coupling("hhh"), Coupling("hhhh")]
+    ZU, ZD, W, ZZH, WWH, ZZHH, WWHH, HHH, HHHH = range(9)
+    calls = []
+    slot = [7]
+
+    def cur(op, ins, cp, prop):
+        s = slot[0]
+        slot[0] += 1
+        calls.append(Call(op, ins, s, cp, prop))
+        return s
+    splits = [(4, 5, 6), (5, 4, 6), (6, 4, 5)]          # Higgs i alone, pair (j, k)
+    pair = {(j, k): cur("hss", (j, k), HHH, P_H) for _, j, k in splits}
+    classes = [
+        (cur("jio", (0, 2), ZU, P_Z), cur("jio", (1, 3), ZD, P_Z), P_Z, ZZH, ZZHH, +1.0),
+        (cur("jio", (0, 3), W, P_W), cur("jio", (1, 2), W, P_W), P_W, WWH, WWHH, -1.0),
+    ]
+    amp = 0
+    jamp = [[], []]
+
+    def add(op, ins, cp, flow, sign):
+        nonlocal amp
+        calls.append(Call(op, ins, amp, cp))
+        jamp[flow].append((amp, sign))
+        amp += 1
+    for flow, (v1, v2, boson, c3, c4, sgn) in enumerate(classes):
+        hs = cur("hvv", (v1, v2), c3, P_H)
+        add("ssss", (hs, 4, 5, 6), HHHH, flow, sgn)
+        for i, j, k in splits:
+            add("sss", (hs, i, pair[(j, k)]), HHH, flow, sgn)
+            add("vvss", (v1, v2, i, pair[(j, k)]), c4, flow, sgn)
+        # each vector current is used right after it is made (short live ranges)
+        for i, j, k in splits:
+            vt = cur("jvs", (v1, i), c3, boson)            # V1 emits Higgs i first
+            add("vvs", (vt, v2, pair[(j, k)]), c3, flow, sgn)
+            add("vvss", (vt, v2, j, k), c4, flow, sgn)
+            for b, c in ((j, k), (k, j)):
+                vtt = cur("jvs", (vt, b), c3, boson)
+                add("vvs", (vtt, v2, c), c3, flow, sgn)
+            vtp = cur("jvs", (v1, pair[(j, k)]), c3, boson)
+            add("vvs", (vtp, v2, i), c3, flow, sgn)
+            vss = cur("jvss", (v1, j, k), c4, boson)
+            add("vvs", (vss, v2, i), c3, flow, sgn)
+    assert amp == 50
+    colour = [[Fraction(9), Fraction(3)], [Fraction(3), Fraction(9)]]
+    tree = [(P_ZERO, ir.PS_FLAT, 2, -2), (P_ZERO, ir.PS_FLAT, 3, -3), (P_ZERO, ir.PS_FLAT, 4, -4),
+            (P_ZERO, ir.PS_FLAT, 5, 6)]
+    return Process("ud_udhhh", legs, cpl, calls, n_amps=amp, n_flows=2, jamp=jamp, colour=colour,
+                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=9, symmetry=6,
+                   sm_overrides={"complex_mass": 1}, ps_tree=tree).validate()
+
+
 def by_name(name):
     if name in ("gg_4g", "gg_4g_ddm"):
         from .gluons import gg_ng
         return gg_ng(6, basis="trace" if name == "gg_4g" else "ddm")
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
-            "ud_udhh_4b": ud_udhh_4b}[name]()
+            "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh}[name]()

@@ -1,0 +1,136 @@
+"""GPU parity of u d -> u d H H H by weak-boson fusion (the paper's test of the
+quartic scalar vertex, Sec. 3.5; HEGET functions of Sec. 4.2.7-4.2.8): |M|^2
+of the 50-diagram kernel (ssssxx, hssxxx, jvssxx, vvssxx, jvsxxx, vvsxxx,
+hvvxxx) against the oracle's Feynman-diagram sum, the momenta and weights of
+its massive-leg phase-space tree, and the cross section."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NAME = "ud_udhhh"
+ROOTS = 2000.0
+SEED = 0x48484821
+MH = 125.0
+LEG_MASS = [0, 0, 0, 0, MH, MH, MH]
+
+
+def oracle_tree():
+    return [(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None),
+            (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def proc(torch):
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    return H.Process(processes.by_name(NAME))
+
+
+def to_aos(t):
+    return np.ascontiguousarray(np.transpose(t.cpu().numpy(), (2, 0, 1)))
+
+
+def to_soa(torch, mom):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
+
+
+def rotated(mom, seed):
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    out = mom.copy()
+    out[..., 1:] = mom[..., 1:] @ q.T
+    return out
+
+
+def test_me2_matches_oracle(torch, oracle, proc):
+    """momenta in: the oracle's tree events (2,000 + a ragged 37) fed to both
+    sides.  |F_gpu/F_oracle - 1| <= 1e-12 per event, except where the event's
+    own FP64 rounding floor nu is larger: V V -> H H H cancels between its 25
+    diagrams (the gauge cancellation the paper's Sec. 6 discusses), and the
+    oracle's F moves by nu under rotations of the frame; there the bound is
+    16 nu (measured: at most 1.3 nu).  The cancellation is stronger than in
+    V V -> H H: 13 % of these events carry a floor above 1e-12 (median error
+    8e-14), so the share within 1e-12 is held to 75 % rather than the 98 %
+    of the other processes."""
+    from oracle import phase_space_tree as T
+    prm = oracle.params(cms=1)
+    for n in (2000, 37):
+        mom, w = T.generate(SEED + n, n, ROOTS, oracle_tree(), 7, leg_mass=LEG_MASS)
+        assert np.all(w > 0)
+        me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+        ref = oracle.me2(oracle.UD_UDHHH, mom, prm)
+        err = np.abs(me2 - ref) / np.abs(ref)
+        bad = err > 1e-12
+        nu = np.zeros(bad.sum())
+        for s in range(8):
+            f = oracle.me2(oracle.UD_UDHHH, rotated(mom[bad], s), prm)
+            nu = np.maximum(nu, np.abs(f / ref[bad] - 1))
+        print(f"ud->udHHH FP64 n={n}: max rel err {err.max():.2e}, median {np.median(err):.2e}, "
+              f"{bad.sum()} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
+        assert np.all(err[bad] <= 16 * nu)
+        assert bad.mean() < 0.25
+
+
+def test_mixed_precision_error(torch, oracle):
+    """the mixed path (FP32 wavefunctions and chain, FP64 kinematics and sums):
+    its error against the FP64 oracle is reported; the bound is FP32's scale"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    from oracle import phase_space_tree as T
+    mixed = H.Process(processes.by_name(NAME), precision="mixed")
+    mom, _ = T.generate(SEED + 1, 4096, ROOTS, oracle_tree(), 7, leg_mass=LEG_MASS)
+    me2 = mixed.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+    ref = oracle.me2(oracle.UD_UDHHH, mom, oracle.params(cms=1))
+    err = np.abs(me2 - ref) / np.abs(ref)
+    print(f"ud->udHHH mixed: max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert np.median(err) < 1e-4
+    assert err.max() < 1e-1
+
+
+@pytest.mark.parametrize("n,offset", [(1000, 0), (4099, 777)])
+def test_momenta_and_weights_match_oracle(torch, oracle, proc, n, offset):
+    from oracle import phase_space_tree as T
+    mom, w = proc.generate(n, seed=SEED, counter_offset=offset, sqrt_s=ROOTS, want_weights=True)
+    torch.cuda.synchronize()
+    ref_mom, ref_w = T.generate(SEED, n, ROOTS, oracle_tree(), 7, counter_offset=offset, leg_mass=LEG_MASS)
+    got = to_aos(mom)
+    assert np.abs(got - ref_mom).max() < 1e-12 * ROOTS
+    msq = got[:, 4:, 0] ** 2 - (got[:, 4:, 1:] ** 2).sum(-1)
+    assert np.abs(msq - MH * MH).max() < 1e-9 * ROOTS ** 2
+    w = w.cpu().numpy()
+    assert np.all(ref_w > 0)
+    assert np.abs(w / ref_w - 1).max() < 1e-12
+
+
+def test_integrate_matches_oracle(torch, oracle, proc):
+    """sigma from the GPU's own events against the oracle's own (flat tree, no
+    resonance poles: the two generators agree to ~1e-15); sigma inherits the
+    per-event rounding floor of the gauge cancellation: 1e-11, as for the
+    H H fusion process"""
+    from oracle import phase_space_tree as T
+    n = 1 << 12
+    r = proc.integrate(n, seed=SEED, sqrt_s=ROOTS)
+    mom, w = T.generate(SEED, n, ROOTS, oracle_tree(), 7, leg_mass=LEG_MASS)
+    f = oracle.me2(oracle.UD_UDHHH, mom, oracle.params(cms=1))
+    sig, err, _, _ = oracle.cross_section(f, w, ROOTS, proc.ir.n_a_n_b, proc.ir.symmetry)
+    print(f"ud->udHHH sigma: GPU {r['sigma_gev2']:.15e} oracle {sig:.15e} rel {r['sigma_gev2'] / sig - 1:.2e}")
+    assert r["n_generated"] == n and r["n_accepted"] == n
+    assert abs(r["sigma_gev2"] / sig - 1) <= 1e-11
+    assert abs(r["err_gev2"] / err - 1) <= 1e-9
+
+
+def test_adaptive_integration_runs(torch, proc):
+    """the adaptive integrator maps the flat tree's 11 uniforms"""
+    assert proc.grid_dims == 11
+    per, comb, chi2, grid = proc.integrate_adaptive(1 << 14, iterations=3, bins=16, seed=SEED, sqrt_s=ROOTS)
+    assert all(p["sigma_gev2"] > 0 for p in per)
+    assert np.all(np.diff(grid, axis=1) > 0)

@@ -393,3 +393,76 @@ def test_spinor_identities(oracle):
     # directions along -z and +z
     for p in ([100.0, 0, 0, -100.0], [100.0, 0, 0, 100.0]):
         assert oracle.selfcheck_spinors(np.array(p), 0.0) < 1e-13
+
+
+# ------------------------------------------------------------------ Higgs triple (SSSS)
+MH = 125.0
+
+
+def hhh_tree():
+    """u d -> u d H H H by successive two-body splittings, all flat: (u (d (H (H H))))"""
+    return [(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None),
+            (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)]
+
+
+def hhh_events(seed, n, rs):
+    from oracle import phase_space_tree as T
+    mom, w = T.generate(seed, n, rs, hhh_tree(), 7, leg_mass=[0, 0, 0, 0, MH, MH, MH])
+    assert np.all(w > 0)
+    return mom
+
+
+@pytest.mark.parametrize("proc,mass", [("WW_HHH", 91.1876 * math.sqrt(1 - 0.2222)), ("ZZ_HHH", 91.1876)])
+def test_longitudinal_vv_hhh_unitarity(oracle, proc, mass):
+    """V_L V_L -> H H H: single diagrams grow with the energy relative to the sum;
+    with every tree of VVH, VVHH, HHH and HHHH at its coupling the sum falls like
+    1/E^2 (|M| drops to ~0.02 from 2 to 20 TeV at fixed decay angles).  Leaving
+    out the quartic scalar diagram, flipping the sign of a VVHH diagram, dropping
+    the triple vector-exchange diagrams or giving a propagator the wrong momentum
+    leaves ratios of 0.77 or more"""
+    from oracle import phase_space_tree as T
+    pid = getattr(oracle, proc)
+    prm = oracle.params(cms=1, wz=0.0, wh=0.0)
+    H = oracle.helicities(pid)
+    k00 = [k for k, h in enumerate(H) if h[0] == 0 and h[1] == 0][0]
+    tree = [(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, 4, None)]
+    u = np.array([[0.4, 0.3, 0.7, 0.55, 0.2]])
+    amps = []
+    for rs in (2000.0, 20000.0):
+        mom, _ = T.generate_from(u, rs, tree, 5, leg_mass=[0, 0, MH, MH, MH])
+        E = rs / 2
+        pv = math.sqrt(E * E - mass * mass)
+        mom[0, 0] = [E, 0, 0, pv]
+        mom[0, 1] = [E, 0, 0, -pv]
+        amps.append(math.sqrt(oracle.me2_per_helicity(pid, mom[0], prm)[k00]))
+    assert amps[0] > 0
+    assert amps[1] / amps[0] < 0.05
+
+
+def test_hhh_bose_symmetry(oracle):
+    mom = hhh_events(21, 6, 2000.0)
+    prm = oracle.params(cms=1)
+    f = oracle.me2(oracle.UD_UDHHH, mom, prm)
+    for perm in itertools.permutations((4, 5, 6)):
+        moved = mom.copy()
+        moved[:, [4, 5, 6]] = mom[:, list(perm)]
+        assert np.max(np.abs(oracle.me2(oracle.UD_UDHHH, moved, prm) / f - 1)) < 1e-12
+
+
+def test_hhh_lorentz_invariance(oracle):
+    mom = hhh_events(22, 4, 2000.0)
+    prm = oracle.params(cms=1)
+    f = oracle.me2(oracle.UD_UDHHH, mom, prm)
+    for b in ([0.3, 0.2, -0.5], [0.0, 0.0, 0.9]):
+        g = oracle.me2(oracle.UD_UDHHH, boost(mom, b), prm)
+        assert np.max(np.abs(g / f - 1)) < 1e-10
+    g = oracle.me2(oracle.UD_UDHHH, rotate(mom, [1, 2, 3], 0.7), prm)
+    assert np.max(np.abs(g / f - 1)) < 1e-10
+
+
+def test_hhh_helicity_selection(oracle):
+    # vector couplings of massless quarks conserve helicity along each line:
+    # 4 of the 16 quark helicity patterns survive (the W W class only for left-handed)
+    mom = hhh_events(23, 1, 2000.0)[0]
+    ph = oracle.me2_per_helicity(oracle.UD_UDHHH, mom, oracle.params(cms=1))
+    assert np.sum(ph > 1e-20 * ph.sum()) == 4

@@ -101,3 +101,52 @@ def test_mappings_of_one_window_agree(T):
     _, wf = T.generate(22, N, ROOTS, c1_tree("flat"), 8)
     eb, ef = wb.std() / math.sqrt(N), wf.std() / math.sqrt(N)
     assert abs(wb.mean() - wf.mean()) < 4.0 * math.hypot(eb, ef), (wb.mean(), eb, wf.mean(), ef)
+
+
+MH = 125.0
+
+
+def lam(a, b, c):
+    return a * a + b * b + c * c - 2 * a * b - 2 * a * c - 2 * b * c
+
+
+def test_massive_two_body_weight_is_exact(T):
+    """collision into two massive particles: dPhi_2 = lambda^(1/2)(s, m1^2, m2^2) / (8 pi s)"""
+    m1, m2 = 125.0, 91.1876
+    mom, w = T.generate(4, 500, ROOTS, [(0.0, 0.0, None, 2, 3, None)], 4, leg_mass=[0, 0, m1, m2])
+    s = ROOTS ** 2
+    assert np.allclose(w, math.sqrt(lam(s, m1 * m1, m2 * m2)) / (8 * math.pi * s), rtol=1e-14, atol=0)
+    assert np.abs(msq(mom[:, 2]) - m1 * m1).max() < 1e-12 * s
+    assert np.abs(msq(mom[:, 3]) - m2 * m2).max() < 1e-12 * s
+
+
+HHH_MASSES = [0, 0, 0, 0, MH, MH, MH]
+
+
+def test_massive_legs_conservation_and_shells(T):
+    tree = [(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None),
+            (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)]
+    mom, w = T.generate(8, 5000, ROOTS, tree, 7, leg_mass=HHH_MASSES)
+    assert np.all(w > 0)
+    assert np.abs(mom[:, 2:].sum(1) - [ROOTS, 0, 0, 0]).max() < 1e-11 * ROOTS
+    m2 = np.array(HHH_MASSES[2:]) ** 2
+    assert np.abs(msq(mom[:, 2:]) - m2).max() < 1e-10 * ROOTS ** 2
+
+
+def test_massive_volume_does_not_depend_on_the_tree(T):
+    """the volume of the u d H H H final state (two massless, three of 125 GeV)
+    from two different factorisations agrees within the Monte Carlo errors (a
+    wrong two-body weight or daughter energy with masses changes one of them;
+    a range too wide leaves events of zero weight, which the conservation test
+    rejects)"""
+    trees = ([(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None),
+              (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)],
+             [(0.0, 0.0, None, -2, -3, None), (0.0, 0.0, "flat", 2, 3, None),
+              (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)])
+    est = []
+    for k, tree in enumerate(trees):
+        _, w = T.generate(11 + k, 200000, 700.0, tree, 7, leg_mass=HHH_MASSES)
+        est.append((w.mean(), w.std() / math.sqrt(w.size)))
+    (a, ea), (b, eb) = est
+    assert abs(a - b) < 4 * math.hypot(ea, eb)
+    assert ea < 0.01 * a and eb < 0.01 * b
