@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "a308ae3a2f9505f4ae23a322cb62867e208fff0b298cd9fc296ab81db45c17ef",
+COUNTERS_FP64 = {"source_digest": "126630e4f0c8cb1697f334c4933b544804b825dac70640c9e6f9216de94e9c7f",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 

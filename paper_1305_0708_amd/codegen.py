@@ -663,7 +663,7 @@ class Gen:
         cand = []
         for nm, us in uses.items():
             if all(rv and lvl >= first_real for lvl, rv in us):
-                cand.append((min(min(lvl for lvl, _ in us), last_real), nm))
+                cand.append((min(lvl for lvl, _ in us), nm))
         loads, off = {}, 0
         budget = min(STASH_WORDS, NEST_LDS_WORDS - inner_words) if inner_words else STASH_WORDS
         for lvl, nm in sorted(cand, key=lambda c: (c[0], list(self._kin).index(c[1]))):
@@ -701,6 +701,15 @@ class Gen:
             k, fi = it.data
             c = p.calls[k]
             w(f"{ind}const cx<T> amp{c.out} = spinor_dot(bra{c.out}, {self._nest_arg(fi)});")
+        elif it.kind == "vbra":
+            k, vo, scal = it.data
+            c = p.calls[k]
+            kfac = " * ".join([f"g{c.cpl}_0"] + [self._nest_arg(a) for a in scal])
+            w(f"{ind}const wf<T> bra{c.out} = vs_bra<T>({self._nest_arg(vo)}, {kfac});")
+        elif it.kind == "vdot":
+            k, v = it.data
+            c = p.calls[k]
+            w(f"{ind}const cx<T> amp{c.out} = vec_dot(bra{c.out}, {self._nest_arg(v)});")
         elif it.kind == "ksum":
             f, g, members = it.data
             expr = " + ".join(_coef_expr(cc, f"amp{a}") for a, cc in members)
@@ -710,8 +719,9 @@ class Gen:
             comps = [" + ".join(_coef_expr(cc, f"bra{a}.c[{m}]") for a, cc in members) for m in range(4)]
             w(f"{ind}const wf<T> bj{f}_{g} = {{{{{', '.join(comps)}}}}};")
         elif it.kind == "kdot":
-            f, g, ket = it.data
-            w(f"{ind}const cx<T> K{f}_{g} = spinor_dot(bj{f}_{g}, {self._nest_arg(ket)});")
+            f, g, ket, vector = it.data
+            prod = "vec_dot" if vector else "spinor_dot"
+            w(f"{ind}const cx<T> K{f}_{g} = {prod}(bj{f}_{g}, {self._nest_arg(ket)});")
         elif it.kind == "jamp":
             f, parts = it.data
             terms = [(" * ".join([f"w{s}" for s in facs] + [f"K{f}_{g}"])) for g, facs in parts]

@@ -726,6 +726,18 @@ template <class T>
 __device__ __forceinline__ cx<T> vvssxx(const wf<T>& v1, const wf<T>& v2, cx<T> s1, cx<T> s2, cx<T> gc) {
   return gc * dot(v1, v2) * s1 * s2;
 }
+// The vector bra of a VVS or VVSS amplitude: vvsxxx(v1, v2, s, gc) =
+// vec_dot(vs_bra(v1, gc s), v2) and vvssxx(v1, v2, s1, s2, gc) =
+// vec_dot(vs_bra(v1, gc s1 s2), v2).  Lets a loop nest form k v1 once in an
+// outer loop and contract it (or a sum of such bras) with many v2.
+template <class T>
+__device__ __forceinline__ wf<T> vs_bra(const wf<T>& v, cx<T> k) {
+  return {{k * v.c[0], k * v.c[1], k * v.c[2], k * v.c[3]}};
+}
+template <class T>
+__device__ __forceinline__ cx<T> vec_dot(const wf<T>& b, const wf<T>& v) {
+  return dot(b, v);
+}
 template <class T, bool MASSIVE>
 __device__ __forceinline__ wf<T> jvssxx(const wf<T>& vc, cx<T> s1, cx<T> s2, cx<T> gc, vec<T> q, cx<T> inv_m2,
                                         cx<T> dinv) {

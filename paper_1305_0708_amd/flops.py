@@ -21,6 +21,8 @@ OP_FLOPS = {
     "iov": 2 * WEYL_C + 2 * (3 * CMUL + CADD) + CADD,           # 114
     "ffv_bra": 2 * WEYL_C + 4 * CMUL,                           # 96: <fo| Vslash (g0 P_L + g1 P_R)
     "spinor_dot": 4 * CMUL + 3 * CADD,                          # 30
+    "vs_bra": 5 * CMUL,                                         # 30: (gc s) x v, four components
+    "vec_dot": 4 * CMUL + 3 * CADD,                             # 30: Minkowski product
     "vvv_r3": 12 + DOT_CC + 2 * DOT_CR + 3 * RMUL + 4 * (RMUL + 2 * CMUL + 2 * CADD),   # 146
     "gggg_r4": 2 * DOT_CC + 2 * RMUL + 4 * (2 * CMUL + CADD),   # 120
     "gggg_r2": 2 * DOT_CC + 2 * RMUL + 4 * (2 * CMUL + CADD),   # 120

@@ -132,7 +132,7 @@ ONE = None   # an argument slot replaced by the scalar 1 (its value deferred as 
 
 @dataclass
 class Item:
-    kind: str          # "ext", "call", "mat", "bra", "dot", "ksum", "jamp"
+    kind: str          # "ext", "call", "mat", "bra", "dot", "vbra", "vdot", "ksum", "bsum", "kdot", "jamp"
     level: int         # loop level (-1: before the loops)
     data: tuple
     flops: int
@@ -155,7 +155,10 @@ def schedule(proc):
         is linear in each wavefunction input) and the scalar becomes a factor
         of the result, carried to the amplitudes;
       * an FFV amplitude whose |fi> sits deeper than <fo| and V is split into
-        a bra formed in the outer loop and a spinor product (plan);
+        a bra formed in the outer loop and a spinor product (plan); a VVS or
+        VVSS amplitude whose one vector sits deeper than all its other inputs
+        likewise into the vector bra gc S V of the outer inputs and a
+        Minkowski product with the deeper vector;
       * each jamp is sum_groups (product of the group's deferred factors) x
         (sum of the group's amplitude cores), the inner sums formed in the
         loop of their amplitudes.
@@ -168,6 +171,7 @@ def schedule(proc):
     fac = {k: () for k in range(nl)}          # ((slot, level), ...) deferred scalar factors
     items = [Item("ext", pos[L], (L,), _ext_flops(proc.legs[L])) for L in pl.order]
     amp_fac, amp_lev = {}, {}
+    vcall = {}       # split VVS / VVSS amplitudes: the plain call, if their bra is not combined
     for k, c in enumerate(proc.calls):
         ins = list(c.ins)
         args, lv, f = [], -1, ()
@@ -199,11 +203,25 @@ def schedule(proc):
                     lv = max(lv, clev[x])
         if c.op in AMP_OPS:
             fi_lev = clev[ins[0]] if c.op == "iov" else None
+            vdeep = None
+            if c.op in ("vvs", "vvss"):
+                # the deeper vector operand becomes the ket of a vector bra
+                d = 0 if clev[ins[0]] > clev[ins[1]] else 1
+                rest = [clev[ins[1 - d]]] + [clev[x] for x, a in zip(ins[2:], args[2:]) if a is not ONE]
+                if clev[ins[d]] > max(rest):
+                    vdeep = (d, max(rest))
             if c.op == "iov" and args[0] is not ONE and max(clev[ins[1]], clev[ins[2]]) < fi_lev:
                 blev = max(clev[ins[1]], clev[ins[2]])
                 items.append(Item("bra", blev, (k, args[1], args[2]), flops.OP_FLOPS["ffv_bra"]))
                 items.append(Item("dot", fi_lev, (k, args[0]), flops.OP_FLOPS["spinor_dot"]))
                 amp_lev[c.out] = fi_lev
+            elif vdeep is not None:
+                d, blev = vdeep
+                items.append(Item("vbra", blev, (k, args[1 - d], tuple(args[2:])),
+                                  flops.OP_FLOPS["vs_bra"] + flops.CMUL * (len(args) - 3)))
+                items.append(Item("vdot", clev[ins[d]], (k, args[d]), flops.OP_FLOPS["vec_dot"]))
+                amp_lev[c.out] = clev[ins[d]]
+                vcall[c.out] = Item("call", clev[ins[d]], (k, tuple(args)), flops.call_flops(c))
             else:
                 items.append(Item("call", lv, (k, tuple(args)), flops.call_flops(c)))
                 amp_lev[c.out] = lv
@@ -217,10 +235,10 @@ def schedule(proc):
     # split FFV amplitudes: bra level and ket argument, to combine bras before the product
     split = {}
     for it in items:
-        if it.kind == "bra":
+        if it.kind in ("bra", "vbra"):
             split[proc.calls[it.data[0]].out] = [it.level, None, it]
     for it in items:
-        if it.kind == "dot":
+        if it.kind in ("dot", "vdot"):
             split[proc.calls[it.data[0]].out][1] = it.data[1]
     combined = set()      # amplitudes whose every jamp term goes through a combined bra
     jamp_items = []
@@ -235,9 +253,10 @@ def schedule(proc):
                 # sum_a c_a <bra_a|ket> = <sum_a c_a bra_a|ket>
                 blev = max(split[a][0] for a, _ in members)
                 ket = kets.pop()
+                vector = split[members[0][0]][2].kind == "vbra"
                 jamp_items.append(Item("bsum", blev, (fl, gi, tuple(members)), 4 * flops.CADD * (len(members) - 1)))
-                jamp_items.append(Item("kdot", max(amp_lev[a] for a, _ in members), (fl, gi, ket),
-                                       flops.OP_FLOPS["spinor_dot"]))
+                jamp_items.append(Item("kdot", max(amp_lev[a] for a, _ in members), (fl, gi, ket, vector),
+                                       flops.OP_FLOPS["vec_dot" if vector else "spinor_dot"]))
                 combined.update(a for a, _ in members)
             else:
                 klev = max(amp_lev[a] for a, _ in members)
@@ -249,8 +268,18 @@ def schedule(proc):
     # the products of amplitudes used only through combined bras are not needed
     needed = {a for it in jamp_items if it.kind == "ksum" for a, _ in it.data[2]}
     items = [it for it in items
-             if not (it.kind == "dot" and proc.calls[it.data[0]].out in combined
+             if not (it.kind in ("dot", "vdot") and proc.calls[it.data[0]].out in combined
                      and proc.calls[it.data[0]].out not in needed)]
+    # a vector bra pays only when it is summed with others: else the plain call
+    out = []
+    for it in items:
+        a = proc.calls[it.data[0]].out if it.kind in ("vbra", "vdot") else None
+        if a is not None and a not in combined:
+            if it.kind == "vdot":
+                out.append(vcall[a])
+            continue
+        out.append(it)
+    items = out
     items += jamp_items
     mult, m = {-1: 1}, 1
     for i, L in enumerate(pl.order):
