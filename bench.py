@@ -153,13 +153,10 @@ def adaptive_leg(torch, H, processes, passes=6, bins=32):
             "sigma_pb": comb["sigma_pb"], "sigma_err_pb": comb["err_pb"], "chi2_per_dof": chi2}
 
 
-def hhh_leg(torch, H, processes, flops, steps, warmup):
-    """u d -> u d H H H (the quartic scalar vertex, 50 diagrams) at sqrt_s_hat =
-    2 TeV: integrate steps of 2^20 events through its flat massive-leg tree,
-    FP64 and mixed"""
-    pir = processes.ud_udhhh()
-    out = {"workload": "u d -> u d H H H by W W and Z Z fusion, sqrt_s_hat = 2 TeV, 2^20 events per step, "
-                       "16 helicity combinations, 2 colour flows", "flop_per_event": flops.per_event(pir)}
+def config_leg(torch, H, pir, workload, flops, steps, warmup):
+    """integrate steps of 2^20 events of one more configuration through its
+    own phase-space tree, FP64 and mixed"""
+    out = {"workload": workload, "flop_per_event": flops.per_event(pir)}
     for prec in ("fp64", "mixed"):
         proc = H.Process(pir, precision=prec)
         wall, kern, r = time_path(torch, proc, steps, warmup, sqrt_s=pir.sqrt_s)
@@ -236,7 +233,7 @@ def main():
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
     ap.add_argument("--profile-proc", default="gg_ttbar_6f",
                     help="process of --profile-leg: gg_ttbar_6f (default), gg_4g, gg_4g_ddm, ud_udhh_4b, ud_udhhh, "
-                         "ee_mumu, "
+                         "ww_ww, ee_mumu, "
                          "'generate' for the phase-space kernel of gg_ttbar_6f alone, or 'adaptive' for the "
                          "adaptive integration of its resonance-tree form (FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -340,7 +337,13 @@ def main():
     line["phase_space"] = phase_space_leg(torch, fp64, args.steps, args.warmup)
     line["resonance_phase_space"] = resonance_leg(torch, H, processes, args.steps, args.warmup, r64)
     line["adaptive_integration"] = adaptive_leg(torch, H, processes)
-    line["triple_higgs"] = hhh_leg(torch, H, processes, flops, args.steps, args.warmup)
+    line["triple_higgs"] = config_leg(
+        torch, H, processes.ud_udhhh(), "u d -> u d H H H by W W and Z Z fusion (quartic scalar vertex), "
+        "sqrt_s_hat = 2 TeV, 2^20 events per step, 16 helicity combinations, 2 colour flows",
+        flops, args.steps, args.warmup)
+    line["w_scattering"] = config_leg(
+        torch, H, processes.ww_ww(), "W- W+ -> W- W+ (massive external W, weak quartic vertex), "
+        "sqrt_s_hat = 1 TeV, 2^20 events per step, 81 helicity combinations", flops, args.steps, args.warmup)
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:

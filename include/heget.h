@@ -234,8 +234,11 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
 
 /* Monte Carlo cross section from n events generated from `seed` (counters
  * 0 .. n-1) by the process's phase space (RAMBO or its resonance tree):
- * sigma = (1/N) sum_i w_i with w_i = dPhi_n,i * pass_i * F_i / (2 s 4 n_a n_b S),
- * reduced on the device in a fixed order.  Synchronises
+ * sigma = (1/N) sum_i w_i with w_i = dPhi_n,i * pass_i * F_i / (2 lambda^(1/2) N_pol n_a n_b S),
+ * lambda^(1/2) = lambda^(1/2)(s, m_a^2, m_b^2) the flux of the incoming legs (s when
+ * both are massless) and N_pol their polarisation states (2 per fermion or
+ * massless vector, 3 per massive vector, 1 per scalar), reduced on the device
+ * in a fixed order.  Synchronises
  * `stream`; fills *out.  The handle keeps a small buffer of per-block partial
  * sums (24 bytes per 256 events), allocated on the first call and grown when a
  * larger n arrives, and 24 bytes of pinned host memory for the reduced sums;

@@ -49,7 +49,8 @@ enum {
   OR_ZZ_HH = 17,        /* Z Z -> H H with on-shell external Z */
   OR_UD_UDHHH = 4,      /* u d -> u d H H H by W W and Z Z fusion; legs u d u d H H H */
   OR_WW_HHH = 18,       /* W- W+ -> H H H with on-shell external W (unitarity check) */
-  OR_ZZ_HHH = 19        /* Z Z -> H H H with on-shell external Z */
+  OR_ZZ_HHH = 19,       /* Z Z -> H H H with on-shell external Z */
+  OR_WW_WW = 20         /* W- W+ -> W- W+ with on-shell external W; legs W- W+ W- W+ */
 };
 
 int or_nlegs(int proc);

@@ -95,14 +95,22 @@ def _min_mass(nodes, leg_mass, d):
 
 def generate_from(u, sqrt_s, nodes, n_legs, leg_mass=None):
     """the same from given uniforms u[n][n_uniforms(nodes)]; leg_mass[k] the
-    mass of final leg k (default all zero)"""
+    mass of leg k (default all zero; legs 0 and 1 the beams)"""
     K = len(nodes)
     n = u.shape[0]
     leg_mass = [0.0] * n_legs if leg_mass is None else [float(x) for x in leg_mass]
     mom = np.zeros((n, n_legs, 4))
-    h = 0.5 * sqrt_s
-    mom[:, 0] = [h, 0.0, 0.0, h]
-    mom[:, 1] = [h, 0.0, 0.0, -h]
+    ma, mb = leg_mass[0], leg_mass[1]
+    if ma == 0.0 and mb == 0.0:
+        h = 0.5 * sqrt_s
+        mom[:, 0] = [h, 0.0, 0.0, h]
+        mom[:, 1] = [h, 0.0, 0.0, -h]
+    else:
+        # beams of masses m_a, m_b along +-z in the collision frame
+        s0 = sqrt_s * sqrt_s
+        pz = math.sqrt(max((s0 - (ma + mb) * (ma + mb)) * (s0 - (ma - mb) * (ma - mb)), 0.0)) / (2.0 * sqrt_s)
+        mom[:, 0] = [(s0 + ma * ma - mb * mb) / (2.0 * sqrt_s), 0.0, 0.0, pz]
+        mom[:, 1] = [(s0 + mb * mb - ma * ma) / (2.0 * sqrt_s), 0.0, 0.0, -pz]
     weight = np.ones(n)
     mass = {0: np.full(n, float(sqrt_s))}            # node -> invariant mass sqrt(s)
     lab = {0: np.tile([sqrt_s, 0.0, 0.0, 0.0], (n, 1))}

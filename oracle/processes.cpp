@@ -311,6 +311,56 @@ void col_qq_qqhh(const int* c, cd* out) {
       for (int j = 0; j < 4; ++j) out[d++] = cls[k] * prs[r];
 }
 
+// W-(p0) W+(p1) -> W-(p2) W+(p3) with on-shell external W's: the quartic
+// contact, photon and Z exchange in the s and t channels through the W W V
+// vertex, and Higgs exchange in the s and t channels (7 diagrams).  Feynman
+// rules with every momentum incoming (an outgoing W- is an incoming W+ of
+// momentum -p and polarisation eps*, and the reverse):
+//   W+_mu(k1) W-_nu(k2) V_la(k3):  i g_V [g_mu nu (k1 - k2)_la + g_nu la (k2 - k3)_mu
+//                                          + g_la mu (k3 - k1)_nu],  g_gamma = e, g_Z = g_W c_W;
+//   W+_mu W+_nu W-_la W-_rho:      i g_W^2 [2 g_mu nu g_la rho - g_mu la g_nu rho - g_mu rho g_nu la];
+//   W+_mu W-_nu H:                 i g_WWH g_mu nu.
+// (eps_P, k_P) W+ and (eps_M, k_M) W- meet a vector boson of incoming momentum
+// kV = -(k_P + k_M): the vertex contracted with both polarisations.
+CVec4 wwv_current(const CVec4& eP, const Vec4& kP, const CVec4& eM, const Vec4& kM) {
+  const Vec4 kV = neg(add(kP, kM));
+  const cd pm = dot(eP, eM);
+  const cd a = dot(eP, sub(kM, kV)), b = dot(eM, sub(kV, kP));
+  const Vec4 d = sub(kP, kM);
+  CVec4 r;
+  for (int m = 0; m < 4; ++m) r[m] = pm * d[m] + a * eM[m] + b * eP[m];
+  return r;
+}
+void amp_ww_ww(const SM& sm, const Vec4* p, const int* h, cd* M) {
+  struct Ext {
+    CVec4 e;
+    Vec4 k;
+  };
+  const Ext A = {eps_in(sm, 1, p[1], sm.mw, h[1]), p[1]};            // W+ in
+  const Ext B = {eps_out(sm, 2, p[2], sm.mw, h[2]), neg(p[2])};      // W- out = W+ in
+  const Ext C = {eps_in(sm, 0, p[0], sm.mw, h[0]), p[0]};            // W- in
+  const Ext D = {eps_out(sm, 3, p[3], sm.mw, h[3]), neg(p[3])};      // W+ out = W- in
+  const cd gw2 = sm.gw * sm.gw, ga = sm.e, gzv = sm.gw * sm.cw, gh = sm.g_wwh;
+  int d = 0;
+  // contact
+  M[d++] = (I1 * gw2 * (2.0 * dot(A.e, B.e) * dot(C.e, D.e) - dot(A.e, C.e) * dot(B.e, D.e) -
+                        dot(A.e, D.e) * dot(B.e, C.e))) / I1;
+  // s channel: (A, C) | (B, D); t channel: (A, D) | (B, C)
+  const Ext* ch[2][4] = {{&A, &C, &B, &D}, {&A, &D, &B, &C}};
+  for (const auto& c : ch) {
+    const Ext &P1 = *c[0], &M1 = *c[1], &P2 = *c[2], &M2 = *c[3];
+    const Vec4 q = add(P1.k, M1.k);
+    const CVec4 G1 = wwv_current(P1.e, P1.k, M1.e, M1.k);
+    const CVec4 G2 = wwv_current(P2.e, P2.k, M2.e, M2.k);
+    M[d++] = ((I1 * ga) * (I1 * ga) * dot(G1, contract(massless_prop(q), G2))) / I1;
+    M[d++] = ((I1 * gzv) * (I1 * gzv) * dot(G1, contract(vector_prop(q, sm.numz2, sm.muz2), G2))) / I1;
+    M[d++] = ((I1 * gh) * (I1 * gh) * dot(P1.e, M1.e) * scalar_prop(q, sm.mh, sm.wh) * dot(P2.e, M2.e)) / I1;
+  }
+}
+void col_trivial7(const int*, cd* c) {
+  for (int j = 0; j < 7; ++j) c[j] = 1.0;
+}
+
 // u(p0) d(p1) -> u(p2) d(p3) H(p4) H(p5) H(p6) by Z Z and W W fusion: 2 x 25
 // diagrams, the W W class with the Fermi sign of its quark pairing.
 void amp_ud_udhhh(const SM& sm, const Vec4* p, const int* h, cd* M) {
@@ -385,6 +435,7 @@ const ProcDef* find_proc(int id) {
     table[OR_UD_UDHHH] = {7, {F, F, F, F, S, S, S}, 50, {3, 3, 3, 3, 1, 1, 1}, amp_ud_udhhh, col_qq_qqhhh};
     table[OR_WW_HHH] = {5, {VM, VM, S, S, S}, 25, {1, 1, 1, 1, 1}, amp_ww_hhh, col_trivial25};
     table[OR_ZZ_HHH] = {5, {VM, VM, S, S, S}, 25, {1, 1, 1, 1, 1}, amp_zz_hhh, col_trivial25};
+    table[OR_WW_WW] = {4, {VM, VM, VM, VM}, 7, {1, 1, 1, 1}, amp_ww_ww, col_trivial7};
   });
   auto it = table.find(id);
   return it == table.end() ? nullptr : &it->second;

@@ -283,9 +283,19 @@ class Gen:
         w(f"__device__ __forceinline__ double ps_tree_{p.name}(const KernelArgs& a, uint64_t event, int64_t i, mom* p) {{")
         w(f"  double u[{nu}];")
         w(f"  ps_uniforms<{nu}>(a.seed, event, u);")
-        w("  const double h = 0.5 * a.sqrt_s;")
-        w("  p[0] = {h, 0.0, 0.0, h};")
-        w("  p[1] = {h, 0.0, 0.0, -h};")
+        beams = [p.legs[k].particle for k in (0, 1)]
+        if all(b == P_ZERO for b in beams):
+            w("  const double h = 0.5 * a.sqrt_s;")
+            w("  p[0] = {h, 0.0, 0.0, h};")
+            w("  p[1] = {h, 0.0, 0.0, -h};")
+        else:
+            # massive beams along +-z in the collision frame
+            ma, mb = (f"a.prop[{b}].m" if b != P_ZERO else "0.0" for b in beams)
+            w(f"  const double ma = {ma}, mb = {mb}, s0 = a.sqrt_s * a.sqrt_s;")
+            w("  const double pz = sqrt(fmax((s0 - (ma + mb) * (ma + mb)) * (s0 - (ma - mb) * (ma - mb)), 0.0)) / "
+              "(2.0 * a.sqrt_s);")
+            w("  p[0] = {(s0 + ma * ma - mb * mb) / (2.0 * a.sqrt_s), 0.0, 0.0, pz};")
+            w("  p[1] = {(s0 + mb * mb - ma * ma) / (2.0 * a.sqrt_s), 0.0, 0.0, -pz};")
         w("  // adaptive integration: the uniforms through the grid, its Jacobian in the weight")
         w(f"  double w = a.grid ? grid_map<{nu}>(a, i, u) : 1.0;")
         w("  const double M0 = a.sqrt_s;")

@@ -148,8 +148,8 @@ heget_status validate(const heget_process_ir* ir) {
     const heget_leg& l = ir->legs[k];
     if (l.kind < 0 || l.kind > 2 || l.particle < 0 || l.particle >= HEGET_N_PARTICLES)
       return fail(HEGET_E_IR, "leg " + std::to_string(k) + ": bad kind or particle");
-    if (k >= 2 && l.particle != HEGET_P_ZERO && ir->n_ps_nodes == 0)
-      return fail(HEGET_E_UNSUPPORTED, "RAMBO phase space needs massless final-state legs (give a resonance tree)");
+    if (l.particle != HEGET_P_ZERO && ir->n_ps_nodes == 0)
+      return fail(HEGET_E_UNSUPPORTED, "RAMBO phase space needs massless legs (give a resonance tree)");
   }
   if (ir->n_couplings < 1 || !ir->couplings) return fail(HEGET_E_IR, "no couplings");
   for (int k = 0; k < ir->n_couplings; ++k)
@@ -349,7 +349,11 @@ double heget::detail::weight_factor(heget_process_t p, double sqrt_s) {
   const double s = sqrt_s * sqrt_s;
   // a resonance tree's weight is per event (multiplied in the kernel)
   const double volume = p->entry->generate ? 1.0 : phase_space_volume(sqrt_s, p->n_legs - 2);
-  return volume / (2.0 * s) / 4.0 / p->n_a_n_b / p->symmetry;
+  const double ma = p->beam_m[0], mb = p->beam_m[1];
+  const double flux = (ma == 0.0 && mb == 0.0)
+                          ? s
+                          : std::sqrt(std::max((s - (ma + mb) * (ma + mb)) * (s - (ma - mb) * (ma - mb)), 0.0));
+  return volume / (2.0 * flux) / double(p->spin_states) / p->n_a_n_b / p->symmetry;
 }
 
 void heget::detail::fill_result(const double h[3], int64_t n, heget_result* out) {
@@ -580,6 +584,13 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   for (int k = 0; k < ir->n_couplings; ++k) coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
   PropEntry prop[HEGET_N_PARTICLES];
   prop_table(ir->sm, prop);
+  p->spin_states = 1;
+  for (int k = 0; k < 2; ++k) {
+    const heget_leg& l = ir->legs[k];
+    const bool massive = l.particle != HEGET_P_ZERO;
+    p->beam_m[k] = massive ? prop[l.particle].m : 0.0;
+    p->spin_states *= l.kind == 2 ? 1 : (l.kind == 1 && massive ? 3 : 2);   // S; massive V; F or massless V
+  }
   if (hipMalloc(&p->d_cpl, cpl.size() * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->d_prop, sizeof(prop)) != hipSuccess || hipMalloc(&p->d_hel, p->hel.size()) != hipSuccess) {
     release(p);

@@ -18,6 +18,8 @@ struct heget_process {
   int cut_enabled = 0;
   double cut_pt = 0, cut_dr = 0;
   int n_a_n_b = 1, symmetry = 1;
+  int spin_states = 4;       // polarisation states of the two incoming legs (spin average)
+  double beam_m[2] = {0, 0}; // masses of the incoming legs (flux)
   double* d_cpl = nullptr;
   heget::PropEntry* d_prop = nullptr;
   int8_t* d_hel = nullptr;
@@ -60,7 +62,8 @@ size_t complex_bytes(heget_process_t p);
 // Massless n-body phase-space volume at sqrt_s (every RAMBO weight).
 double phase_space_volume(double sqrt_s, int n);
 
-// Per-event weight factor of heget_integrate: Phi_n / (2 s) x 1/4 x 1/(n_a n_b) x 1/S.
+// Per-event weight factor of heget_integrate: Phi_n / (2 lambda^(1/2)(s, m_a^2, m_b^2))
+// x 1/(spin states of the incoming legs) x 1/(n_a n_b) x 1/S (massless beams: 2 s, 4 states).
 double weight_factor(heget_process_t p, double sqrt_s);
 
 // Launches the process's amplitude kernel over a.n events (256 per block; a

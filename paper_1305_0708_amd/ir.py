@@ -235,8 +235,8 @@ class Process:
                     raise ValueError("ordering template: every jamp row is the same combination")
         if self.ps_tree is not None:
             validate_ps_tree(self.ps_tree, self.legs, self.ps_window)
-        elif any(leg.particle != P_ZERO for leg in self.legs[2:]):
-            raise ValueError("RAMBO phase space needs massless final legs (give a resonance tree)")
+        elif any(leg.particle != P_ZERO for leg in self.legs):
+            raise ValueError("RAMBO phase space needs massless legs (give a resonance tree)")
         return self
 
     # -------------------------------------------------------------- fingerprint

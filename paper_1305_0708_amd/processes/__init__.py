@@ -207,9 +207,40 @@ def ud_udhhh(sqrt_s=2000.0):
                    sm_overrides={"complex_mass": 1}, ps_tree=tree).validate()
 
 
+def ww_ww(sqrt_s=1000.0):
+    """W- W+ -> W- W+ with on-shell external W bosons (massive external vector
+    wavefunctions and the weak quartic vertex, Sec. 4.2.3-4.2.5): the W W W W
+    contact, photon and Z exchange in the s and t channels through W W V, and
+    Higgs exchange in both channels, 7 diagrams.  Arguments in the HELAS order:
+    the first W of a vertex flows in as a W- (an incoming W- or an outgoing
+    W+), the second as a W+.  Phase space: the two-body decay of the collision
+    with the W mass on every leg."""
+    legs = [Leg(V, True, particle=P_W, name="W-"), Leg(V, True, particle=P_W, name="W+"),
+            Leg(V, False, particle=P_W, name="W-"), Leg(V, False, particle=P_W, name="W+")]
+    cpl = [Coupling("wwa"), Coupling("wwz"), Coupling("wwww"), Coupling("wwh")]
+    WWA, WWZ, WWWW, WWH = range(4)
+    calls = [Call("wwww", (0, 1, 3, 2), 0, WWWW)]
+    slot, amp = 4, 1
+    # s channel: W-(0) W+(1) -> V* -> W-(2) W+(3); t channel: W-(0) -> W-(2) V*, V* W+(1) -> W+(3)
+    for (a, b), (c, d) in (((0, 1), (3, 2)), ((0, 2), (3, 1))):
+        for cp, prop in ((WWA, P_ZERO), (WWZ, P_Z)):
+            calls.append(Call("jvv", (a, b), slot, cp, prop))
+            calls.append(Call("vvv", (c, d, slot), amp, cp))
+            slot += 1
+            amp += 1
+        calls.append(Call("hvv", (a, b), slot, WWH, P_H))
+        calls.append(Call("vvs", (c, d, slot), amp, WWH))
+        slot += 1
+        amp += 1
+    tree = [(P_ZERO, ir.PS_FLAT, 2, 3)]
+    return Process("ww_ww", legs, cpl, calls, n_amps=amp, n_flows=1, jamp=[[(k, 1.0) for k in range(amp)]],
+                   colour=[[Fraction(1)]], helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=1,
+                   symmetry=1, sm_overrides={"complex_mass": 1}, ps_tree=tree).validate()
+
+
 def by_name(name):
     if name in ("gg_4g", "gg_4g_ddm"):
         from .gluons import gg_ng
         return gg_ng(6, basis="trace" if name == "gg_4g" else "ddm")
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
-            "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh}[name]()
+            "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww}[name]()

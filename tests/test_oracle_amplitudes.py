@@ -466,3 +466,62 @@ def test_hhh_helicity_selection(oracle):
     mom = hhh_events(23, 1, 2000.0)[0]
     ph = oracle.me2_per_helicity(oracle.UD_UDHHH, mom, oracle.params(cms=1))
     assert np.sum(ph > 1e-20 * ph.sum()) == 4
+
+
+# ------------------------------------------------------------------ W W -> W W (EW VVVV, massive externals)
+def ww_event(rs, mw, c, phi=0.4):
+    E = rs / 2
+    p = math.sqrt(E * E - mw * mw)
+    s = math.sqrt(1 - c * c)
+    return np.array([[E, 0, 0, p], [E, 0, 0, -p], [E, p * s * math.cos(phi), p * s * math.sin(phi), p * c],
+                     [E, -p * s * math.cos(phi), -p * s * math.sin(phi), -p * c]])
+
+
+def longitudinal(oracle, mom, prm):
+    H = oracle.helicities(oracle.WW_WW)
+    k = [i for i, h in enumerate(H) if all(x == 0 for x in h)][0]
+    return math.sqrt(oracle.me2_per_helicity(oracle.WW_WW, mom, prm)[k])
+
+
+def test_longitudinal_ww_ww_unitarity(oracle):
+    """W_L W_L -> W_L W_L: single diagrams grow like E^4 / m_W^4; the quartic
+    contact with photon and Z exchange cancels that to E^2, Higgs exchange the
+    rest, and |M| stays flat (ratio 0.98 from 2 to 20 TeV).  Leaving out the
+    Higgs, the Z or one term of the W W V vertex, or flipping the quartic sign,
+    gives ratios of 99 to 1e6 (checked by planting each in a copy of the oracle)"""
+    mw = 91.1876 * math.sqrt(1 - 0.2222)
+    prm = oracle.params(cms=1, wz=0.0, wh=0.0)
+    a = [longitudinal(oracle, ww_event(rs, mw, 0.3), prm) for rs in (2000.0, 20000.0)]
+    assert 0.5 < a[1] / a[0] < 2.0
+
+
+def test_ww_ww_goldstone_limit(oracle):
+    """equivalence theorem in the gaugeless limit (g -> 0 at fixed v, so m_W ->
+    0): the longitudinal amplitude becomes the Goldstone-boson one,
+    -(m_H^2 / v^2) [s / (s - m_H^2) + t / (t - m_H^2)], up to O(g^2) and
+    O(m_W^2 / s) (1e-4 to 1.5e-3 at these points)"""
+    sw2, mh, v, alpha = 0.2222, 125.0, 246.22, 1e-6
+    e = math.sqrt(4 * math.pi * alpha)
+    gw = e / math.sqrt(sw2)
+    mw = gw * v / 2
+    prm = oracle.params(cms=1, wz=0.0, wh=0.0, alpha=alpha, mz=mw / math.sqrt(1 - sw2), sw2=sw2)
+
+    def mdot(a, b):
+        return a[0] * b[0] - a[1:] @ b[1:]
+    for rs, c in ((300.0, 0.3), (1000.0, -0.5), (3000.0, 0.7)):
+        m = ww_event(rs, mw, c)
+        s, t = mdot(m[0] + m[1], m[0] + m[1]), mdot(m[0] - m[2], m[0] - m[2])
+        gold = (mh * mh / (v * v)) * (s / (s - mh * mh) + t / (t - mh * mh))
+        assert abs(longitudinal(oracle, m, prm) / abs(gold) - 1) < 5e-3
+
+
+def test_ww_ww_lorentz_invariance(oracle):
+    """the longitudinal diagrams cancel from E^4 / m_W^4 ~ 1.5e3 at 1 TeV, which
+    the FP64 rounding of a changed frame carries: 1e-9 (measured 1.7e-10)"""
+    prm = oracle.params(cms=1)
+    mw = 91.1876 * math.sqrt(1 - 0.2222)
+    mom = np.array([ww_event(1000.0, mw, c, phi) for c, phi in ((0.3, 0.4), (-0.7, 2.0), (0.95, 5.0))])
+    f = oracle.me2(oracle.WW_WW, mom, prm)
+    for b in ([0.3, 0.2, -0.5], [0.0, 0.0, 0.9]):
+        g = oracle.me2(oracle.WW_WW, boost(mom, b), prm)
+        assert np.max(np.abs(g / f - 1)) < 1e-9
