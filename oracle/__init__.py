@@ -34,7 +34,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 EE_MUMU, GG_TT_6F, GG_4G, UD_UDHH_4B = 0, 1, 2, 3
 GG_GG, GG_GGG, UU_TT, GG_TT, UU_UUHH_4B, WW_HH, ZZ_HH = 10, 11, 12, 13, 14, 16, 17
-UD_UDHHH, WW_HHH, ZZ_HHH, WW_WW = 4, 18, 19, 20
+UD_UDHHH, WW_HHH, ZZ_HHH, WW_WW, GG_5G = 4, 18, 19, 20, 21
 
 
 class Params(ctypes.Structure):
@@ -86,6 +86,7 @@ def lib():
         L.or_me2_hel.argtypes = [ctypes.c_int, P(Params), dp, ip, dp]
         L.or_gluon_partial.argtypes = [ctypes.c_int, P(Params), dp, ip, ip, dp]
         L.or_gluon_colour_matrix.argtypes = [ctypes.c_int, dp]
+        L.or_gluon_colour_matrix_fierz.argtypes = [ctypes.c_int, dp]
         L.or_trace_me2.argtypes = [ctypes.c_int, P(Params), dp, dp]
         L.or_nlegs.argtypes = [ctypes.c_int]
         L.or_selfcheck_spinors.argtypes = [dp, ctypes.c_double]
@@ -235,6 +236,14 @@ def gluon_colour_matrix(n):
     k = math.factorial(n - 1)
     C = np.zeros((k, k))
     lib().or_gluon_colour_matrix(n, _dp(C))
+    return C
+
+
+def gluon_colour_matrix_fierz(n):
+    k = math.factorial(n - 1)
+    C = np.zeros((k, k))
+    if lib().or_gluon_colour_matrix_fierz(n, _dp(C)) != 0:
+        raise ValueError(n)
     return C
 
 

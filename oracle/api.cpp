@@ -17,6 +17,7 @@ int gluon_count(int proc) {
     case OR_GG_GG: return 4;
     case OR_GG_GGG: return 5;
     case OR_GG_4G: return 6;
+    case OR_GG_5G: return 7;
     default: return 0;
   }
 }
@@ -151,6 +152,13 @@ extern "C" int or_gluon_colour_matrix(int n, double* C) {
   const std::vector<double>& M = gluon_colour_matrix(n);
   std::memcpy(C, M.data(), M.size() * sizeof(double));
   return int(M.size());
+}
+
+extern "C" int or_gluon_colour_matrix_fierz(int n, double* C) {
+  if (n < 3 || n > 8) return -1;
+  const std::vector<double> M = fierz_colour_matrix(n);
+  std::copy(M.begin(), M.end(), C);
+  return 0;
 }
 
 extern "C" int or_trace_me2(int proc, const or_params* prm, const double* mom, double* out) {

@@ -121,12 +121,62 @@ cd gluon_partial(int n, const SM& sm, const Vec4* p, const int* hel, const int* 
   return bg.partial(order, n);
 }
 
+// The same matrix by Fierz expansion, for more gluons than the brute-force sum
+// reaches: conj Tr(T^{a_s0} ... ) = Tr(... T^{a_s0}) (hermitian generators),
+// and each gluon's pair of generators, one in each trace, is replaced by
+//   T^a_{ij} T^a_{kl} = (1/2) [delta_il delta_jk - (1/N) delta_ij delta_kl].
+// Each of the 2^n choices of terms joins the 2n fundamental indices into
+// closed loops, worth N per loop.
+std::vector<double> fierz_colour_matrix(int n) {
+  const auto ords = orderings(n);
+  const int no = int(ords.size());
+  const double N = 3.0;
+  std::vector<double> C(size_t(no) * no, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int x = 0; x < no; ++x) {
+    int pos1[8], pos2[8], par[16];
+    for (int p = 0; p < n; ++p) pos1[ords[x][n - 1 - p]] = p;   // reversed: the conjugated trace
+    for (int y = 0; y < no; ++y) {
+      for (int q = 0; q < n; ++q) pos2[ords[y][q]] = q;
+      double sum = 0.0;
+      for (int choice = 0; choice < (1 << n); ++choice) {
+        // nodes 0..n-1: indices I_p of trace 1 (T at p runs I_p -> I_(p+1)); n..2n-1: J_q of trace 2
+        for (int k = 0; k < 2 * n; ++k) par[k] = k;
+        auto find = [&](int a) {
+          while (par[a] != a) a = par[a] = par[par[a]];
+          return a;
+        };
+        auto join = [&](int a, int b) { par[find(a)] = find(b); };
+        int k1 = 0;
+        for (int g = 0; g < n; ++g) {
+          const int p = pos1[g], q = pos2[g];
+          const int ip = p, ip1 = (p + 1) % n, jq = n + q, jq1 = n + (q + 1) % n;
+          if ((choice >> g) & 1) {   // -(1/N) delta(I_p, I_p+1) delta(J_q, J_q+1)
+            join(ip, ip1);
+            join(jq, jq1);
+            ++k1;
+          } else {                   // delta(I_p, J_q+1) delta(I_p+1, J_q)
+            join(ip, jq1);
+            join(ip1, jq);
+          }
+        }
+        int loops = 0;
+        for (int k = 0; k < 2 * n; ++k) loops += find(k) == k;
+        sum += std::pow(N, loops) * std::pow(-1.0 / N, k1);
+      }
+      C[size_t(x) * no + y] = sum / double(1 << n);
+    }
+  }
+  return C;
+}
+
 const std::vector<double>& gluon_colour_matrix(int n) {
   static std::map<int, std::vector<double>> cache;
   static std::mutex mu;
   std::lock_guard<std::mutex> lock(mu);
   auto it = cache.find(n);
   if (it != cache.end()) return it->second;
+  if (n > 6) return cache[n] = fierz_colour_matrix(n);   // 8^n explicit colours: brute force up to 6
   const auto ords = orderings(n);
   const int no = int(ords.size());
   const Colour& CL = colour();

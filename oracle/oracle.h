@@ -50,7 +50,8 @@ enum {
   OR_UD_UDHHH = 4,      /* u d -> u d H H H by W W and Z Z fusion; legs u d u d H H H */
   OR_WW_HHH = 18,       /* W- W+ -> H H H with on-shell external W (unitarity check) */
   OR_ZZ_HHH = 19,       /* Z Z -> H H H with on-shell external Z */
-  OR_WW_WW = 20         /* W- W+ -> W- W+ with on-shell external W; legs W- W+ W- W+ */
+  OR_WW_WW = 20,        /* W- W+ -> W- W+ with on-shell external W; legs W- W+ W- W+ */
+  OR_GG_5G = 21         /* g g -> g g g g g (Berends-Giele; colour matrix by Fierz expansion) */
 };
 
 int or_nlegs(int proc);
@@ -120,6 +121,10 @@ int or_gluon_partial(int n, const or_params* prm, const double* mom, const int* 
  * Tr(T^a1 T^a_sigma2 ...) conj(Tr(T^a1 T^a_tau2 ...)), brute force over SU(3);
  * orderings enumerated as the lexicographic permutations of legs 1..n-1. */
 int or_gluon_colour_matrix(int n, double* C);
+
+/* The same matrix by Fierz expansion and closed-loop counting (n = 3 .. 8);
+ * the matrix the oracle uses from 7 gluons on. */
+int or_gluon_colour_matrix_fierz(int n, double* C);
 
 /* Spin-summed |M|^2 from Dirac traces with completeness relations (no spinors):
  * proc OR_UU_TT or OR_GG_TT, colour summed. */

@@ -31,5 +31,6 @@ void condition_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>
 double gluon_me2(int n, const SM& sm, const Vec4* p);
 cd gluon_partial(int n, const SM& sm, const Vec4* p, const int* hel, const int* order);
 const std::vector<double>& gluon_colour_matrix(int n);
+std::vector<double> fierz_colour_matrix(int n);
 
 }  // namespace orc

@@ -39,6 +39,9 @@ TEMPLATE_KIN_PER_LEVEL = True
 TEMPLATE_STASH_WORDS = 48
 # MFMA colour form: 16-event chunks of a wave per pass (each fragment load serves them all)
 COLOUR_CHUNKS = 2
+# amplitude rows of the MFMA colour form above this many bytes (FP64) are not
+# staged in LDS: the workspace holds them in the colour form's layout
+DIRECT_ROWS_BYTES = 128 * 1024
 # per-lane LDS words (in the arithmetic type) of the helicity nest's stash of
 # event kinematics: 64 words are 128 KiB per 256-lane block in FP64
 STASH_WORDS = 64
@@ -752,8 +755,11 @@ class Gen:
         if any(leg.kind == F for leg in p.legs):
             raise NotImplementedError("ordering templates support vector and scalar legs")
         mf = p.uses_colour_mfma()
+        # the colour form's amplitude rows ([2 o][256] per helicity): staged in LDS,
+        # or, when they would not fit, laid out that way in the workspace itself
+        self._direct_rows = mf and 2 * no * 256 * 8 > DIRECT_ROWS_BYTES
         self._template_stash_plan()
-        rows = 2 * no if mf else 0
+        rows = 2 * no if mf and not self._direct_rows else 0
         if self._tstash_words or rows:
             w("  // per-lane LDS rows (column = lane): the helicity nest's stash of outer")
             w("  // currents while the orderings run (FP64), then the amplitude rows of the colour form")
@@ -761,7 +767,11 @@ class Gen:
             w(f"  __shared__ T lds_rows[kStash ? {max(rows, self._tstash_words)} : {max(rows, 1)}][256];")
         for k, L in sorted(self._fixed_vector_positions().items()):
             w(f"  const VPol<T> VP{k} = vpol_pre<T>(p[{L}]);   // position {k} is leg {L} in every ordering")
-        w("  // this block's workspace slot: A[o][h][256] of its events")
+        if self._direct_rows:
+            w("  // this block's workspace slot: per helicity h, the real and imaginary rows")
+            w(f"  // [2 o][256] of the orderings' amplitudes (h * {2 * no * 256} + (2 o) * 256 + lane)")
+        else:
+            w("  // this block's workspace slot: A[o][h][256] of its events")
         w("  cx<T>* const work = static_cast<cx<T>*>(a.work) + size_t(blockIdx.x) * size_t(a.work_stride);")
         w("  const int nh = a.n_hel;")
         w("  if (pass) {")
@@ -793,13 +803,32 @@ class Gen:
             self._call(w, c, ind + "    ")
         self._scope = None
         expr = " + ".join(_coef_expr(cc, f"amp{ai}") for ai, cc in p.jamp[0])
-        w(f"{ind}    work[(size_t(o) * nh + h) * 256 + threadIdx.x] = {expr};")
+        w(f"{ind}    {self._work_store('h', expr)}")
         w(f"{ind}  }}")
         w(f"{ind}}}")
         w("    }")
+        if self._direct_rows:
+            w("  } else {")
+            w("    // the colour form reads every lane of the wave: a failed lane's rows are zero")
+            w("    T* const wr = reinterpret_cast<T*>(work) + threadIdx.x;")
+            w("    for (int h = 0; h < nh; ++h)")
+            w(f"      for (int r = 0; r < {2 * no}; ++r) wr[(size_t(h) * {2 * no} + r) * 256] = T(0);")
         w("  }")
         w("  double me2 = 0.0;")
-        if mf:
+        if mf and self._direct_rows:
+            nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
+            w("  // the MFMA colour form needs every lane of the wavefront; it reads the wave's")
+            w("  // columns of the workspace rows, written above by the wave's own lanes")
+            w("  if (__any(pass)) {")
+            w("    __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"workgroup\");")
+            w("    __builtin_amdgcn_wave_barrier();")
+            w("    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\");")
+            w("    const T* const rows = reinterpret_cast<const T*>(work);")
+            w("    for (int h = 0; h < nh; ++h)")
+            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
+              f"(rows + size_t(h) * {2 * no * 256}, a.cstep, a));")
+            w("  }")
+        elif mf:
             nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
             w("  // the MFMA colour form needs every lane of the wavefront: failed lanes take part with zeros")
             w("  if (__any(pass)) {")
@@ -825,6 +854,14 @@ class Gen:
             self._colour(w, lambda f: f"A{f}")
             w("    }")
             w("  }")
+
+    def _work_store(self, h, value):
+        """store of ordering o's amplitude at helicity h in the workspace slot"""
+        if not self._direct_rows:
+            return f"work[(size_t(o) * nh + {h}) * 256 + threadIdx.x] = {value};"
+        no = len(self.p.orderings)
+        return (f"{{ const cx<T> v_ = {value}; T* const r_ = reinterpret_cast<T*>(work) + "
+                f"(size_t({h}) * {2 * no} + 2 * o) * 256 + threadIdx.x; r_[0] = v_.r; r_[256] = v_.i; }}")
 
     def _bind_positions(self, w, ind):
         """bind every position to the ordering's leg (uniform over the wave):
@@ -1065,7 +1102,7 @@ class Gen:
             else:
                 w(f"{ind}wf<T> Rt = {{}};")
         elif it.kind == "adot":
-            w(f"{ind}work[(size_t(o) * nh + {row}) * 256 + threadIdx.x] = dot(w0, Rt);")
+            w(f"{ind}{self._work_store(row, 'dot(w0, Rt)')}")
         else:
             raise ValueError(it.kind)
 

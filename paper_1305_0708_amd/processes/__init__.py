@@ -12,6 +12,8 @@ Leg order (the momentum layout of heget_eval):
   ud_udhh_4b   u d u d b bbar b bbar              (H -> b bbar twice)
   gg_4g        g g g g g g   (120 trace-basis flows; gg_4g_ddm: the 24 evaluated orderings as flows)
 """
+import copy
+import functools
 from fractions import Fraction
 
 from .. import ir
@@ -238,9 +240,16 @@ def ww_ww(sqrt_s=1000.0):
                    symmetry=1, sm_overrides={"complex_mass": 1}, ps_tree=tree).validate()
 
 
+@functools.lru_cache(maxsize=None)
+def _gluons(n, basis):
+    from .gluons import gg_ng
+    return gg_ng(n, basis=basis)
+
+
 def by_name(name):
-    if name in ("gg_4g", "gg_4g_ddm"):
-        from .gluons import gg_ng
-        return gg_ng(6, basis="trace" if name == "gg_4g" else "ddm")
+    gluon = {"gg_4g": (6, "trace"), "gg_4g_ddm": (6, "ddm"), "gg_5g_ddm": (7, "ddm")}
+    if name in gluon:
+        # the colour matrices of the larger bases take seconds to build: built once, copied out
+        return copy.deepcopy(_gluons(*gluon[name]))
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
             "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww}[name]()

@@ -1,0 +1,92 @@
+"""GPU parity of g g -> g g g g g (seven gluons: 120 colour-ordered amplitudes
+per helicity in the DDM basis, 128 helicity combinations, the colour form on
+MFMA with its amplitude rows read from the workspace) against the oracle's
+Berends-Giele recursion in the trace basis (720 orderings, colour matrix by
+Fierz expansion): two colour bases, one |M|^2.  FP64 only: the FP32 MFMA
+colour form stays off the GPU until the cause of an earlier fault is shown."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NAME = "gg_5g_ddm"
+ROOTS = 1000.0
+SEED = 0x47474735
+CUT = (20.0, 0.4)          # generation cut: failing events have |M|^2 = 0
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def proc(torch):
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    return H.Process(processes.by_name(NAME))
+
+
+def to_soa(torch, mom):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
+
+
+def to_aos(t):
+    return np.ascontiguousarray(np.transpose(t.cpu().numpy(), (2, 0, 1)))
+
+
+def rotated(mom, seed):
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    out = mom.copy()
+    out[..., 1:] = mom[..., 1:] @ q.T
+    return out
+
+
+N_REF = 300        # two blocks of 256 lanes, the second ragged
+
+
+@pytest.fixture(scope="module")
+def reference(oracle):
+    """the oracle's F (cut applied) for the first N_REF events of the stream,
+    shared by every check (about 3 s of CPU per event)"""
+    mom = oracle.generate(SEED, N_REF, 5, ROOTS)
+    return mom, oracle.me2(oracle.GG_5G, mom) * oracle.cut_gluons(mom, *CUT)
+
+
+@pytest.mark.parametrize("n", [N_REF, 45])
+def test_me2_matches_oracle(torch, oracle, proc, reference, n):
+    """the kernel's own events (RAMBO, generation cut; two blocks with a ragged
+    tail, and 45 events in one ragged block): |F_gpu/F_oracle - 1| <= 1e-12, or
+    16 nu where the event's own FP64 floor nu (the rotation spread of the
+    oracle's F) is larger; cut events are exactly 0 on both sides"""
+    me2, mom = proc.eval(n=n, seed=SEED, sqrt_s=ROOTS, want_momenta=True)
+    me2 = me2.cpu().numpy()
+    ref_mom, ref = reference[0][:n], reference[1][:n]
+    assert np.abs(to_aos(mom) - ref_mom).max() < 1e-13 * ROOTS
+    zero = ref == 0
+    assert np.all(me2[zero] == 0.0)
+    got, ref, mom = me2[~zero], ref[~zero], ref_mom[~zero]
+    err = np.abs(got - ref) / np.abs(ref)
+    bad = err > 1e-12
+    nu = np.zeros(bad.sum())
+    for s in range(8):
+        nu = np.maximum(nu, np.abs(oracle.me2(oracle.GG_5G, rotated(mom[bad], s)) / ref[bad] - 1))
+    print(f"gg->5g FP64 n={n}: {zero.sum()} cut, max rel err {err.max():.2e}, median {np.median(err):.2e}, "
+          f"{bad.sum()} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
+    assert np.all(err[bad] <= 16 * nu)
+    assert bad.mean() < 0.05
+
+
+def test_integrate_matches_its_events(torch, oracle, proc, reference):
+    """sigma of heget_integrate over the same events equals the oracle's sum"""
+    r = proc.integrate(N_REF, seed=SEED, sqrt_s=ROOTS)
+    f = reference[1]
+    sig, err, _, _ = oracle.cross_section(f, oracle.phase_space_volume(ROOTS, 5), ROOTS, proc.ir.n_a_n_b,
+                                          proc.ir.symmetry)
+    print(f"gg->5g sigma: GPU {r['sigma_gev2']:.15e} oracle {sig:.15e} rel {r['sigma_gev2'] / sig - 1:.2e}")
+    assert r["n_accepted"] == int(np.sum(f != 0))
+    assert abs(r["sigma_gev2"] / sig - 1) <= 1e-12

@@ -151,17 +151,17 @@ def _pt_case(oracle, n, seed, n_orders):
     return worst_pt, worst_zero, scale
 
 
-@pytest.mark.parametrize("n", [4, 5, 6])
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
 def test_gluon_parke_taylor_and_zeros(oracle, n):
     worst_pt, worst_zero, scale = _pt_case(oracle, n, 21 + n, 12)
     assert worst_pt < 1e-11
     assert worst_zero < 1e-12 * scale
 
 
-@pytest.mark.parametrize("proc,n", [("GG_GG", 4), ("GG_GGG", 5), ("GG_4G", 6)])
+@pytest.mark.parametrize("proc,n", [("GG_GG", 4), ("GG_GGG", 5), ("GG_4G", 6), ("GG_5G", 7)])
 def test_gluon_ward_identity(oracle, proc, n):
     pid = getattr(oracle, proc)
-    mom = oracle.generate(13, 3, n - 2, 1000.0)
+    mom = oracle.generate(13, 3 if n < 7 else 1, n - 2, 1000.0)
     base = oracle.me2(pid, mom)
     for leg in range(n):
         w = oracle.me2(pid, mom, oracle.params(gauge_leg=leg))
@@ -182,6 +182,21 @@ def test_gluon_bose_symmetry(oracle):
     assert np.max(np.abs(oracle.me2(oracle.GG_4G, perm) / base - 1)) < 1e-12
     swap_in = mom[:, [1, 0, 2, 3, 4, 5], :]
     assert np.max(np.abs(oracle.me2(oracle.GG_4G, swap_in) / base - 1)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6])
+def test_fierz_colour_matrix_equals_the_explicit_sum(oracle, n):
+    """the oracle's 7-gluon colour matrix comes from Fierz expansion with loop
+    counting; for up to 6 gluons it equals the brute-force sum over 8^n colours"""
+    A, B = oracle.gluon_colour_matrix(n), oracle.gluon_colour_matrix_fierz(n)
+    assert np.abs(A - B).max() < 1e-12 * np.abs(A).max()
+
+
+def test_seven_gluon_bose_symmetry(oracle):
+    mom = oracle.generate(29, 1, 5, 1000.0)
+    base = oracle.me2(oracle.GG_5G, mom)
+    perm = mom[:, [0, 1, 5, 2, 6, 4, 3], :]
+    assert np.max(np.abs(oracle.me2(oracle.GG_5G, perm) / base - 1)) < 1e-12
 
 
 def fierz_trace_product(traces, N=3):
