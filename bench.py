@@ -153,15 +153,14 @@ def adaptive_leg(torch, H, processes, passes=6, bins=32):
             "sigma_pb": comb["sigma_pb"], "sigma_err_pb": comb["err_pb"], "chi2_per_dof": chi2}
 
 
-def config_leg(torch, H, pir, workload, flops, steps, warmup):
-    """integrate steps of 2^20 events of one more configuration through its
-    own phase-space tree, FP64 and mixed"""
-    out = {"workload": workload, "flop_per_event": flops.per_event(pir)}
-    for prec in ("fp64", "mixed"):
+def config_leg(torch, H, pir, workload, flops, steps, warmup, n=N_EVENTS, precisions=("fp64", "mixed")):
+    """integrate steps of n events of one more configuration, per precision"""
+    out = {"workload": workload, "events_per_step": n, "flop_per_event": flops.per_event(pir)}
+    for prec in precisions:
         proc = H.Process(pir, precision=prec)
-        wall, kern, r = time_path(torch, proc, steps, warmup, sqrt_s=pir.sqrt_s)
-        out[prec] = {"events_per_s": N_EVENTS / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
-                     "model_tflops": flops.per_event(pir) * N_EVENTS / kern / 1e12, "sigma_pb": r["sigma_pb"]}
+        wall, kern, r = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s)
+        out[prec] = {"events_per_s": n / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
+                     "model_tflops": flops.per_event(pir) * n / kern / 1e12, "sigma_pb": r["sigma_pb"]}
     return out
 
 
@@ -233,13 +232,13 @@ def main():
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
     ap.add_argument("--profile-proc", default="gg_ttbar_6f",
                     help="process of --profile-leg: gg_ttbar_6f (default), gg_4g, gg_4g_ddm, ud_udhh_4b, ud_udhhh, "
-                         "ww_ww, ee_mumu, "
+                         "ww_ww, gg_5g_ddm (2^16 events per launch), ee_mumu, "
                          "'generate' for the phase-space kernel of gg_ttbar_6f alone, or 'adaptive' for the "
                          "adaptive integration of its resonance-tree form (FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (scale for HBM byte counters)")
     args = ap.parse_args()
-    if args.profile_leg == "mixed" and args.profile_proc == "gg_4g":
+    if args.profile_leg == "mixed" and args.profile_proc in ("gg_4g", "gg_5g_ddm"):
         print("bench.py: the mixed-precision 120-flow MFMA kernel is switched off on the GPU "
               "(an unexplained fault); profile gg_4g_ddm in mixed precision", file=sys.stderr)
         sys.exit(2)
@@ -264,10 +263,11 @@ def main():
             return
         pir = processes.by_name(args.profile_proc)
         proc = H.Process(pir, precision=args.profile_leg)
-        wall, kern, r = time_path(torch, proc, args.steps, args.warmup, sqrt_s=pir.sqrt_s)
+        n = N_EVENTS if args.profile_proc != "gg_5g_ddm" else 1 << 16
+        wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
-               "kernel_ms": kern * 1e3, "events_per_launch": N_EVENTS, "flop_per_event": flops.per_event(pir),
-               "events_per_s": N_EVENTS / wall, "n_accepted": r["n_accepted"]}
+               "kernel_ms": kern * 1e3, "events_per_launch": n, "flop_per_event": flops.per_event(pir),
+               "events_per_s": n / wall, "n_accepted": r["n_accepted"]}
         if args.copy_calibration:
             src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
             dst = torch.empty_like(src)
@@ -344,6 +344,11 @@ def main():
     line["w_scattering"] = config_leg(
         torch, H, processes.ww_ww(), "W- W+ -> W- W+ (massive external W, weak quartic vertex), "
         "sqrt_s_hat = 1 TeV, 2^20 events per step, 81 helicity combinations", flops, args.steps, args.warmup)
+    # seven gluons: 120 DDM orderings x 128 helicities per event, FP64 (the FP32 MFMA colour form is off)
+    line["seven_gluons"] = config_leg(
+        torch, H, processes.by_name("gg_5g_ddm"), "g g -> g g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV, "
+        "Delta R > 0.4, 2^16 events per step, 128 helicity combinations, 120 DDM colour flows on MFMA",
+        flops, 3, 1, n=1 << 16, precisions=("fp64",))
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:
