@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "126630e4f0c8cb1697f334c4933b544804b825dac70640c9e6f9216de94e9c7f",
+COUNTERS_FP64 = {"source_digest": "4370b50918613e1c178b8b67b68f052b577c7f71b4aa6dce0aed091066e5e1d9",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 
@@ -344,6 +344,10 @@ def main():
     line["w_scattering"] = config_leg(
         torch, H, processes.ww_ww(), "W- W+ -> W- W+ (massive external W, weak quartic vertex), "
         "sqrt_s_hat = 1 TeV, 2^20 events per step, 81 helicity combinations", flops, args.steps, args.warmup)
+    line["hadronic_collision"] = config_leg(
+        torch, H, processes.gg_ttbar_6f_had(), "gg -> t tbar -> 6f at a 14 TeV hadron collider (parton densities "
+        "1), tops in |y| < 2.5 by rapidity, ln(m^2 + pT^2) and azimuth, x_a, x_b from momentum conservation, "
+        "resonance-tree decays, 2^20 events per step", flops, args.steps, args.warmup)
     # seven gluons: 120 DDM orderings x 128 helicities per event, FP64 (the FP32 MFMA colour form is off)
     line["seven_gluons"] = config_leg(
         torch, H, processes.by_name("gg_5g_ddm"), "g g -> g g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV, "

@@ -181,6 +181,18 @@ typedef struct {
   int32_t n_ps_nodes;
   const heget_ps_node* ps_nodes;
   double ps_window;
+  /* Hadronic collision (the paper's Appendix A, parton densities set to 1):
+   * ps_hadron_ymax > 0 makes node 0 of the tree a parton collision at a hadron
+   * collider whose energy is the sqrt_s of eval / integrate.  Node 0's two
+   * daughters get rapidities flat in [-ymax, ymax], the first daughter
+   * ln(m^2 + pT^2) flat from pT = ps_hadron_ptmin (> 0 for a massless daughter)
+   * to the kinematic limit and a flat azimuth, the second the balancing pT;
+   * x_a, x_b = sum (E +- p_z) / sqrt_s, the event's weight 0 unless both are
+   * below 1.  dSigma_2 = (2 pi / S) dy_1 dy_0 dpT^2 / (4 pi)^2 dphi / (2 pi); the
+   * partonic flux 1 / (2 s_hat) joins the per-event weight.  0: the tree's
+   * collision at fixed sqrt_s (rest frame).  Part of the kernel's structure. */
+  double ps_hadron_ymax;
+  double ps_hadron_ptmin;
 } heget_process_ir;
 
 typedef struct heget_process* heget_process_t;

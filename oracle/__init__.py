@@ -265,16 +265,18 @@ HBARC2_PB = 0.3893793721e9  # (hbar c)^2 in pb GeV^2 (PDG)
 
 
 def cross_section(me2_values, phase_space_weight, sqrt_s, n_a_n_b, symmetry, passed=None, beam_mass=(0.0, 0.0),
-                  spin_states=4):
+                  spin_states=4, flux_in_weight=False):
     """sigma = (1/N) sum_i w_i with w_i = Phi_n * pass_i * F_i / (2 F spins n_a n_b S),
     the flux F = lambda^(1/2)(s, m_a^2, m_b^2) (s for massless beams) and spins
     the polarisation states of the two incoming particles (4 for fermions and
-    gluons, 9 for two massive vector bosons), summed exactly (math.fsum).
+    gluons, 9 for two massive vector bosons), summed exactly (math.fsum).  With
+    flux_in_weight the weights already hold 1 / (2 F) (hadronic collisions,
+    s_hat per event).
     Returns (sigma_GeV^-2, err_GeV^-2, sum_w, sum_w2)."""
     s = sqrt_s * sqrt_s
     ma, mb = beam_mass
     flux = s if ma == 0.0 and mb == 0.0 else math.sqrt(max((s - (ma + mb) ** 2) * (s - (ma - mb) ** 2), 0.0))
-    f = 1.0 / (2.0 * flux) / spin_states / n_a_n_b / symmetry
+    f = (1.0 if flux_in_weight else 1.0 / (2.0 * flux)) / spin_states / n_a_n_b / symmetry
     w = phase_space_weight * f * np.asarray(me2_values, dtype=np.float64)
     if passed is not None:
         w = np.where(np.asarray(passed) != 0, w, 0.0)

@@ -35,8 +35,8 @@ import numpy as np
 from . import uniforms_bulk
 
 
-def n_uniforms(nodes):
-    return sum(sum(1 for d in nd[3:5] if d < 0) + 2 for nd in nodes)
+def n_uniforms(nodes, hadronic=None):
+    return sum(sum(1 for d in nd[3:5] if d < 0) + 2 for nd in nodes) + (2 if hadronic else 0)
 
 
 def _sample_s(u, lo, hi, m, g, mapping, window):
@@ -75,14 +75,14 @@ def _boost(P, M, q):
     return out
 
 
-def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0, leg_mass=None):
+def generate(seed, n_events, sqrt_s, nodes, n_legs, counter_offset=0, leg_mass=None, hadronic=None):
     """nodes[k] = (mass, width, mapping, d0, d1, window): node 0 is the collision
     (mass and width ignored), d >= 0 a final leg, d < 0 node -1 - d; mapping
     "bw" or "flat", window None (flat over the kinematic range) or the factor
     of min(window, m / Gamma).  Returns momenta [n][n_legs][4] (legs 0, 1 the
     beams along +-z) and the phase-space weight [n] (0 where a window is empty)."""
-    u = uniforms_bulk(seed, n_events, n_uniforms(nodes), counter_offset)
-    return generate_from(u, sqrt_s, nodes, n_legs, leg_mass)
+    u = uniforms_bulk(seed, n_events, n_uniforms(nodes, hadronic), counter_offset)
+    return generate_from(u, sqrt_s, nodes, n_legs, leg_mass, hadronic)
 
 
 def _min_mass(nodes, leg_mass, d):
@@ -93,9 +93,53 @@ def _min_mass(nodes, leg_mass, d):
     return _min_mass(nodes, leg_mass, node[3]) + _min_mass(nodes, leg_mass, node[4])
 
 
-def generate_from(u, sqrt_s, nodes, n_legs, leg_mass=None):
-    """the same from given uniforms u[n][n_uniforms(nodes)]; leg_mass[k] the
-    mass of leg k (default all zero; legs 0 and 1 the beams)"""
+def _hadronic_pair(u, sqrt_s, m0, m1, y_max, pt_min):
+    """the paper's Appendix A at a hadron collider of energy sqrt_s with parton
+    densities set to 1: rapidities y0, y1 flat in [-y_max, y_max], the first
+    daughter's ln(m0^2 + pT^2) flat up to the kinematic limit, its azimuth
+    flat; the second balances pT; x_a, x_b from momentum conservation.
+
+        d Sigma_2 = dx_a dx_b dPhi_2 = (2 pi / S) dy_1 dy_0 dpT^2 / (4 pi)^2 dphi / (2 pi)
+
+    Returns the daughters' lab momenta, the beams', and the weight
+    dSigma_2 / (2 s_hat) (the partonic flux per event), 0 unless x_a, x_b < 1."""
+    S = sqrt_s * sqrt_s
+    y0 = -y_max + 2.0 * y_max * u[:, 0]
+    y1 = -y_max + 2.0 * y_max * u[:, 3]
+    lam = np.maximum((S - (m0 + m1) ** 2) * (S - (m0 - m1) ** 2), 0.0)
+    pt2max = lam / (4.0 * S)
+    llo = np.log(m0 * m0 + pt_min * pt_min)
+    lhi = np.log(m0 * m0 + pt2max)
+    L = llo + u[:, 1] * (lhi - llo)
+    mt0sq = np.exp(L)
+    pt = np.sqrt(np.maximum(mt0sq - m0 * m0, 0.0))
+    phi = 2.0 * math.pi * u[:, 2]
+    px, py = pt * np.cos(phi), pt * np.sin(phi)
+    mt0 = np.sqrt(mt0sq)
+    mt1 = np.sqrt(m1 * m1 + pt * pt)
+    e0, z0 = mt0 * np.cosh(y0), mt0 * np.sinh(y0)
+    e1, z1 = mt1 * np.cosh(y1), mt1 * np.sinh(y1)
+    xa = (e0 + z0 + e1 + z1) / sqrt_s
+    xb = (e0 - z0 + e1 - z1) / sqrt_s
+    ok = (lhi > llo) & (xa < 1.0) & (xb < 1.0)
+    sh = xa * xb * S
+    w = (2.0 * math.pi / S) * (2.0 * y_max) * (2.0 * y_max) * mt0sq * (lhi - llo) / (16.0 * math.pi * math.pi)
+    w = np.where(ok, w / (2.0 * sh), 0.0)
+    n = u.shape[0]
+    q0 = np.stack([e0, px, py, z0], axis=1)
+    q1 = np.stack([e1, -px, -py, z1], axis=1)
+    h = 0.5 * sqrt_s
+    pa = np.stack([xa * h, np.zeros(n), np.zeros(n), xa * h], axis=1)
+    pb = np.stack([xb * h, np.zeros(n), np.zeros(n), -xb * h], axis=1)
+    return q0, q1, pa, pb, w
+
+
+def generate_from(u, sqrt_s, nodes, n_legs, leg_mass=None, hadronic=None):
+    """the same from given uniforms u[n][n_uniforms(nodes, hadronic)]; leg_mass[k]
+    the mass of leg k (default all zero; legs 0 and 1 the beams).  hadronic =
+    (y_max, pt_min): node 0 is a parton collision at a hadron collider of
+    energy sqrt_s (parton densities 1, the partonic flux in the weight), its
+    two daughters generated in rapidity, ln(m^2 + pT^2) and azimuth."""
     K = len(nodes)
     n = u.shape[0]
     leg_mass = [0.0] * n_legs if leg_mass is None else [float(x) for x in leg_mass]
@@ -134,6 +178,16 @@ def generate_from(u, sqrt_s, nodes, n_legs, leg_mass=None):
             dm[j] = np.sqrt(s)
             mass[-1 - d] = dm[j]
         m0, m1 = dm[0], dm[1]
+        if k == 0 and hadronic is not None:
+            q0, q1, mom[:, 0], mom[:, 1], wh = _hadronic_pair(u[:, iu:iu + 4], sqrt_s, m0, m1, *hadronic)
+            iu += 4
+            weight *= wh
+            for d, q in ((d0, q0), (d1, q1)):
+                if d >= 0:
+                    mom[:, d] = q
+                else:
+                    lab[-1 - d] = q
+            continue
         lam = (M * M - (m0 + m1) ** 2) * (M * M - (m0 - m1) ** 2)
         lam = np.maximum(lam, 0.0)
         pst = np.sqrt(lam) / (2.0 * M)

@@ -64,7 +64,9 @@ class _IRBuffers:
             proc.n_amps, proc.n_flows, self.jamp, self.colour, float(den), len(hels), self.hel,
             proc.n_a_n_b, proc.symmetry, int(proc.cut_enabled), proc.cut_pt, proc.cut_dr,
             len(orders), self.orders if orders else None, self.flow_map if flat_m else None,
-            len(tree), self.ps_nodes if tree else None, float(proc.ps_window))
+            len(tree), self.ps_nodes if tree else None, float(proc.ps_window),
+            float(proc.ps_hadronic[0]) if proc.ps_hadronic else 0.0,
+            float(proc.ps_hadronic[1]) if proc.ps_hadronic else 0.0)
 
 
 class Process:

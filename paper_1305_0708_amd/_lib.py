@@ -58,7 +58,8 @@ class heget_process_ir(ctypes.Structure):
                 ("n_orderings", ctypes.c_int32), ("orderings", ctypes.POINTER(ctypes.c_int8)),
                 ("flow_map", ctypes.POINTER(ctypes.c_int8)),
                 ("n_ps_nodes", ctypes.c_int32), ("ps_nodes", ctypes.POINTER(heget_ps_node)),
-                ("ps_window", ctypes.c_double)]
+                ("ps_window", ctypes.c_double), ("ps_hadron_ymax", ctypes.c_double),
+                ("ps_hadron_ptmin", ctypes.c_double)]
 
 
 class heget_result(ctypes.Structure):

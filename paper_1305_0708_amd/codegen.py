@@ -271,7 +271,7 @@ class Gen:
         tree = self.p.ps_tree
         if tree is None:
             return 0
-        return sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
+        return sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree) + (2 if self.p.ps_hadronic else 0)
 
     def _emit_ps_tree(self, w):
         """the process's resonance phase space as straight-line device code:
@@ -280,10 +280,17 @@ class Gen:
         below each), then its two-body decay"""
         p = self.p
         tree = p.ps_tree
-        nu = sum(1 for node in tree for d in node[2:4] if d < 0) + 2 * len(tree)
-        w(f"// phase space: the collision and its resonances decay in two bodies (tree of {len(tree)} nodes);")
-        w("// fills p[0 .. n_legs-1] and returns the event's weight dPhi_n")
+        nu = self.ps_dims()
+        had = p.ps_hadronic
+        if had:
+            w(f"// phase space: a parton collision at a hadron collider (parton densities 1) and the two-body")
+            w(f"// decays of its resonances (tree of {len(tree)} nodes); fills p[0 .. n_legs-1] and returns the")
+            w("// event's weight dSigma_n / (2 s_hat)")
+        else:
+            w(f"// phase space: the collision and its resonances decay in two bodies (tree of {len(tree)} nodes);")
+            w("// fills p[0 .. n_legs-1] and returns the event's weight dPhi_n")
         w(f"__device__ __forceinline__ double ps_tree_{p.name}(const KernelArgs& a, uint64_t event, int64_t i, mom* p) {{")
+        w("#pragma clang fp contract(off)   // each product and sum rounds on its own (plain IEEE)")
         w(f"  double u[{nu}];")
         w(f"  ps_uniforms<{nu}>(a.seed, event, u);")
         beams = [p.legs[k].particle for k in (0, 1)]
@@ -338,6 +345,11 @@ class Gen:
                 dm[j] = f"M{nd}"
                 iu += 1
             outs = [f"p[{d}]" if d >= 0 else f"P{-1 - d}" for d in (d0, d1)]
+            if k == 0 and had:
+                w(f"  w *= ps_hadronic(u + {iu}, a.sqrt_s, {dm[0]}, {dm[1]}, {_c(had[0])}, {_c(had[1])}, "
+                  f"{outs[0]}, {outs[1]}, p[0], p[1]);")
+                iu += 4
+                continue
             w(f"  w *= ps_decay(u[{iu}], u[{iu + 1}], P{k}, M{k}, {dm[0]}, {dm[1]}, {'true' if k == 0 else 'false'}, "
               f"{outs[0]}, {outs[1]});")
             iu += 2

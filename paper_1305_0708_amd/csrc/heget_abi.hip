@@ -119,6 +119,11 @@ uint64_t fingerprint(const heget_process_ir* ir) {
     }
     H.f64(ir->ps_window);
   }
+  if (ir->ps_hadron_ymax > 0) {
+    H.i32(1);
+    H.f64(ir->ps_hadron_ymax);
+    H.f64(ir->ps_hadron_ptmin);
+  }
   return H.h;
 }
 
@@ -250,6 +255,14 @@ heget_status validate(const heget_process_ir* ir) {
     for (int k = 1; k < ir->n_ps_nodes; ++k)
       if (node_seen[k] != 1) return fail(HEGET_E_IR, "phase-space tree: every node but the first is a daughter once");
   }
+  if (!(ir->ps_hadron_ymax >= 0) || !std::isfinite(ir->ps_hadron_ymax) || !(ir->ps_hadron_ptmin >= 0))
+    return fail(HEGET_E_IR, "hadronic collision: ymax and ptmin must be >= 0");
+  if (ir->ps_hadron_ymax > 0) {
+    if (ir->n_ps_nodes == 0) return fail(HEGET_E_IR, "hadronic collision: needs a phase-space tree");
+    for (int d : ir->ps_nodes[0].daughter)
+      if (d >= 0 && ir->legs[d].particle == HEGET_P_ZERO && !(ir->ps_hadron_ptmin > 0))
+        return fail(HEGET_E_IR, "hadronic collision: a massless daughter of the collision needs ptmin > 0");
+  }
   return HEGET_OK;
 }
 
@@ -349,6 +362,7 @@ double heget::detail::weight_factor(heget_process_t p, double sqrt_s) {
   const double s = sqrt_s * sqrt_s;
   // a resonance tree's weight is per event (multiplied in the kernel)
   const double volume = p->entry->generate ? 1.0 : phase_space_volume(sqrt_s, p->n_legs - 2);
+  if (p->hadronic) return 1.0 / double(p->spin_states) / p->n_a_n_b / p->symmetry;   // flux per event
   const double ma = p->beam_m[0], mb = p->beam_m[1];
   const double flux = (ma == 0.0 && mb == 0.0)
                           ? s
@@ -584,6 +598,7 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   for (int k = 0; k < ir->n_couplings; ++k) coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
   PropEntry prop[HEGET_N_PARTICLES];
   prop_table(ir->sm, prop);
+  p->hadronic = ir->ps_hadron_ymax > 0 ? 1 : 0;
   p->spin_states = 1;
   for (int k = 0; k < 2; ++k) {
     const heget_leg& l = ir->legs[k];

@@ -19,6 +19,7 @@ struct heget_process {
   double cut_pt = 0, cut_dr = 0;
   int n_a_n_b = 1, symmetry = 1;
   int spin_states = 4;       // polarisation states of the two incoming legs (spin average)
+  int hadronic = 0;          // hadronic collision: the partonic flux is in the per-event weight
   double beam_m[2] = {0, 0}; // masses of the incoming legs (flux)
   double* d_cpl = nullptr;
   heget::PropEntry* d_prop = nullptr;

@@ -189,6 +189,46 @@ __device__ __forceinline__ double ps_decay(double uc, double uphi, const mom& P,
   return rl / (8.0 * pi * M * M);
 }
 
+// A parton collision at a hadron collider of energy sqrt_S (the paper's
+// Appendix A with parton densities set to 1): daughter 0 (mass m0) and
+// daughter 1 (mass m1) get rapidities flat in [-y_max, y_max] (u[0], u[3]);
+// daughter 0 gets ln(m0^2 + pT^2) flat from pT = pt_min to the kinematic
+// limit lambda^(1/2)(S, m0^2, m1^2) / (2 sqrt_S) (u[1]) and a flat azimuth
+// (u[2]); daughter 1 balances pT.  x_a, x_b = sum (E +- p_z) / sqrt_S give the
+// incoming partons along +-z.  Returns dSigma_2 / (2 s_hat) with
+// dSigma_2 = (2 pi / S) dy_1 dy_0 dpT^2 / (4 pi)^2 dphi / (2 pi), or 0 unless
+// x_a, x_b < 1.
+__device__ __forceinline__ double ps_hadronic(const double* u, double sqrt_S, double m0, double m1, double y_max,
+                                              double pt_min, mom& q0, mom& q1, mom& pa, mom& pb) {
+#pragma clang fp contract(off)
+  const double pi = 3.14159265358979323846;
+  const double S = sqrt_S * sqrt_S;
+  const double y0 = -y_max + 2.0 * y_max * u[0];
+  const double y1 = -y_max + 2.0 * y_max * u[3];
+  const double lam = fmax((S - (m0 + m1) * (m0 + m1)) * (S - (m0 - m1) * (m0 - m1)), 0.0);
+  const double pt2max = lam / (4.0 * S);
+  const double llo = log(m0 * m0 + pt_min * pt_min), lhi = log(m0 * m0 + pt2max);
+  const double L = llo + u[1] * (lhi - llo);
+  const double mt0sq = exp(L);
+  const double pt = sqrt(fmax(mt0sq - m0 * m0, 0.0));
+  double sf, cf;
+  sincos(2.0 * pi * u[2], &sf, &cf);
+  const double px = pt * cf, py = pt * sf;
+  const double mt0 = sqrt(mt0sq), mt1 = sqrt(m1 * m1 + pt * pt);
+  const double e0 = mt0 * cosh(y0), z0 = mt0 * sinh(y0);
+  const double e1 = mt1 * cosh(y1), z1 = mt1 * sinh(y1);
+  const double xa = (e0 + z0 + e1 + z1) / sqrt_S, xb = (e0 - z0 + e1 - z1) / sqrt_S;
+  q0 = {e0, px, py, z0};
+  q1 = {e1, -px, -py, z1};
+  const double h = 0.5 * sqrt_S;
+  pa = {xa * h, 0.0, 0.0, xa * h};
+  pb = {xb * h, 0.0, 0.0, -xb * h};
+  if (!(lhi > llo && xa < 1.0 && xb < 1.0)) return 0.0;
+  const double sh = xa * xb * S;
+  const double w = (2.0 * pi / S) * (2.0 * y_max) * (2.0 * y_max) * mt0sq * (lhi - llo) / (16.0 * pi * pi);
+  return w / (2.0 * sh);
+}
+
 // every final particle has pT > pt_min and every final pair Delta R > dr_min
 template <int NOUT>
 __device__ __forceinline__ bool pass_pt_dr(const mom* p, double pt_min, double dr_min) {

@@ -152,6 +152,11 @@ class Process:
     # None: RAMBO.  ps_window: the Breit-Wigner window factor (paper: 20).
     ps_tree: Optional[List[Tuple[int, int, int, int]]] = None
     ps_window: float = 20.0
+    # Optional hadronic collision (the paper's Appendix A with parton densities
+    # set to 1): (y_max, pt_min).  Node 0 of the tree is then a parton collision
+    # at the hadronic sqrt_s, its two daughters generated in rapidity within
+    # +-y_max, ln(m^2 + pT^2) from pt_min and azimuth; x_a, x_b follow.
+    ps_hadronic: Optional[Tuple[float, float]] = None
 
     def uses_colour_mfma(self):
         """The colour quadratic form runs on MFMA for ordering templates with
@@ -237,6 +242,13 @@ class Process:
             validate_ps_tree(self.ps_tree, self.legs, self.ps_window)
         elif any(leg.particle != P_ZERO for leg in self.legs):
             raise ValueError("RAMBO phase space needs massless legs (give a resonance tree)")
+        if self.ps_hadronic is not None:
+            y_max, pt_min = self.ps_hadronic
+            if self.ps_tree is None or not (y_max > 0 and math.isfinite(y_max)) or not pt_min >= 0:
+                raise ValueError("hadronic collision: needs a tree, y_max > 0, pt_min >= 0")
+            for d in self.ps_tree[0][2:4]:
+                if d >= 0 and self.legs[d].particle == P_ZERO and not pt_min > 0:
+                    raise ValueError("hadronic collision: a massless daughter of the collision needs pt_min > 0")
         return self
 
     # -------------------------------------------------------------- fingerprint
@@ -296,6 +308,10 @@ class Process:
                 for x in node:
                     i32(x)
             f64(self.ps_window)
+        if self.ps_hadronic:
+            i32(1)
+            f64(self.ps_hadronic[0])
+            f64(self.ps_hadronic[1])
         return bytes(b)
 
     def fingerprint(self):

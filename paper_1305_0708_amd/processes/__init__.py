@@ -13,6 +13,7 @@ Leg order (the momentum layout of heget_eval):
   gg_4g        g g g g g g   (120 trace-basis flows; gg_4g_ddm: the 24 evaluated orderings as flows)
 """
 import copy
+import dataclasses
 import functools
 from fractions import Fraction
 
@@ -246,10 +247,22 @@ def _gluons(n, basis):
     return gg_ng(n, basis=basis)
 
 
+def gg_ttbar_6f_had(sqrt_s=14000.0, y_max=2.5):
+    """C1 at a hadron collider of energy sqrt_s (the paper's Appendix A): the
+    top pair from a gluon-gluon collision with x_a, x_b from momentum
+    conservation and parton densities set to 1 (CTEQ6L1 is absent), the tops
+    in rapidity within +-y_max, ln(m_t^2 + pT^2) and azimuth, each decaying
+    through the resonance tree of gg_ttbar_6f_bw.  sigma = integral dx_a dx_b
+    sigma_hat(x_a x_b s) over |y_t| < y_max."""
+    return dataclasses.replace(gg_ttbar_6f_bw(), name="gg_ttbar_6f_had", sqrt_s=sqrt_s,
+                               ps_hadronic=(y_max, 0.0)).validate()
+
+
 def by_name(name):
     gluon = {"gg_4g": (6, "trace"), "gg_4g_ddm": (6, "ddm"), "gg_5g_ddm": (7, "ddm")}
     if name in gluon:
         # the colour matrices of the larger bases take seconds to build: built once, copied out
         return copy.deepcopy(_gluons(*gluon[name]))
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
-            "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww}[name]()
+            "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww,
+            "gg_ttbar_6f_had": gg_ttbar_6f_had}[name]()

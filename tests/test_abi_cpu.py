@@ -46,7 +46,7 @@ def _status(fn):
     return 0
 
 
-@pytest.mark.parametrize("name", ["ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm"])
+@pytest.mark.parametrize("name", ["ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "gg_ttbar_6f_had", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm"])
 def test_fingerprint_matches_compiled_kernel(name):
     # a valid IR passes validation and the kernel lookup; without a GPU the
     # first device allocation then fails with HEGET_E_OOM (on a GPU: success)

@@ -1,0 +1,24 @@
+"""CPU checks of the benchmark's bookkeeping: the executed-flop and HBM-byte
+counters that bench.py quotes for the dominant kernel were taken on the kernel
+source it would run now (else its roofline would fall back to the IR flop
+model, which counts arithmetic the compiler drops and can exceed the peak)."""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_counters_were_taken_on_the_current_kernel_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1305_0708_amd import processes
+    assert bench.counters_valid(processes.by_name("gg_ttbar_6f")), \
+        "the C1 kernel source changed since its counters were taken: re-take them and update the digest"
+
+
+def test_executed_flops_stay_below_the_peak_at_the_quoted_duration():
+    sys.path.insert(0, ROOT)
+    import bench
+    # 2^20 events in the traced 1.18-1.24 ms
+    tflops = bench.COUNTERS_FP64["flop_per_event"] * (1 << 20) / 1.18e-3 / 1e12
+    assert tflops < bench.FP64_PEAK_TFLOPS

@@ -1,0 +1,120 @@
+"""GPU parity of the hadronic collision of the paper's Appendix A (parton
+densities set to 1) for C1: the top pair from a gluon-gluon collision at a
+14 TeV hadron collider, x_a and x_b from momentum conservation, the tops in
+rapidity within +-2.5, ln(m^2 + pT^2) and azimuth, then the resonance tree's
+decays.  Momenta and per-event weights of heget_generate against the oracle's
+generator, |M|^2 of the lab-frame events, and the cross section."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NAME = "gg_ttbar_6f_had"
+ROOTS = 14000.0
+SEED = 0x48414452
+MT, WT, MW, WW = 175.0, 1.55, 80.4, 2.085
+HAD = (2.5, 0.0)
+
+
+def oracle_tree():
+    return [(0.0, 0.0, None, -2, -3, None), (MT, WT, "bw", 2, -4, 20.0), (MT, WT, "bw", 5, -5, 20.0),
+            (MW, WW, "bw", 3, 4, 20.0), (MW, WW, "bw", 6, 7, 20.0)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def proc(torch):
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    return H.Process(processes.by_name(NAME))
+
+
+def to_aos(t):
+    return np.ascontiguousarray(np.transpose(t.cpu().numpy(), (2, 0, 1)))
+
+
+def to_soa(torch, mom):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
+
+
+@pytest.mark.parametrize("n,offset", [(1000, 0), (4099, 999)])
+def test_momenta_and_weights_match_oracle(torch, oracle, proc, n, offset):
+    from oracle import phase_space_tree as T
+    mom, w = proc.generate(n, seed=SEED, counter_offset=offset, sqrt_s=ROOTS, want_weights=True)
+    torch.cuda.synchronize()
+    ref_mom, ref_w = T.generate(SEED, n, ROOTS, oracle_tree(), 8, counter_offset=offset, hadronic=HAD)
+    w = w.cpu().numpy()
+    ok = ref_w > 0
+    assert 0.1 < ok.mean() < 1.0
+    assert np.array_equal(w > 0, ok)                 # the same events fail x_a, x_b < 1
+    assert np.abs(w[ok] / ref_w[ok] - 1).max() < 1e-12
+    got = to_aos(mom)
+    assert np.abs(got[ok] - ref_mom[ok]).max() < 1e-12 * ROOTS
+
+
+def boost_z(mom, beta):
+    """boost every momentum of each event along z by its own velocity beta"""
+    g = 1.0 / np.sqrt(1.0 - beta * beta)
+    out = mom.copy()
+    out[..., 0] = g[:, None] * (mom[..., 0] - beta[:, None] * mom[..., 3])
+    out[..., 3] = g[:, None] * (mom[..., 3] - beta[:, None] * mom[..., 0])
+    return out
+
+
+def rotated(mom, seed):
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    out = mom.copy()
+    out[..., 1:] = mom[..., 1:] @ q.T
+    return out
+
+
+def test_me2_of_hadronic_events_matches_oracle(torch, oracle, proc):
+    """lab-frame events, momenta in.  The partonic system moves along z (x_a !=
+    x_b): invariants and Breit-Wigner denominators then come from large,
+    cancelling components, and an FP64 evaluation of F carries a rounding
+    error that grows with the boost.  |F_gpu/F_oracle - 1| <= 1e-12, or 16 nu
+    where the event's floor nu is larger: the largest change of the oracle's own
+    F between the lab frame, the partons' rest frame and rotated frames"""
+    from oracle import phase_space_tree as T
+    prm = oracle.params()
+    mom, w = T.generate(SEED + 1, 3000, ROOTS, oracle_tree(), 8, hadronic=HAD)
+    mom = mom[w > 0]
+    me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+    ref = oracle.me2(oracle.GG_TT_6F, mom, prm)
+    err = np.abs(me2 - ref) / np.abs(ref)
+    bad = err > 1e-12
+    sub = mom[bad]
+    beta = (sub[:, 0, 0] - sub[:, 1, 0]) / (sub[:, 0, 0] + sub[:, 1, 0])
+    frames = [boost_z(sub, beta)] + [rotated(sub, s) for s in range(4)]
+    nu = np.zeros(bad.sum())
+    for f in frames:
+        nu = np.maximum(nu, np.abs(oracle.me2(oracle.GG_TT_6F, f, prm) / ref[bad] - 1))
+    print(f"hadronic events: F max rel diff {err.max():.2e}, median {np.median(err):.2e}, "
+          f"{bad.sum()} of {err.size} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
+    assert np.all(err[bad] <= 16 * nu)
+
+
+def test_integrate_matches_oracle(torch, oracle, proc):
+    """sigma = integral dx_a dx_b sigma_hat with the partonic flux 1 / (2 s_hat)
+    in each event's weight; sigma inherits the lab-frame floor of F: 1e-11"""
+    from oracle import phase_space_tree as T
+    n = 1 << 13
+    r = proc.integrate(n, seed=SEED, sqrt_s=ROOTS)
+    mom, w = T.generate(SEED, n, ROOTS, oracle_tree(), 8, hadronic=HAD)
+    f = np.zeros(n)
+    ok = w > 0
+    f[ok] = oracle.me2(oracle.GG_TT_6F, mom[ok], oracle.params())
+    sig, err, _, _ = oracle.cross_section(f, w, ROOTS, proc.ir.n_a_n_b, proc.ir.symmetry, flux_in_weight=True)
+    print(f"hadronic sigma: GPU {r['sigma_gev2']:.15e} oracle {sig:.15e} rel {r['sigma_gev2'] / sig - 1:.2e}; "
+          f"{r['n_accepted']} of {n} events with x_a, x_b < 1")
+    assert r["n_accepted"] == int(ok.sum())
+    assert abs(r["sigma_gev2"] / sig - 1) <= 1e-11
+    assert abs(r["err_gev2"] / err - 1) <= 1e-9

@@ -150,3 +150,51 @@ def test_massive_volume_does_not_depend_on_the_tree(T):
     (a, ea), (b, eb) = est
     assert abs(a - b) < 4 * math.hypot(ea, eb)
     assert ea < 0.01 * a and eb < 0.01 * b
+
+
+# ------------------------------------------------------------ hadronic collision (Appendix A, densities 1)
+def test_hadronic_two_body_volume_matches_quadrature(T):
+    """t tbar at a 2 TeV hadron collider with the rapidity range covering every
+    kinematically allowed top (|y| <= ln(sqrt_S / m_t) < 2.5): the Monte Carlo
+    mean of dSigma_2 g(s_hat) (the weight times 2 s_hat) equals the integral
+    over dx_a dx_b of Phi_2(s_hat; m_t, m_t) g(s_hat), here with g = S / s_hat,
+    by two-dimensional quadrature in x_a, x_b"""
+    from scipy import integrate
+    m, rs = 175.0, 2000.0
+    S = rs * rs
+    mom, w = T.generate(5, 400000, rs, [(0.0, 0.0, None, 2, 3, None)], 4, leg_mass=[0, 0, m, m],
+                        hadronic=(2.5, 0.0))
+    P = mom[:, 0] + mom[:, 1]
+    sh = P[:, 0] ** 2 - (P[:, 1:] ** 2).sum(1)
+    val = w * 2.0 * sh * (S / sh)
+    est, err = val.mean(), val.std() / math.sqrt(val.size)
+
+    def phi2_g(xb, xa):
+        s = xa * xb * S
+        return math.sqrt(max((s - 4 * m * m) * s, 0.0)) / (8 * math.pi * s) * (S / s) if s > 4 * m * m else 0.0
+    ref, _ = integrate.dblquad(phi2_g, 4 * m * m / S, 1.0, lambda xa: 4 * m * m / (S * xa), 1.0,
+                               epsabs=1e-12, epsrel=1e-9)
+    assert abs(est - ref) < 4 * err
+    assert err < 0.01 * ref
+
+
+def test_hadronic_tree_conservation_and_beams(T):
+    """C1 from a gluon-gluon collision at 14 TeV: the incoming partons along +-z
+    with x_a, x_b < 1 carry the final state's four-momentum; the tops sit in
+    |y| < 2.5; an event outside x < 1 has weight 0"""
+    tree = [(0.0, 0.0, None, -2, -3, None), (MT, WT, "bw", 2, -4, 20.0), (MT, WT, "bw", 5, -5, 20.0),
+            (MW, WW, "bw", 3, 4, 20.0), (MW, WW, "bw", 6, 7, 20.0)]
+    rs = 14000.0
+    assert T.n_uniforms(tree, (2.5, 0.0)) == 16
+    mom, w = T.generate(9, 20000, rs, tree, 8, hadronic=(2.5, 0.0))
+    ok = w > 0
+    assert 0.1 < ok.mean() < 1.0
+    xa, xb = 2 * mom[:, 0, 0] / rs, 2 * mom[:, 1, 0] / rs
+    assert np.all(xa[ok] < 1) and np.all(xb[ok] < 1) and np.all((xa >= 1) | (xb >= 1) | ok)
+    assert np.abs(mom[:, 0, 1:3]).max() == 0 and np.abs(mom[:, 1, 1:3]).max() == 0
+    bal = mom[:, 0] + mom[:, 1] - mom[:, 2:].sum(1)
+    assert np.abs(bal[ok]).max() < 1e-10 * rs
+    assert np.abs(msq(mom[ok][:, 2:])).max() < 1e-10 * rs ** 2
+    top = mom[:, 2:5].sum(1)
+    y = 0.5 * np.log((top[:, 0] + top[:, 3]) / (top[:, 0] - top[:, 3]))
+    assert np.abs(y).max() < 2.5 + 1e-9
