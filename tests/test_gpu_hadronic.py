@@ -118,3 +118,19 @@ def test_integrate_matches_oracle(torch, oracle, proc):
     assert r["n_accepted"] == int(ok.sum())
     assert abs(r["sigma_gev2"] / sig - 1) <= 1e-11
     assert abs(r["err_gev2"] / err - 1) <= 1e-9
+
+
+def test_mixed_precision_error(torch, oracle):
+    """the mixed path on lab-frame hadronic events: the error against the FP64
+    oracle is reported (FP32 wavefunctions and chain)"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    from oracle import phase_space_tree as T
+    mixed = H.Process(processes.by_name(NAME), precision="mixed")
+    mom, w = T.generate(SEED + 2, 3000, ROOTS, oracle_tree(), 8, hadronic=HAD)
+    mom = mom[w > 0]
+    me2 = mixed.eval(momenta=to_soa(torch, mom)).cpu().numpy()
+    ref = oracle.me2(oracle.GG_TT_6F, mom, oracle.params())
+    err = np.abs(me2 - ref) / np.abs(ref)
+    print(f"hadronic mixed: max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert np.median(err) < 1e-3
