@@ -210,8 +210,10 @@ typedef struct {
  * mixed path (FP32 wavefunctions, vertex chain and colour sum; FP64 momenta,
  * propagator denominators and reductions).  *out receives the handle.
  * Errors: HEGET_E_INVALID (null pointers), HEGET_E_IR (malformed IR),
- * HEGET_E_UNSUPPORTED (no kernel compiled for this structure), HEGET_E_OOM,
- * HEGET_E_HIP.  heget_eval never allocates. */
+ * HEGET_E_UNSUPPORTED (no kernel compiled for this structure; or HEGET_MIXED for a
+ * process whose colour form runs on MFMA, switched off after unexplained GPU
+ * faults of those mixed kernels), HEGET_E_OOM, HEGET_E_HIP.  heget_eval never
+ * allocates. */
 heget_status heget_process_create(const heget_process_ir* ir, heget_precision prec, heget_process_t* out);
 
 /* Release the handle and its device tables (synchronises the device first). */

@@ -582,6 +582,13 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
                   (unsigned long long)fp);
     return fail(HEGET_E_UNSUPPORTED, buf);
   }
+  // Mixed-precision kernels with the MFMA colour form have made illegal memory
+  // accesses on the GPU (an FP32 colour form over FP32 rows, and an FP32 chain
+  // feeding an FP64 colour form) with no cause found in their code: refused
+  // until one is, so that no caller launches them.
+  if (prec == HEGET_MIXED && entry->colour_mfma)
+    return fail(HEGET_E_UNSUPPORTED, "mixed precision is switched off for processes whose colour form runs on "
+                "MFMA (an unexplained GPU fault); use FP64, or a basis with the VALU colour form");
   heget_process* p = new heget_process();
   p->entry = entry;
   p->prec = prec;

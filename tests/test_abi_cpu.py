@@ -123,3 +123,18 @@ def test_adaptive_entry_points_reject_a_null_handle(lib):
     assert lib.heget_integrate_adaptive(None, 1024, 2, 8, 1000.0, 1, None, comb, None, None, None) \
         == _lib.HEGET_E_INVALID
     assert lib.heget_process_grid_dims(None) == -1
+
+
+@pytest.mark.parametrize("name,expect", [("gg_4g", -5), ("gg_5g_ddm", -5), ("gg_4g_ddm", None)])
+def test_mixed_precision_on_the_mfma_colour_form_is_refused(name, expect):
+    """the mixed kernels of processes whose colour form runs on MFMA are refused
+    at create, before any allocation (HEGET_E_UNSUPPORTED); a process with the
+    VALU colour form gets past the check (then, without a GPU, HEGET_E_OOM at
+    the first device allocation)"""
+    import paper_1305_0708_amd as H
+    import torch
+    from paper_1305_0708_amd import processes
+    st = _status(lambda: H.Process(processes.by_name(name), precision="mixed"))
+    if expect is None:
+        expect = 0 if torch.cuda.is_available() else -3
+    assert st == expect

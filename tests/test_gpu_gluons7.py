@@ -2,8 +2,8 @@
 per helicity in the DDM basis, 128 helicity combinations, the colour form on
 MFMA with its amplitude rows read from the workspace) against the oracle's
 Berends-Giele recursion in the trace basis (720 orderings, colour matrix by
-Fierz expansion): two colour bases, one |M|^2.  FP64 only: the FP32 MFMA
-colour form stays off the GPU until the cause of an earlier fault is shown."""
+Fierz expansion): two colour bases, one |M|^2.  FP64 only: the mixed kernel
+is switched off (MIXED_OFF below)."""
 import numpy as np
 import pytest
 
@@ -90,3 +90,33 @@ def test_integrate_matches_its_events(torch, oracle, proc, reference):
     print(f"gg->5g sigma: GPU {r['sigma_gev2']:.15e} oracle {sig:.15e} rel {r['sigma_gev2'] / sig - 1:.2e}")
     assert r["n_accepted"] == int(np.sum(f != 0))
     assert abs(r["sigma_gev2"] / sig - 1) <= 1e-12
+
+
+MIXED_OFF = ("the mixed kernel (FP32 chain, FP64 amplitude rows and FP64 MFMA colour form) made an illegal "
+             "memory access on its first launch with no cause found in its code; heget_process_create "
+             "refuses mixed precision for MFMA colour forms until one is")
+
+
+@pytest.mark.skip(reason=MIXED_OFF)
+def test_mixed_precision_error(torch, oracle, reference):
+    """the mixed kernel on the same events: cut events exactly 0 (the cut is
+    taken on FP64 kinematics), the relative error of F at FP32's scale, and
+    sigma from its own integrate step near the oracle's"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    mixed = H.Process(processes.by_name(NAME), precision="mixed")
+    me2 = mixed.eval(n=N_REF, seed=SEED, sqrt_s=ROOTS).cpu().numpy()
+    ref = reference[1]
+    zero = ref == 0
+    assert np.all(me2[zero] == 0.0)
+    err = np.abs(me2[~zero] - ref[~zero]) / np.abs(ref[~zero])
+    r = mixed.integrate(N_REF, seed=SEED, sqrt_s=ROOTS)
+    sig, _, _, _ = oracle.cross_section(ref, oracle.phase_space_volume(ROOTS, 5), ROOTS, mixed.ir.n_a_n_b,
+                                        mixed.ir.symmetry)
+    print(f"gg->5g mixed: max rel err {err.max():.2e}, median {np.median(err):.2e}; "
+          f"sigma rel {r['sigma_gev2'] / sig - 1:.2e}")
+    assert np.all(np.isfinite(me2))
+    assert np.median(err) < 1e-4
+    assert err.max() < 1e-1
+    assert r["n_accepted"] == int(np.sum(~zero))
+    assert abs(r["sigma_gev2"] / sig - 1) < 1e-3
