@@ -37,6 +37,10 @@ TEMPLATE_KIN_PER_LEVEL = True
 # FP32 kernels hold these currents in registers without spilling, and there
 # the opaque reads cost more than they save.
 TEMPLATE_STASH_WORDS = 48
+# ordering templates: each vertex vector of the running sum R is added right
+# after the last of its operands is formed in the sum's loop (first, when all
+# come from outer loops), so that the currents it reads can die early
+TEMPLATE_EARLY_VERTEX_SUM = True
 # MFMA colour form: 16-event chunks of a wave per pass (each fragment load serves them all)
 COLOUR_CHUNKS = 2
 # amplitude rows of the MFMA colour form above this many bytes (FP64) are not
@@ -1036,6 +1040,8 @@ class Gen:
         self._rt_level = rs.level
         outer = [(a, cf) for a, cf in rs.data if self._r_level(sc, a) < rs.level]
         lst = by_level[rs.level]
+        if TEMPLATE_EARLY_VERTEX_SUM:
+            lst = self._early_vertex_terms(lst)
         first = next(i for i, it in enumerate(lst) if it.kind in ("rvec", "rsum"))
         lst.insert(first, nest.Item("rstart", rs.level, tuple(outer), 0))
         by_level[rs.level] = [it for it in lst if it.kind != "rsum"]
@@ -1069,6 +1075,31 @@ class Gen:
             ind = ind[:-2]
             w(f"{ind}}}")
         self._scope = None
+
+    def _early_vertex_terms(self, lst):
+        """the items of the running sum's loop with every vertex vector moved to
+        just after the item that forms the last of its operands in this loop
+        (to the front when none does); the other items keep their order"""
+        p = self.p
+        rest = [it for it in lst if it.kind not in ("rvec", "rsum")]
+        formed = {}
+        for i, it in enumerate(rest):
+            if it.kind == "ext":
+                formed[it.data[0]] = i
+            elif it.kind == "call":
+                formed[p.calls[it.data[0]].out] = i
+        after = {}
+        for it in lst:
+            if it.kind == "rvec":
+                last = max((formed.get(x, -1) for x in p.calls[it.data[0]].ins), default=-1)
+                after.setdefault(last, []).append(it)
+        out = list(after.get(-1, []))
+        for i, it in enumerate(rest):
+            out.append(it)
+            out.extend(after.get(i, []))
+        out.extend(it for it in lst if it.kind == "rsum")
+        assert sorted(map(id, out)) == sorted(map(id, lst))
+        return out
 
     def _r_level(self, sc, amp):
         for it in sc.items:
