@@ -41,6 +41,9 @@ TEMPLATE_STASH_WORDS = 48
 # after the last of its operands is formed in the sum's loop (first, when all
 # come from outer loops), so that the currents it reads can die early
 TEMPLATE_EARLY_VERTEX_SUM = True
+# ordering templates: the same for the sums of partial currents (vadd, vsub) in
+# every loop, so that a current's terms are accumulated as they are formed
+TEMPLATE_EARLY_CURRENT_SUMS = True
 # MFMA colour form: 16-event chunks of a wave per pass (each fragment load serves them all)
 COLOUR_CHUNKS = 2
 # amplitude rows of the MFMA colour form above this many bytes (FP64) are not
@@ -1039,9 +1042,10 @@ class Gen:
         rs = next(it for it in sc.items if it.kind == "rsum")
         self._rt_level = rs.level
         outer = [(a, cf) for a, cf in rs.data if self._r_level(sc, a) < rs.level]
+        if TEMPLATE_EARLY_CURRENT_SUMS or TEMPLATE_EARLY_VERTEX_SUM:
+            for lvl in list(by_level):
+                by_level[lvl] = self._early_consumers(by_level[lvl], lvl == rs.level)
         lst = by_level[rs.level]
-        if TEMPLATE_EARLY_VERTEX_SUM:
-            lst = self._early_vertex_terms(lst)
         first = next(i for i, it in enumerate(lst) if it.kind in ("rvec", "rsum"))
         lst.insert(first, nest.Item("rstart", rs.level, tuple(outer), 0))
         by_level[rs.level] = [it for it in lst if it.kind != "rsum"]
@@ -1076,28 +1080,40 @@ class Gen:
             w(f"{ind}}}")
         self._scope = None
 
-    def _early_vertex_terms(self, lst):
-        """the items of the running sum's loop with every vertex vector moved to
-        just after the item that forms the last of its operands in this loop
-        (to the front when none does); the other items keep their order"""
+    def _early_consumers(self, lst, rt_loop):
+        """one loop's items with every consumer that shrinks the live set (a
+        vertex vector of the running sum in the sum's loop, a sum of partial
+        currents) moved to just after the item that forms the last of its
+        operands in this loop, or to the front when none does; movers with the
+        same anchor keep their order, every other item keeps its order"""
         p = self.p
-        rest = [it for it in lst if it.kind not in ("rvec", "rsum")]
-        formed = {}
-        for i, it in enumerate(rest):
-            if it.kind == "ext":
-                formed[it.data[0]] = i
-            elif it.kind == "call":
-                formed[p.calls[it.data[0]].out] = i
-        after = {}
-        for it in lst:
+
+        def movable(it):
             if it.kind == "rvec":
-                last = max((formed.get(x, -1) for x in p.calls[it.data[0]].ins), default=-1)
-                after.setdefault(last, []).append(it)
-        out = list(after.get(-1, []))
-        for i, it in enumerate(rest):
-            out.append(it)
-            out.extend(after.get(i, []))
-        out.extend(it for it in lst if it.kind == "rsum")
+                return rt_loop and TEMPLATE_EARLY_VERTEX_SUM
+            return (it.kind == "call" and TEMPLATE_EARLY_CURRENT_SUMS
+                    and p.calls[it.data[0]].op in ir.LINEAR_OPS)
+
+        def outs(it):
+            if it.kind == "ext":
+                return (it.data[0],)
+            if it.kind == "call":
+                return (p.calls[it.data[0]].out,)
+            return ()
+
+        out, moved = [], set()
+        for it in lst:
+            if not movable(it):
+                out.append(it)
+                continue
+            ins = set(p.calls[it.data[0]].ins)
+            at = max((i for i, o in enumerate(out) if ins & set(outs(o))), default=-1) + 1
+            while at < len(out) and id(out[at]) in moved:
+                at += 1
+            out.insert(at, it)
+            moved.add(id(it))
+        rs = [it for it in out if it.kind == "rsum"]
+        out = [it for it in out if it.kind != "rsum"] + rs
         assert sorted(map(id, out)) == sorted(map(id, lst))
         return out
 
