@@ -40,7 +40,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    the compiled kernel does, after the compiler has dropped the operations on
 #    the structural zeros of fixed-helicity massless spinors that the IR flop
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
-COUNTERS_FP64 = {"source_digest": "4370b50918613e1c178b8b67b68f052b577c7f71b4aa6dce0aed091066e5e1d9",
+# All were re-taken on the kernel with the bra sums accumulated bra by bra
+# (the same values as on the kernel before it).
+COUNTERS_FP64 = {"source_digest": "b40c3fc1f6ee5b67dccdc316e30018dfa79ed057ba53b95336d1c0b393be727a",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 

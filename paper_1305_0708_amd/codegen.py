@@ -750,6 +750,11 @@ class Gen:
             f, g, members = it.data
             comps = [" + ".join(_coef_expr(cc, f"bra{a}.c[{m}]") for a, cc in members) for m in range(4)]
             w(f"{ind}const wf<T> bj{f}_{g} = {{{{{', '.join(comps)}}}}};")
+        elif it.kind == "bacc":
+            f, g, a, cc, j, last = it.data
+            name = f"bj{f}_{g}" if last else f"bj{f}_{g}_{j}"
+            comps = [(f"bj{f}_{g}_{j - 1}.c[{m}] + " if j else "") + _coef_expr(cc, f"bra{a}.c[{m}]") for m in range(4)]
+            w(f"{ind}const wf<T> {name} = {{{{{', '.join(comps)}}}}};")
         elif it.kind == "kdot":
             f, g, ket, vector = it.data
             prod = "vec_dot" if vector else "spinor_dot"

@@ -132,7 +132,7 @@ ONE = None   # an argument slot replaced by the scalar 1 (its value deferred as 
 
 @dataclass
 class Item:
-    kind: str          # "ext", "call", "mat", "bra", "dot", "vbra", "vdot", "ksum", "bsum", "kdot", "jamp"
+    kind: str          # "ext", "call", "mat", "bra", "dot", "vbra", "vdot", "ksum", "bsum", "bacc", "kdot", "jamp"
     level: int         # loop level (-1: before the loops)
     data: tuple
     flops: int
@@ -144,6 +144,36 @@ class Schedule:
     choices: List[Tuple[int, ...]]
     items: List[Item]          # in dependency order
     flops_per_event: int       # model flops of the loop nest, per event
+
+
+# each combined bra joins its jamp group's sum right after it is formed (bras
+# of outer loops first, at the top of the sum's loop), so that the bras of a
+# group do not all stay live until one sum takes them
+EARLY_BRA_SUMS = True
+
+
+def _early_bra_sums(items, proc):
+    """the items with every bra sum ("bsum") replaced by a chain of partial sums
+    ("bacc": jamp, group, amplitude, coefficient, position in the chain, last),
+    each right after the bra it adds; the last one defines the group's sum"""
+    out = [it for it in items if it.kind != "bsum"]
+    bra_at = {proc.calls[it.data[0]].out: i for i, it in enumerate(out) if it.kind in ("bra", "vbra")}
+    after = {}
+    for it in items:
+        if it.kind != "bsum":
+            continue
+        f, g, members = it.data
+        chain = sorted(members, key=lambda m: (out[bra_at[m[0]]].level == it.level, bra_at[m[0]]))
+        for j, (a, cc) in enumerate(chain):
+            i = bra_at[a]
+            anchor = i if out[i].level == it.level else -1
+            after.setdefault(anchor, []).append(
+                Item("bacc", it.level, (f, g, a, cc, j, j == len(chain) - 1), 0 if j == 0 else 4 * flops.CADD))
+    res = list(after.get(-1, []))
+    for i, it in enumerate(out):
+        res.append(it)
+        res.extend(after.get(i, []))
+    return res
 
 
 def schedule(proc):
@@ -281,6 +311,8 @@ def schedule(proc):
         out.append(it)
     items = out
     items += jamp_items
+    if EARLY_BRA_SUMS:
+        items = _early_bra_sums(items, proc)
     mult, m = {-1: 1}, 1
     for i, L in enumerate(pl.order):
         m *= len(pl.choices[L])

@@ -39,10 +39,12 @@ def test_schedule_is_complete_and_ordered(name):
             assert level_of[fi[1]] <= it.level
         elif it.kind == "bsum":
             seen_amps.extend(a for a, _ in it.data[2])      # products formed with the combined bra
+        elif it.kind == "bacc":
+            seen_amps.append(it.data[2])                     # the same, one bra at a time
     assert sorted(seen_calls) == list(range(len(p.calls)))
     assert set(seen_amps) == set(range(p.n_amps))
     ks = [it for it in sc.items if it.kind in ("ksum", "bsum")]
-    used = sorted(a for it in ks for a, _ in it.data[2])
+    used = sorted([a for it in ks for a, _ in it.data[2]] + [it.data[2] for it in sc.items if it.kind == "bacc"])
     assert used == sorted(a for terms in p.jamp for a, _ in terms)
     assert {it.data[0] for it in sc.items if it.kind == "jamp"} == set(range(p.n_flows))
 
