@@ -246,6 +246,22 @@ heget_status heget_eval(heget_process_t p, int64_t n, const double* momenta_in, 
 heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_t counter_offset, double sqrt_s,
                             double* momenta_out, double* weights_out, void* stream);
 
+/* The counter-based random numbers alone (the first step of every generated
+ * event; not in the paper, which seeds a per-thread xorshift generator: the
+ * counter-based Philox4x32-10 of Salmon et al., SC'11, makes any event
+ * reproducible from (seed, event index)).  Event i (counter counter_offset + i)
+ * uses counter (i_lo, i_hi, j, 0) and key (seed_lo, seed_hi) for its block j,
+ * and block j gives the uniforms 2 j and 2 j + 1: u = (floor(x / 2^12) + 1/2)
+ * 2^-52 for the 64-bit words x = w0 2^32 + w1 and x = w2 2^32 + w3, exact in
+ * FP64 and strictly inside (0, 1).  These are the uniforms heget_eval's RAMBO
+ * and resonance-tree generators draw (RAMBO: 4 per final particle, in the
+ * order cos theta, phi, and the two factors of the energy).  u_out: device
+ * FP64 SoA [n_u][n], u_out[k * n + i] = uniform k of event i; written
+ * asynchronously on `stream`.  n = 0 is a no-op.  Errors: HEGET_E_INVALID
+ * (n < 0, n_u outside 1 .. 64, null u_out with n > 0), HEGET_E_HIP. */
+heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, int32_t n_u, double* u_out,
+                            void* stream);
+
 /* Monte Carlo cross section from n events generated from `seed` (counters
  * 0 .. n-1) by the process's phase space (RAMBO or its resonance tree):
  * sigma = (1/N) sum_i w_i with w_i = dPhi_n,i * pass_i * F_i / (2 lambda^(1/2) N_pol n_a n_b S),

@@ -31,6 +31,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+# the same sources built with long double arithmetic: the extended-precision
+# reference that bounds the rounding of an FP64 evaluation (oracle/build.py)
+_LIB_LD_PATH = os.path.join(_HERE, "_build", "liboracle_ld.so")
 
 EE_MUMU, GG_TT_6F, GG_4G, UD_UDHH_4B = 0, 1, 2, 3
 GG_GG, GG_GGG, UU_TT, GG_TT, UU_UUHH_4B, WW_HH, ZZ_HH = 10, 11, 12, 13, 14, 16, 17
@@ -56,16 +59,17 @@ def params(**kw):
     return Params(**d)
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def lib(extended=False):
+    """the FP64 oracle library, or with extended=True its long-double build"""
+    path = _LIB_LD_PATH if extended else _LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        L = ctypes.CDLL(_LIB_PATH)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         dp, ip = P(ctypes.c_double), P(ctypes.c_int)
         L.or_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
@@ -91,8 +95,10 @@ def lib():
         L.or_nlegs.argtypes = [ctypes.c_int]
         L.or_selfcheck_spinors.argtypes = [dp, ctypes.c_double]
         L.or_selfcheck_spinors.restype = ctypes.c_double
-        _lib = L
-    return _lib
+        L.or_decay_width.argtypes = [ctypes.c_int, P(Params), dp]
+        L.or_condition.argtypes = [ctypes.c_int, P(Params), ctypes.c_int64, dp, dp, ctypes.c_int]
+        _libs[path] = L
+    return _libs[path]
 
 
 def _dp(a):
@@ -155,14 +161,16 @@ def nlegs(proc):
     return lib().or_nlegs(proc)
 
 
-def me2(proc, mom, prm=None, threads=0):
-    """Helicity- and colour-summed |M|^2 per event (no averaging)."""
+def me2(proc, mom, prm=None, threads=0, extended=False):
+    """Helicity- and colour-summed |M|^2 per event (no averaging).  With
+    extended=True the long-double build evaluates it on the same (FP64)
+    momenta and parameters and the result is rounded to FP64 once."""
     prm = prm or params()
     mom = np.ascontiguousarray(mom, dtype=np.float64)
     if mom.ndim == 2:
         mom = mom[None]
     out = np.zeros(mom.shape[0])
-    rc = lib().or_eval(proc, ctypes.byref(prm), mom.shape[0], _dp(mom), _dp(out), threads)
+    rc = lib(extended).or_eval(proc, ctypes.byref(prm), mom.shape[0], _dp(mom), _dp(out), threads)
     if rc != 0:
         raise ValueError(f"oracle: unknown process {proc}")
     return out
@@ -175,8 +183,6 @@ def condition(proc, mom, prm=None, threads=0):
     if mom.ndim == 2:
         mom = mom[None]
     out = np.zeros(mom.shape[0])
-    lib().or_condition.argtypes = [ctypes.c_int, ctypes.POINTER(Params), ctypes.c_int64,
-                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     if lib().or_condition(proc, ctypes.byref(prm), mom.shape[0], _dp(mom), _dp(out), threads) != 0:
         raise ValueError(f"oracle: no diagram list for process {proc}")
     return out
@@ -253,6 +259,16 @@ def trace_me2(proc, mom, prm=None):
     out = np.zeros(1)
     if lib().or_trace_me2(proc, ctypes.byref(prm), _dp(mom), _dp(out)) != 0:
         raise ValueError(proc)
+    return out[0]
+
+
+def decay_width(which, prm=None, extended=False):
+    """tree-level width (GeV) of W+ -> e+ nu_e (which 0) or t -> b W+ (which 1)
+    from the oracle's own vertex, spinors and polarisation vectors"""
+    prm = prm or params()
+    out = np.zeros(1)
+    if lib(extended).or_decay_width(which, ctypes.byref(prm), _dp(out)) != 0:
+        raise ValueError(which)
     return out[0]
 
 

@@ -55,9 +55,9 @@ extern "C" int or_eval(int proc, const or_params* prm, int64_t n_events, const d
     if (ng) {
       me2[i] = gluon_me2(ng, sm, p);
     } else {
-      double s = 0.0;
+      real s = 0.0;
       for (const auto& h : hels) s += me2_one_helicity(*P, *C, sm, p, h.data());
-      me2[i] = s;
+      me2[i] = double(s);
     }
   }
   return 0;
@@ -79,9 +79,9 @@ extern "C" int or_condition(int proc, const or_params* prm, int64_t n_events, co
   for (int64_t i = 0; i < n_events; ++i) {
     Vec4 p[16];
     load(mom + i * P->nlegs * 4, P->nlegs, p);
-    double a2 = 0.0, b2 = 0.0;
+    real a2 = 0.0, b2 = 0.0;
     for (const auto& h : hels) condition_one_helicity(*P, C, sm, p, h.data(), a2, b2);
-    kappa[i] = std::sqrt(b2 / a2);
+    kappa[i] = double(std::sqrt(b2 / a2));
   }
   return 0;
 }
@@ -149,14 +149,14 @@ extern "C" int or_gluon_partial(int n, const or_params* prm, const double* mom, 
 
 extern "C" int or_gluon_colour_matrix(int n, double* C) {
   if (n < 3 || n > 6) return -1;
-  const std::vector<double>& M = gluon_colour_matrix(n);
-  std::memcpy(C, M.data(), M.size() * sizeof(double));
+  const std::vector<real>& M = gluon_colour_matrix(n);
+  std::copy(M.begin(), M.end(), C);
   return int(M.size());
 }
 
 extern "C" int or_gluon_colour_matrix_fierz(int n, double* C) {
   if (n < 3 || n > 8) return -1;
-  const std::vector<double> M = fierz_colour_matrix(n);
+  const std::vector<real> M = fierz_colour_matrix(n);
   std::copy(M.begin(), M.end(), C);
   return 0;
 }
@@ -169,13 +169,19 @@ extern "C" int or_trace_me2(int proc, const or_params* prm, const double* mom, d
   return out[0] < 0 ? -1 : 0;
 }
 
+extern "C" int or_decay_width(int which, const or_params* prm, double* out) {
+  const SM sm(*prm);
+  out[0] = double(decay_width(sm, which));
+  return out[0] < 0 ? -1 : 0;
+}
+
 extern "C" double or_selfcheck_spinors(const double* pin, double m) {
   // Dirac equation, completeness and helicity eigenvalue checks for one momentum
   Vec4 p = {pin[0], pin[1], pin[2], pin[3]};
   const Mat4 ps = slash(p);
   const Mat4 mm = mscale(m, ident4());
-  double worst = 0.0;
-  const double scale = p[0] + 1.0;
+  real worst = 0.0;
+  const real scale = p[0] + 1;
   Mat4 su = zero4(), sv = zero4();
   for (int lam : {-1, 1}) {
     const Spinor u = u_spinor(p, m, lam), v = v_spinor(p, m, lam);

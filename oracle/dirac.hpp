@@ -13,13 +13,20 @@
 #include <complex>
 #include <vector>
 
+// The arithmetic type: double, or (for the extended-precision reference build
+// of the same sources) long double, chosen with -DORC_REAL=...
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+
 namespace orc {
 
-using cd = std::complex<double>;
+using real = ORC_REAL;
+using cd = std::complex<real>;
 static const cd I1(0.0, 1.0);
-static const double PI = 3.14159265358979323846264338327950288;
+static const real PI = 3.14159265358979323846264338327950288L;
 
-using Vec4 = std::array<double, 4>;   // real contravariant four-vector (E, px, py, pz)
+using Vec4 = std::array<real, 4>;   // real contravariant four-vector (E, px, py, pz)
 using CVec4 = std::array<cd, 4>;      // complex contravariant four-vector
 using Spinor = std::array<cd, 4>;     // Dirac spinor (column) or adjoint spinor (row)
 
@@ -27,12 +34,12 @@ struct Mat4 {
   cd m[4][4];
 };
 
-inline double metric(int mu) { return mu == 0 ? 1.0 : -1.0; }
+inline real metric(int mu) { return mu == 0 ? 1.0 : -1.0; }
 
 inline Vec4 add(const Vec4& a, const Vec4& b) { return {a[0] + b[0], a[1] + b[1], a[2] + b[2], a[3] + b[3]}; }
 inline Vec4 sub(const Vec4& a, const Vec4& b) { return {a[0] - b[0], a[1] - b[1], a[2] - b[2], a[3] - b[3]}; }
 inline Vec4 neg(const Vec4& a) { return {-a[0], -a[1], -a[2], -a[3]}; }
-inline double dot(const Vec4& a, const Vec4& b) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
+inline real dot(const Vec4& a, const Vec4& b) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
 inline cd dot(const CVec4& a, const CVec4& b) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
 inline cd dot(const CVec4& a, const Vec4& b) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
 inline CVec4 cvec(const Vec4& a) { return {a[0], a[1], a[2], a[3]}; }
@@ -139,26 +146,26 @@ inline Spinor dbar(const Spinor& s) {
 // Two-component helicity eigenstates along direction (theta, phi):
 // (sigma . n) chi_lam = lam chi_lam, lam = +1 / -1.
 inline std::array<cd, 2> chi(const Vec4& p, int lam) {
-  double pp = std::sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
-  double th = std::atan2(std::sqrt(p[1] * p[1] + p[2] * p[2]), p[3]);
-  double ph = std::atan2(p[2], p[1]);
+  real pp = std::sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  real th = std::atan2(std::sqrt(p[1] * p[1] + p[2] * p[2]), p[3]);
+  real ph = std::atan2(p[2], p[1]);
   (void)pp;
-  double c = std::cos(0.5 * th), s = std::sin(0.5 * th);
+  real c = std::cos(0.5 * th), s = std::sin(0.5 * th);
   if (lam > 0) return {cd(c, 0.0), std::exp(I1 * ph) * s};
   return {-std::exp(-I1 * ph) * s, cd(c, 0.0)};
 }
 
 // Fermion spinor u(p, lam) in the Dirac-Pauli representation:
 // u = ( sqrt(E+m) chi ; lam sqrt(E-m) chi ), since sigma.p chi = lam |p| chi.
-inline Spinor u_spinor(const Vec4& p, double m, int lam) {
-  double pp = std::sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
-  double E = std::sqrt(pp * pp + m * m);
+inline Spinor u_spinor(const Vec4& p, real m, int lam) {
+  real pp = std::sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  real E = std::sqrt(pp * pp + m * m);
   auto x = chi(p, lam);
-  double a = std::sqrt(E + m), b = lam * std::sqrt(std::max(E - m, 0.0));
+  real a = std::sqrt(E + m), b = lam * std::sqrt(std::max(E - m, real(0)));
   return {a * x[0], a * x[1], b * x[0], b * x[1]};
 }
 // Antifermion spinor by charge conjugation: v(p, lam) = i gamma^2 u(p, lam)^*
-inline Spinor v_spinor(const Vec4& p, double m, int lam) {
+inline Spinor v_spinor(const Vec4& p, real m, int lam) {
   Spinor u = u_spinor(p, m, lam);
   Spinor uc{};
   for (int i = 0; i < 4; ++i) uc[i] = std::conj(u[i]);
@@ -170,32 +177,32 @@ inline Spinor v_spinor(const Vec4& p, double m, int lam) {
 // e2 = (0, -sin ph, cos ph, 0); lam = 0 is longitudinal (|k|, E khat)/m.
 // lam = 4 is the gauge-check vector k^mu / k^0; lam = 10 + alpha is the
 // contravariant unit vector along axis alpha (for covariant polarisation sums).
-inline CVec4 eps_vec(const Vec4& k, double m, int lam) {
+inline CVec4 eps_vec(const Vec4& k, real m, int lam) {
   if (lam == 4) return {1.0, k[1] / k[0], k[2] / k[0], k[3] / k[0]};
   if (lam >= 10 && lam < 14) {
     CVec4 e{};
     e[lam - 10] = 1.0;
     return e;
   }
-  double kt = std::sqrt(k[1] * k[1] + k[2] * k[2]);
-  double kk = std::sqrt(kt * kt + k[3] * k[3]);
-  double th = std::atan2(kt, k[3]), ph = std::atan2(k[2], k[1]);
+  real kt = std::sqrt(k[1] * k[1] + k[2] * k[2]);
+  real kk = std::sqrt(kt * kt + k[3] * k[3]);
+  real th = std::atan2(kt, k[3]), ph = std::atan2(k[2], k[1]);
   if (lam == 0) {
-    double E = std::sqrt(kk * kk + m * m);
+    real E = std::sqrt(kk * kk + m * m);
     return {kk / m, E / m * std::sin(th) * std::cos(ph), E / m * std::sin(th) * std::sin(ph), E / m * std::cos(th)};
   }
   Vec4 e1 = {0.0, std::cos(th) * std::cos(ph), std::cos(th) * std::sin(ph), -std::sin(th)};
   Vec4 e2 = {0.0, -std::sin(ph), std::cos(ph), 0.0};
-  const double r = 1.0 / std::sqrt(2.0);
+  const real r = 1 / std::sqrt(real(2));
   CVec4 e;
-  for (int mu = 0; mu < 4; ++mu) e[mu] = r * (-double(lam) * e1[mu] - I1 * e2[mu]);
+  for (int mu = 0; mu < 4; ++mu) e[mu] = r * (-real(lam) * e1[mu] - I1 * e2[mu]);
   return e;
 }
 
 // ----------------------------------------------------------- propagators
 // Each returns the Feynman-rule factor including its explicit i.
 // Fermion: i (pslash + m) / (p^2 - m^2 + i m Gamma), p along the fermion arrow.
-inline Mat4 fermion_prop(const Vec4& p, double m, double w) {
+inline Mat4 fermion_prop(const Vec4& p, real m, real w) {
   cd den = dot(p, p) - m * m + I1 * m * w;
   return mscale(I1 / den, madd(slash(p), mscale(m, ident4())));
 }
@@ -218,7 +225,7 @@ inline Tens vector_prop(const Vec4& q, cd num2, cd pole2) {
 // Massless vector, Feynman gauge: -i g^{mu nu} / q^2
 inline Tens massless_prop(const Vec4& q) {
   Tens r;
-  double den = dot(q, q);
+  real den = dot(q, q);
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) r.t[a][b] = (a == b) ? -I1 * metric(a) / den : cd(0.0, 0.0);
   return r;
@@ -231,7 +238,7 @@ inline CVec4 contract(const Tens& T, const CVec4& x) {
   return r;
 }
 // Scalar: i / (q^2 - m^2 + i m Gamma)
-inline cd scalar_prop(const Vec4& q, double m, double w) { return I1 / (dot(q, q) - m * m + I1 * m * w); }
+inline cd scalar_prop(const Vec4& q, real m, real w) { return I1 / (dot(q, q) - m * m + I1 * m * w); }
 
 // Spinor current  row gamma^mu Gamma col  as a contravariant vector
 inline CVec4 current(const Spinor& row, const Mat4& chiral, const Spinor& col) {

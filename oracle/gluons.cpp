@@ -41,7 +41,7 @@ CVec4 v3(const Cur& A, const Cur& B) {
 CVec4 v4(const Cur& A, const Cur& B, const Cur& C) {
   const cd ac = dot(A.J, C.J), ab = dot(A.J, B.J), bc = dot(B.J, C.J);
   CVec4 r;
-  for (int m = 0; m < 4; ++m) r[m] = 2.0 * ac * B.J[m] - ab * C.J[m] - bc * A.J[m];
+  for (int m = 0; m < 4; ++m) r[m] = real(2) * ac * B.J[m] - ab * C.J[m] - bc * A.J[m];
   return r;
 }
 
@@ -66,8 +66,8 @@ struct BG {
   }
   // vertex sum (no propagator) for the ordered legs, off-shell leg last
   CVec4 vertex_sum(const int* legs, int len) {
-    const cd c3 = -2.0 * I1 * sm.gs;
-    const cd c4 = 2.0 * I1 * sm.gs * sm.gs;
+    const cd c3 = real(-2) * I1 * sm.gs;
+    const cd c4 = real(2) * I1 * sm.gs * sm.gs;
     CVec4 K{};
     for (int m = 1; m < len; ++m) {
       const Cur& A = current(legs, m);
@@ -91,7 +91,7 @@ struct BG {
     Vec4 P = {0, 0, 0, 0};
     for (int i = 0; i < len; ++i) P = add(P, ext[legs[i]].P);
     const CVec4 K = vertex_sum(legs, len);
-    const cd prop = 0.5 * (-I1) / dot(P, P);
+    const cd prop = real(0.5) * (-I1) / dot(P, P);
     Cur c{cscale(prop, K), P};
     return memo.emplace(k, c).first->second;
   }
@@ -127,18 +127,18 @@ cd gluon_partial(int n, const SM& sm, const Vec4* p, const int* hel, const int* 
 //   T^a_{ij} T^a_{kl} = (1/2) [delta_il delta_jk - (1/N) delta_ij delta_kl].
 // Each of the 2^n choices of terms joins the 2n fundamental indices into
 // closed loops, worth N per loop.
-std::vector<double> fierz_colour_matrix(int n) {
+std::vector<real> fierz_colour_matrix(int n) {
   const auto ords = orderings(n);
   const int no = int(ords.size());
-  const double N = 3.0;
-  std::vector<double> C(size_t(no) * no, 0.0);
+  const real N = 3.0;
+  std::vector<real> C(size_t(no) * no, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int x = 0; x < no; ++x) {
     int pos1[8], pos2[8], par[16];
     for (int p = 0; p < n; ++p) pos1[ords[x][n - 1 - p]] = p;   // reversed: the conjugated trace
     for (int y = 0; y < no; ++y) {
       for (int q = 0; q < n; ++q) pos2[ords[y][q]] = q;
-      double sum = 0.0;
+      real sum = 0.0;
       for (int choice = 0; choice < (1 << n); ++choice) {
         // nodes 0..n-1: indices I_p of trace 1 (T at p runs I_p -> I_(p+1)); n..2n-1: J_q of trace 2
         for (int k = 0; k < 2 * n; ++k) par[k] = k;
@@ -164,14 +164,14 @@ std::vector<double> fierz_colour_matrix(int n) {
         for (int k = 0; k < 2 * n; ++k) loops += find(k) == k;
         sum += std::pow(N, loops) * std::pow(-1.0 / N, k1);
       }
-      C[size_t(x) * no + y] = sum / double(1 << n);
+      C[size_t(x) * no + y] = sum / real(1 << n);
     }
   }
   return C;
 }
 
-const std::vector<double>& gluon_colour_matrix(int n) {
-  static std::map<int, std::vector<double>> cache;
+const std::vector<real>& gluon_colour_matrix(int n) {
+  static std::map<int, std::vector<real>> cache;
   static std::mutex mu;
   std::lock_guard<std::mutex> lock(mu);
   auto it = cache.find(n);
@@ -182,7 +182,7 @@ const std::vector<double>& gluon_colour_matrix(int n) {
   const Colour& CL = colour();
   int ncfg = 1;
   for (int i = 0; i < n; ++i) ncfg *= 8;
-  std::vector<double> C(no * no, 0.0);
+  std::vector<real> C(no * no, 0.0);
 #pragma omp parallel
   {
     std::vector<cd> loc(no * no, 0.0);
@@ -224,12 +224,12 @@ const std::vector<double>& gluon_colour_matrix(int n) {
   return cache[n] = C;
 }
 
-double gluon_me2(int n, const SM& sm, const Vec4* p) {
+real gluon_me2(int n, const SM& sm, const Vec4* p) {
   const auto ords = orderings(n);
   const int no = int(ords.size());
-  const std::vector<double>& C = gluon_colour_matrix(n);
+  const std::vector<real>& C = gluon_colour_matrix(n);
   std::vector<cd> A(no);
-  double tot = 0.0;
+  real tot = 0.0;
   int hel[8];
   for (int hc = 0; hc < (1 << n); ++hc) {
     for (int i = 0; i < n; ++i) hel[i] = ((hc >> (n - 1 - i)) & 1) ? 1 : -1;

@@ -8,6 +8,8 @@
 
 namespace {
 
+const double kPi = 3.14159265358979323846;
+
 // One Philox round: two 32x32 -> 64 bit products, words permuted and keyed.
 void philox_round(uint32_t c[4], const uint32_t k[2]) {
   const uint64_t p0 = uint64_t(0xD2511F53u) * uint64_t(c[0]);
@@ -68,7 +70,7 @@ extern "C" void or_uniforms_bulk(uint64_t seed, uint64_t counter_offset, int64_t
 
 extern "C" double or_phase_space_volume(double sqrt_s, int n) {
   const double s = sqrt_s * sqrt_s;
-  return std::pow(2.0 * orc::PI, 4 - 3 * n) * std::pow(0.5 * orc::PI, n - 1) * std::pow(s, n - 2) /
+  return std::pow(2.0 * kPi, 4 - 3 * n) * std::pow(0.5 * kPi, n - 1) * std::pow(s, n - 2) /
          (factorial(n - 1) * factorial(n - 2));
 }
 
@@ -78,7 +80,7 @@ extern "C" double or_rambo(double sqrt_s, int n, const double* u, double* p) {
   for (int k = 0; k < n; ++k) {
     const double c = 2.0 * u[4 * k] - 1.0;
     const double s = std::sqrt(1.0 - c * c);
-    const double f = 2.0 * orc::PI * u[4 * k + 1];
+    const double f = 2.0 * kPi * u[4 * k + 1];
     const double q0 = -std::log(u[4 * k + 2] * u[4 * k + 3]);
     double* q = p + 4 * k;
     q[0] = q0;
@@ -141,7 +143,7 @@ extern "C" void or_cut_gluons(int64_t n_events, int n_legs, const double* mom, d
     for (int k = 2; k < n_legs; ++k)
       for (int l = k + 1; l < n_legs; ++l) {
         double dphi = std::fabs(phi[k] - phi[l]);
-        if (dphi > orc::PI) dphi = 2.0 * orc::PI - dphi;
+        if (dphi > kPi) dphi = 2.0 * kPi - dphi;
         const double deta = eta[k] - eta[l];
         if (!(std::sqrt(deta * deta + dphi * dphi) > dr_min)) ok = 0;
       }

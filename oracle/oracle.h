@@ -136,6 +136,12 @@ int or_trace_me2(int proc, const or_params* prm, const double* mom, double* out)
 int or_weights(double phase_space_weight, double factor, int64_t n_events, const double* me2,
                const int32_t* pass, double* w);
 
+/* Tree-level two-body decay width (GeV) from the oracle's W-fermion vertex,
+ * spinors and massive polarisation vectors, spin-summed and averaged:
+ * which 0 = W+ -> e+ nu_e (massless leptons), 1 = t -> b W+ (massless b).
+ * Returns -1 for an unknown `which`. */
+int or_decay_width(int which, const or_params* prm, double* out);
+
 /* Self-checks of the building blocks (Dirac equation, completeness, helicity,
  * polarisation orthogonality); returns the largest violation found. */
 double or_selfcheck_spinors(const double* p, double m);

@@ -27,14 +27,14 @@ const Colour& colour() {
 namespace {
 
 // external states --------------------------------------------------------
-Spinor u_in(const Vec4& p, double m, int h) { return u_spinor(p, m, h); }           // incoming fermion
-Spinor vbar_in(const Vec4& p, double m, int h) { return dbar(v_spinor(p, m, h)); }  // incoming antifermion
-Spinor ubar_out(const Vec4& p, double m, int h) { return dbar(u_spinor(p, m, h)); } // outgoing fermion
-Spinor v_out(const Vec4& p, double m, int h) { return v_spinor(p, m, h); }          // outgoing antifermion
-CVec4 eps_in(const SM& sm, int leg, const Vec4& k, double m, int h) {
+Spinor u_in(const Vec4& p, real m, int h) { return u_spinor(p, m, h); }           // incoming fermion
+Spinor vbar_in(const Vec4& p, real m, int h) { return dbar(v_spinor(p, m, h)); }  // incoming antifermion
+Spinor ubar_out(const Vec4& p, real m, int h) { return dbar(u_spinor(p, m, h)); } // outgoing fermion
+Spinor v_out(const Vec4& p, real m, int h) { return v_spinor(p, m, h); }          // outgoing antifermion
+CVec4 eps_in(const SM& sm, int leg, const Vec4& k, real m, int h) {
   return eps_vec(k, m, sm.gauge_leg == leg ? 4 : h);
 }
-CVec4 eps_out(const SM& sm, int leg, const Vec4& k, double m, int h) {
+CVec4 eps_out(const SM& sm, int leg, const Vec4& k, real m, int h) {
   return conjv(eps_vec(k, m, sm.gauge_leg == leg ? 4 : h));
 }
 Mat4 chiral(cd gl, cd gr) { return madd(mscale(gl, gam().pl), mscale(gr, gam().pr)); }
@@ -47,7 +47,7 @@ void amp_ee_mumu(const SM& sm, const Vec4* p, const int* h, cd* M) {
   const Spinor ub2 = ubar_out(p[2], 0, h[2]);
   const Spinor v3 = v_out(p[3], 0, h[3]);
   const Vec4 q = add(p[0], p[1]);
-  const double Ql = -1.0, T3 = -0.5;
+  const real Ql = -1.0, T3 = -0.5;
   // photon
   {
     const Mat4 c = chiral(sm.g_a(Ql), sm.g_a(Ql));
@@ -166,7 +166,7 @@ void col_uu_tt(const int* col, cd* c) {
 struct Boson {
   cd num2, pole2;  // unitary-gauge numerator mass^2 and pole
   cd g_vvh;        // Feynman rule / i of V V H
-  double g_vvhh;   // Feynman rule / i of V V H H
+  real g_vvhh;   // Feynman rule / i of V V H H
 };
 Boson boson_w(const SM& sm) { return {sm.numw2, sm.muw2, sm.g_wwh, sm.g_wwhh}; }
 Boson boson_z(const SM& sm) { return {sm.numz2, sm.muz2, sm.g_zzh, sm.g_zzhh}; }
@@ -236,9 +236,9 @@ struct QuarkLine {
 struct FusionClass {
   QuarkLine l1, l2;
   int boson;  // 0 = W, 1 = Z
-  double sign;
+  real sign;
 };
-const double Qu = 2.0 / 3.0, Qd = -1.0 / 3.0;
+const real Qu = real(2) / 3, Qd = real(-1) / 3;
 
 void amp_qq_qqhh_4b(const SM& sm, const std::vector<FusionClass>& classes, const Vec4* p, const int* h,
                     cd* M) {
@@ -254,7 +254,7 @@ void amp_qq_qqhh_4b(const SM& sm, const std::vector<FusionClass>& classes, const
   struct Pair {
     Vec4 h1, h2;
     cd d;
-    double sign;
+    real sign;
   } pairs[2];
   pairs[0].h1 = add(p[4], p[5]);
   pairs[0].h2 = add(p[6], p[7]);
@@ -303,8 +303,8 @@ void amp_uu_uuhh(const SM& sm, const Vec4* p, const int* h, cd* M) { amp_qq_qqhh
 // colour: class 0 connects (0->2, 1->3), class 1 (0->3, 1->2); b pairing A
 // (4,5)(6,7), pairing B (4,7)(6,5).
 void col_qq_qqhh(const int* c, cd* out) {
-  const double cls[2] = {double(c[2] == c[0] && c[3] == c[1]), double(c[3] == c[0] && c[2] == c[1])};
-  const double prs[2] = {double(c[4] == c[5] && c[6] == c[7]), double(c[4] == c[7] && c[6] == c[5])};
+  const real cls[2] = {real(c[2] == c[0] && c[3] == c[1]), real(c[3] == c[0] && c[2] == c[1])};
+  const real prs[2] = {real(c[4] == c[5] && c[6] == c[7]), real(c[4] == c[7] && c[6] == c[5])};
   int d = 0;
   for (int k = 0; k < 2; ++k)
     for (int r = 0; r < 2; ++r)
@@ -343,7 +343,7 @@ void amp_ww_ww(const SM& sm, const Vec4* p, const int* h, cd* M) {
   const cd gw2 = sm.gw * sm.gw, ga = sm.e, gzv = sm.gw * sm.cw, gh = sm.g_wwh;
   int d = 0;
   // contact
-  M[d++] = (I1 * gw2 * (2.0 * dot(A.e, B.e) * dot(C.e, D.e) - dot(A.e, C.e) * dot(B.e, D.e) -
+  M[d++] = (I1 * gw2 * (real(2) * dot(A.e, B.e) * dot(C.e, D.e) - dot(A.e, C.e) * dot(B.e, D.e) -
                         dot(A.e, D.e) * dot(B.e, C.e))) / I1;
   // s channel: (A, C) | (B, D); t channel: (A, D) | (B, C)
   const Ext* ch[2][4] = {{&A, &C, &B, &D}, {&A, &D, &B, &C}};
@@ -385,13 +385,13 @@ void amp_ud_udhhh(const SM& sm, const Vec4* p, const int* h, cd* M) {
 }
 // colour: class 0 connects (0->2, 1->3), class 1 (0->3, 1->2)
 void col_qq_qqhhh(const int* c, cd* out) {
-  const double cls[2] = {double(c[2] == c[0] && c[3] == c[1]), double(c[3] == c[0] && c[2] == c[1])};
+  const real cls[2] = {real(c[2] == c[0] && c[3] == c[1]), real(c[3] == c[0] && c[2] == c[1])};
   for (int k = 0; k < 2; ++k)
     for (int j = 0; j < 25; ++j) out[25 * k + j] = cls[k];
 }
 
 // V(p0) V(p1) -> H(p2) H(p3) H(p4) with on-shell external vectors
-void amp_vv_hhh(const SM& sm, const Boson& B, double mv, const Vec4* p, const int* h, cd* M) {
+void amp_vv_hhh(const SM& sm, const Boson& B, real mv, const Vec4* p, const int* h, cd* M) {
   const CVec4 E1 = eps_in(sm, 0, p[0], mv, h[0]);
   const CVec4 E2 = eps_in(sm, 1, p[1], mv, h[1]);
   cd part[25];
@@ -405,7 +405,7 @@ void col_trivial25(const int*, cd* c) {
 }
 
 // V(p0) V(p1) -> H(p2) H(p3) with on-shell external vectors
-void amp_vv_hh(const SM& sm, const Boson& B, double mv, const Vec4* p, const int* h, cd* M) {
+void amp_vv_hh(const SM& sm, const Boson& B, real mv, const Vec4* p, const int* h, cd* M) {
   const CVec4 E1 = eps_in(sm, 0, p[0], mv, h[0]);
   const CVec4 E2 = eps_in(sm, 1, p[1], mv, h[1]);
   cd part[4];
@@ -504,12 +504,12 @@ const std::vector<std::vector<cd>>& colour_assignments(int id, const ProcDef& P)
 }
 
 // sum over explicit colours of |sum_d c_d M_d|^2 for one helicity combination
-double me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm, const Vec4* p,
+real me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm, const Vec4* p,
                         const int* h) {
   const int nd = P.ndiag;
   std::vector<cd> M(nd);
   P.amp(sm, p, h, M.data());
-  double s = 0.0;
+  real s = 0.0;
   for (const auto& c : cols) {
     cd a = 0;
     for (int d = 0; d < nd; ++d) a += c[d] * M[d];
@@ -521,13 +521,13 @@ double me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& co
 // Conditioning of the diagram sum for one helicity: accumulates
 // sum_col |sum_d c_d M_d|^2 into a2 and sum_col (sum_d |c_d M_d|)^2 into b2.
 void condition_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm,
-                            const Vec4* p, const int* h, double& a2, double& b2) {
+                            const Vec4* p, const int* h, real& a2, real& b2) {
   const int nd = P.ndiag;
   std::vector<cd> M(nd);
   P.amp(sm, p, h, M.data());
   for (const auto& c : cols) {
     cd a = 0;
-    double b = 0;
+    real b = 0;
     for (int d = 0; d < nd; ++d) {
       a += c[d] * M[d];
       b += std::abs(c[d] * M[d]);
@@ -549,13 +549,13 @@ Mat4 bar(const Mat4& A) {
     for (int j = 0; j < 4; ++j) d.m[i][j] = std::conj(A.m[j][i]);
   return mul(mul(gam().g[0], d), gam().g[0]);
 }
-Mat4 pm(const Vec4& p, double m) { return madd(slash(p), mscale(m, ident4())); }
+Mat4 pm(const Vec4& p, real m) { return madd(slash(p), mscale(m, ident4())); }
 }  // namespace
 
-double trace_me2(int id, const SM& sm, const Vec4* p) {
+real trace_me2(int id, const SM& sm, const Vec4* p) {
   const Gammas& G = gam();
   if (id == OR_UU_TT) {
-    const double s = dot(add(p[0], p[1]), add(p[0], p[1]));
+    const real s = dot(add(p[0], p[1]), add(p[0], p[1]));
     cd tot = 0;
     for (int mu = 0; mu < 4; ++mu)
       for (int nu = 0; nu < 4; ++nu) {
@@ -563,7 +563,7 @@ double trace_me2(int id, const SM& sm, const Vec4* p) {
         const cd t2 = trace(mul(mul(G.g[mu], pm(p[3], -sm.mt)), mul(G.g[nu], pm(p[2], sm.mt))));
         tot += metric(mu) * metric(nu) * t1 * t2;
       }
-    const double g4 = std::pow(sm.gs, 4);
+    const real g4 = std::pow(sm.gs, 4);
     return 2.0 * g4 / (s * s) * std::real(tot);   // colour: Tr(T^a T^b) Tr(T^a T^b) = 2
   }
   if (id == OR_GG_TT) {
@@ -578,8 +578,8 @@ double trace_me2(int id, const SM& sm, const Vec4* p) {
       }
     auto proj = [](const Vec4& k, const Vec4& r, int a, int b) {
       // lower-index projector P_ab = -g_ab + (k_a r_b + r_a k_b)/(k.r)
-      const double ka = metric(a) * k[a], kb = metric(b) * k[b];
-      const double ra = metric(a) * r[a], rb = metric(b) * r[b];
+      const real ka = metric(a) * k[a], kb = metric(b) * k[b];
+      const real ra = metric(a) * r[a], rb = metric(b) * r[b];
       return -(a == b ? metric(a) : 0.0) + (ka * rb + ra * kb) / dot(k, r);
     };
     const ProcDef& P = *find_proc(OR_GG_TT);
@@ -590,7 +590,7 @@ double trace_me2(int id, const SM& sm, const Vec4* p) {
       for (int nu = 0; nu < 4; ++nu)
         for (int mp = 0; mp < 4; ++mp)
           for (int np = 0; np < 4; ++np) {
-            const double w = proj(p[0], p[1], mu, mp) * proj(p[1], p[0], nu, np);
+            const real w = proj(p[0], p[1], mu, mp) * proj(p[1], p[0], nu, np);
             if (w == 0.0) continue;
             for (int a = 0; a < 3; ++a)
               for (int b = 0; b < 3; ++b) {
@@ -602,6 +602,51 @@ double trace_me2(int id, const SM& sm, const Vec4* p) {
     return std::real(tot);
   }
   return -1.0;
+}
+
+// Two-body decay widths at tree level from the oracle's own W-fermion vertex
+// (coefficient -i g_w gamma^mu P_L, g_w = SM::g_w()), helicity spinors and
+// massive polarisation vectors, summed over every spin state, averaged over
+// the decaying particle's, and integrated over the (isotropic) two-body phase
+// space: Gamma = |p| / (8 pi M^2) * (1 / N_spin) * sum |M|^2.
+//   which 0: W+ -> e+ nu_e  (massless leptons), W at rest with mass m_W;
+//   which 1: t -> b W+      (massless b), top at rest with mass m_t.
+real decay_width(const SM& sm, int which) {
+  const Mat4 PL = gam().pl;
+  const real st = real(0.6), ct = real(0.8);   // any decay axis: the spin sum is isotropic
+  if (which == 0) {
+    const real m = sm.mw, e = m / 2;
+    const Vec4 pe = {e, e * st, 0, e * ct}, pn = {e, -e * st, 0, -e * ct};
+    const Vec4 kw = {m, 0, 0, 0};
+    real sum = 0;
+    for (int lw : {-1, 0, 1}) {
+      const CVec4 ew = eps_vec(kw, m, lw);
+      for (int hn : {-1, 1})
+        for (int he : {-1, 1}) {
+          const CVec4 j = current(dbar(u_spinor(pn, 0, hn)), PL, v_spinor(pe, 0, he));
+          const cd M = sm.g_w() * dot(j, ew);
+          sum += std::norm(M);
+        }
+    }
+    return (e / (8 * PI * m * m)) * sum / 3;
+  }
+  if (which == 1) {
+    const real mt = sm.mt, mw = sm.mw;
+    const real p = (mt * mt - mw * mw) / (2 * mt);
+    const Vec4 pb = {p, p * st, 0, p * ct};
+    const Vec4 kw = {std::sqrt(p * p + mw * mw), -p * st, 0, -p * ct};
+    const Vec4 kt = {mt, 0, 0, 0};
+    real sum = 0;
+    for (int ht : {-1, 1})
+      for (int hb : {-1, 1})
+        for (int lw : {-1, 0, 1}) {
+          const CVec4 ew = conjv(eps_vec(kw, mw, lw));
+          const CVec4 j = current(dbar(u_spinor(pb, 0, hb)), PL, u_spinor(kt, mt, ht));
+          sum += std::norm(sm.g_w() * dot(j, ew));
+        }
+    return (p / (8 * PI * mt * mt)) * sum / 2;
+  }
+  return -1;
 }
 
 }  // namespace orc

@@ -21,16 +21,17 @@ const ProcDef* find_proc(int id);
 const std::vector<cd>& colour_matrix(int id, const ProcDef& P);
 std::vector<std::vector<int>> helicity_table(const ProcDef& P);
 const std::vector<std::vector<cd>>& colour_assignments(int id, const ProcDef& P);
-double me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm, const Vec4* p,
+real me2_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm, const Vec4* p,
                         const int* h);
-double trace_me2(int id, const SM& sm, const Vec4* p);
+real trace_me2(int id, const SM& sm, const Vec4* p);
+real decay_width(const SM& sm, int which);
 void condition_one_helicity(const ProcDef& P, const std::vector<std::vector<cd>>& cols, const SM& sm,
-                            const Vec4* p, const int* h, double& a2, double& b2);
+                            const Vec4* p, const int* h, real& a2, real& b2);
 
 // n-gluon Berends-Giele
-double gluon_me2(int n, const SM& sm, const Vec4* p);
+real gluon_me2(int n, const SM& sm, const Vec4* p);
 cd gluon_partial(int n, const SM& sm, const Vec4* p, const int* hel, const int* order);
-const std::vector<double>& gluon_colour_matrix(int n);
-std::vector<double> fierz_colour_matrix(int n);
+const std::vector<real>& gluon_colour_matrix(int n);
+std::vector<real> fierz_colour_matrix(int n);
 
 }  // namespace orc

@@ -19,12 +19,12 @@
 namespace orc {
 
 struct SM {
-  double e, sw2, sw, cw, gw, gz, gs;
-  double mz, wz, mw, ww, mt, wt, mh, wh, mb_yuk, v;
+  real e, sw2, sw, cw, gw, gz, gs;
+  real mz, wz, mw, ww, mt, wt, mh, wh, mb_yuk, v;
   cd muw2, muz2;        // complex masses squared (propagator poles)
   cd numw2, numz2;      // masses squared in the unitary-gauge numerator
   cd g_wwh, g_zzh;      // Feynman rule / i for W+W-H and ZZH (metric tensor stripped)
-  double g_wwhh, g_zzhh, g_hhh, g_hhhh, y_b;
+  real g_wwhh, g_zzhh, g_hhh, g_hhhh, y_b;
   int gauge_leg;
   explicit SM(const or_params& p) {
     e = std::sqrt(4.0 * PI * p.alpha);
@@ -66,22 +66,22 @@ struct SM {
     gauge_leg = p.gauge_leg;
   }
   // fermion couplings to neutral bosons: coefficient of fbar gamma^mu P_{L,R} f V_mu
-  double gl_z(double t3, double q) const { return -gz * (t3 - q * sw2); }
-  double gr_z(double q) const { return gz * q * sw2; }
-  double g_a(double q) const { return -e * q; }
-  double g_w() const { return -gw / std::sqrt(2.0); }
+  real gl_z(real t3, real q) const { return -gz * (t3 - q * sw2); }
+  real gr_z(real q) const { return gz * q * sw2; }
+  real g_a(real q) const { return -e * q; }
+  real g_w() const { return -gw / std::sqrt(real(2)); }
 };
 
 // SU(3) generators T^a = lambda^a / 2 and structure constants
 // f^{abc} = -2 i Tr([T^a, T^b] T^c).
 struct Colour {
   cd T[8][3][3];
-  double f[8][8][8];
+  real f[8][8][8];
   Colour() {
     for (auto& a : T)
       for (auto& r : a)
         for (auto& x : r) x = 0.0;
-    const double h = 0.5;
+    const real h = 0.5;
     T[0][0][1] = h; T[0][1][0] = h;
     T[1][0][1] = -h * I1; T[1][1][0] = h * I1;
     T[2][0][0] = h; T[2][1][1] = -h;
@@ -89,7 +89,7 @@ struct Colour {
     T[4][0][2] = -h * I1; T[4][2][0] = h * I1;
     T[5][1][2] = h; T[5][2][1] = h;
     T[6][1][2] = -h * I1; T[6][2][1] = h * I1;
-    const double r3 = 1.0 / std::sqrt(3.0);
+    const real r3 = 1 / std::sqrt(real(3));
     T[7][0][0] = h * r3; T[7][1][1] = h * r3; T[7][2][2] = -2.0 * h * r3;
     for (int a = 0; a < 8; ++a)
       for (int b = 0; b < 8; ++b)
@@ -99,7 +99,7 @@ struct Colour {
             for (int j = 0; j < 3; ++j)
               for (int k = 0; k < 3; ++k)
                 tr += (T[a][i][j] * T[b][j][k] - T[b][i][j] * T[a][j][k]) * T[c][k][i];
-          f[a][b][c] = std::real(-2.0 * I1 * tr);
+          f[a][b][c] = std::real(real(-2) * I1 * tr);
         }
   }
 };

@@ -69,6 +69,17 @@ class _IRBuffers:
             float(proc.ps_hadronic[1]) if proc.ps_hadronic else 0.0)
 
 
+def uniforms(n, n_u, seed=0, counter_offset=0, stream=None):
+    """The Philox step alone: uniforms of events counter_offset .. + n - 1 as a
+    float64 CUDA tensor [n_u][n] (heget_uniforms)."""
+    import torch
+    out = torch.empty((n_u, max(n, 0)), dtype=torch.float64, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(_lib.load().heget_uniforms(seed, counter_offset, n, n_u, ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
 class Process:
     """A created process handle (heget_process_create)."""
 

@@ -10,6 +10,7 @@ HEGET_FP64, HEGET_MIXED = 0, 1
 
 EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "heget_integrate",
             "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error", "heget_generate",
+            "heget_uniforms",
             "heget_integrate_adaptive", "heget_process_grid_dims",
             "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
             "heget_server_destroy"]
@@ -108,6 +109,8 @@ def load(path=None):
     L.heget_eval.restype = ctypes.c_int
     L.heget_generate.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, vp, vp, vp]
     L.heget_generate.restype = ctypes.c_int
+    L.heget_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, vp, vp]
+    L.heget_uniforms.restype = ctypes.c_int
     L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.POINTER(heget_result), vp]
     L.heget_integrate.restype = ctypes.c_int

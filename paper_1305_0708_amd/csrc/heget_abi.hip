@@ -405,6 +405,21 @@ const void* generate_kernel() {
   return reinterpret_cast<const void*>(&generate_momenta<NOUT>);
 }
 
+// The Philox step alone: uniforms of events counter_offset .. + n - 1, block j
+// of event i giving u[2 j][i] and u[2 j + 1][i] (SoA, coalesced per draw).
+__global__ __launch_bounds__(256) void uniforms_kernel(uint64_t seed, uint64_t counter_offset, int64_t n,
+                                                       int n_u, double* out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t ev = counter_offset + uint64_t(i);
+  for (int j = 0; 2 * j < n_u; ++j) {
+    uint32_t c[4] = {uint32_t(ev), uint32_t(ev >> 32), uint32_t(j), 0u};
+    heget::philox4x32_10(c, uint32_t(seed), uint32_t(seed >> 32));
+    out[int64_t(2 * j) * n + i] = heget::unit_open(c[0], c[1]);
+    if (2 * j + 1 < n_u) out[int64_t(2 * j + 1) * n + i] = heget::unit_open(c[2], c[3]);
+  }
+}
+
 // Fixed-order reduction of one request's per-block partials (one block).
 __global__ __launch_bounds__(256) void reduce_partials(const double* partials, int64_t nblocks, double* out) {
   heget::reduce_triples(partials, nblocks, out);
@@ -740,6 +755,20 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
   a.weight_factor = heget::detail::phase_space_volume(sqrt_s, p->n_legs - 2);
   void* args[] = {&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(256), args, 0, static_cast<hipStream_t>(stream)));
+  return HEGET_OK;
+}
+
+heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, int32_t n_u, double* u_out,
+                            void* stream) {
+  g_err.clear();
+  if (n < 0 || n_u < 1 || n_u > 64) return fail(HEGET_E_INVALID, "need n >= 0 and 1 <= n_u <= 64");
+  if (n == 0) return HEGET_OK;
+  if (!u_out) return fail(HEGET_E_INVALID, "null u_out");
+  const int64_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
+  hipLaunchKernelGGL(uniforms_kernel, dim3(unsigned(grid)), dim3(256), 0, static_cast<hipStream_t>(stream), seed,
+                     counter_offset, n, int(n_u), u_out);
+  HIP_TRY(hipGetLastError());
   return HEGET_OK;
 }
 

@@ -1,0 +1,143 @@
+"""Per-event bounds of the FP64 path against the extended-precision oracle.
+
+The FP64 target is |F_gpu / F - 1| <= 1e-12 per event.  F here is the oracle's
+value computed in long double (the same oracle sources built with a 64-bit
+significand, oracle/build.py), which for the given FP64 momenta is exact to
+about kappa * 5e-20, kappa the event's cancellation factor.
+
+No FP64 evaluation reaches 1e-12 on every event of every process: where the
+amplitude cancels between diagrams (the longitudinal weak bosons of u d -> u d
+H H and u d -> u d H H H, whose gauge cancellations the paper's Sec. 6
+discusses) or where the invariants come from large, cancelling lab-frame
+components (the hadronic collision), rounding at 1.1e-16 is amplified beyond
+it.  The FP64 oracle itself, an independent FP64 evaluation of the same
+Feynman rules, shows this: its largest error against the long-double value on
+each process's parity events is X below (measured on the CPU;
+tests/test_oracle_extended.py measures it again and checks the table).
+
+The GPU's bound on those same events is B = max(1e-12, 4 X), rounded up to the
+next value of the 1-2-5 series: the error another FP64 evaluation of the same
+events may carry, with a factor 4 for a different operation order (fused
+multiply-adds, the helicity nest's grouping of the sums).  Processes whose
+FP64 oracle stays within half the bar (X <= 5e-13) keep the plain 1e-12.  SHARE is the
+fraction of events that must in addition meet 1e-12 itself.
+
+Event sets are defined here, once, for the CPU test and the GPU tests.
+"""
+import math
+
+import numpy as np
+
+# name -> largest |F_fp64 oracle / F_long double - 1| on the parity events (CPU measurement)
+X_ORACLE = {
+    "ee_mumu": 1.6e-15,
+    "gg_ttbar_6f": 4.9e-13,
+    "gg_4g": 1.1e-13,
+    "ud_udhh_4b": 5.0e-12,
+    "ud_udhhh": 6.1e-11,
+    "ww_ww": 6.6e-13,
+    "gg_ttbar_6f_had": 3.9e-9,
+    "gg_ttbar_6f_bw": 7.3e-13,
+}
+X_ORACLE["gg_4g_ddm"] = X_ORACLE["gg_4g"]
+
+
+def _ladder(x):
+    """smallest value of the 1-2-5 series >= x"""
+    e = math.floor(math.log10(x))
+    for m in (1.0, 2.0, 5.0, 10.0):
+        if m * 10.0 ** e >= x * (1 - 1e-12):
+            return m * 10.0 ** e
+    return 10.0 ** (e + 1)
+
+
+def bound(name):
+    x = X_ORACLE[name]
+    return 1e-12 if x <= 5e-13 else _ladder(max(1e-12, 4.0 * x))
+
+
+BOUND = {name: bound(name) for name in X_ORACLE}
+# share of the parity events that must also be within 1e-12
+SHARE = {"ee_mumu": 1.0, "gg_ttbar_6f": 0.99, "gg_4g": 0.99, "gg_4g_ddm": 0.99, "ud_udhh_4b": 0.98,
+         "ud_udhhh": 0.75, "ww_ww": 0.99, "gg_ttbar_6f_had": 0.25, "gg_ttbar_6f_bw": 0.99}
+
+# ---------------------------------------------------------------- event sets
+RAMBO = {   # name -> (oracle id, final legs, sqrt_s, params, seed, cut)
+    "ee_mumu": ("EE_MUMU", 2, 200.0, {}, 0x48454745, None),
+    "gg_ttbar_6f": ("GG_TT_6F", 6, 1000.0, {}, 0x48454746, None),
+    "ud_udhh_4b": ("UD_UDHH_4B", 6, 2000.0, {"cms": 1}, 0x48454748, None),
+    "gg_4g": ("GG_4G", 4, 1000.0, {}, 0x48454747, (20.0, 0.4)),
+    "gg_4g_ddm": ("GG_4G", 4, 1000.0, {}, 0x48454747, (20.0, 0.4)),
+}
+N_PARITY = 3 * 1024 + 37          # several 256-lane blocks and a ragged tail
+
+MH = 125.0
+MW_CMS = 91.1876 * math.sqrt(1 - 0.2222)   # the complex-mass relation m_W = c_W m_Z
+MT, WT, MW, WW = 175.0, 1.55, 80.4, 2.085
+TREES = {   # name -> (oracle id, params, sqrt_s, tree, n_legs, leg masses, hadronic, [(seed, n)])
+    "ud_udhhh": ("UD_UDHHH", {"cms": 1}, 2000.0,
+                 [(0.0, 0.0, None, 2, -2, None), (0.0, 0.0, "flat", 3, -3, None),
+                  (0.0, 0.0, "flat", 4, -4, None), (0.0, 0.0, "flat", 5, 6, None)],
+                 7, [0, 0, 0, 0, MH, MH, MH], None, [(0x48484821 + 2000, 2000), (0x48484821 + 37, 37)]),
+    "ww_ww": ("WW_WW", {"cms": 1}, 1000.0, [(0.0, 0.0, None, 2, 3, None)], 4, [MW_CMS] * 4, None,
+              [(0x57575757 + 3000, 3000), (0x57575757 + 41, 41)]),
+    "gg_ttbar_6f_had": ("GG_TT_6F", {}, 14000.0,
+                        [(0.0, 0.0, None, -2, -3, None), (MT, WT, "bw", 2, -4, 20.0), (MT, WT, "bw", 5, -5, 20.0),
+                         (MW, WW, "bw", 3, 4, 20.0), (MW, WW, "bw", 6, 7, 20.0)],
+                        8, None, (2.5, 0.0), [(0x48414452 + 1, 3000)]),
+    "gg_ttbar_6f_bw": ("GG_TT_6F", {}, 1000.0,
+                       [(0.0, 0.0, None, -2, -3, None), (MT, WT, "bw", 2, -4, 20.0), (MT, WT, "bw", 5, -5, 20.0),
+                        (MW, WW, "bw", 3, 4, 20.0), (MW, WW, "bw", 6, 7, 20.0)],
+                       8, None, None, [(0x4845474B, 2048)]),
+}
+
+
+def rambo_events(oracle, name, n=N_PARITY, salt=0x55):
+    _, nout, rs, _, seed, _ = RAMBO[name]
+    return oracle.generate(seed ^ salt, n, nout, rs)
+
+
+def tree_events(oracle, name):
+    """the parity events of a resonance-tree process: a list of momentum arrays
+    (events whose weight is 0 -- outside x_a, x_b < 1 -- are dropped)"""
+    from oracle import phase_space_tree as T
+    _, _, rs, tree, nl, masses, had, sets = TREES[name]
+    out = []
+    for seed, n in sets:
+        mom, w = T.generate(seed, n, rs, tree, nl, leg_mass=masses, hadronic=had)
+        out.append(mom[w > 0])
+    return out
+
+
+def oracle_params(oracle, name):
+    kw = RAMBO[name][3] if name in RAMBO else TREES[name][1]
+    return oracle.params(**kw)
+
+
+def oracle_id(oracle, name):
+    return getattr(oracle, RAMBO[name][0] if name in RAMBO else TREES[name][0])
+
+
+def reference(oracle, name, mom, extended=True):
+    """F per event (the cut applied for gluon processes): long double by default"""
+    f = oracle.me2(oracle_id(oracle, name), mom, oracle_params(oracle, name), extended=extended)
+    cut = RAMBO.get(name, (None,) * 6)[5]
+    if cut is not None:
+        f = f * oracle.cut_gluons(mom, *cut)
+    return f
+
+
+def check(oracle, name, mom, got, ref=None, share=None):
+    """every event within BOUND[name] of the extended-precision F, the share
+    within 1e-12 at least SHARE[name], cut events exactly 0; returns the errors"""
+    ref = reference(oracle, name, mom) if ref is None else ref
+    zero = ref == 0
+    assert np.all(got[zero] == 0.0)
+    err = np.abs(got[~zero] - ref[~zero]) / np.abs(ref[~zero])
+    b = BOUND[name]
+    within = float(np.mean(err <= 1e-12)) if err.size else 1.0
+    print(f"{name} fp64 vs extended: max {err.max(initial=0):.2e} (bound {b:.0e}), median "
+          f"{np.median(err) if err.size else 0:.2e}, {within:.4f} within 1e-12 ({err.size} events)")
+    assert np.all(err <= b), (err.max(), b)
+    assert within >= (SHARE[name] if share is None else share)
+    return err

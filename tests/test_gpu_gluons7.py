@@ -38,14 +38,6 @@ def to_aos(t):
     return np.ascontiguousarray(np.transpose(t.cpu().numpy(), (2, 0, 1)))
 
 
-def rotated(mom, seed):
-    rng = np.random.default_rng(seed)
-    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
-    out = mom.copy()
-    out[..., 1:] = mom[..., 1:] @ q.T
-    return out
-
-
 N_REF = 300        # two blocks of 256 lanes, the second ragged
 
 
@@ -60,25 +52,18 @@ def reference(oracle):
 @pytest.mark.parametrize("n", [N_REF, 45])
 def test_me2_matches_oracle(torch, oracle, proc, reference, n):
     """the kernel's own events (RAMBO, generation cut; two blocks with a ragged
-    tail, and 45 events in one ragged block): |F_gpu/F_oracle - 1| <= 1e-12, or
-    16 nu where the event's own FP64 floor nu (the rotation spread of the
-    oracle's F) is larger; cut events are exactly 0 on both sides"""
+    tail, and 45 events in one ragged block): |F_gpu/F_oracle - 1| <= 1e-12 on
+    every event against the FP64 oracle (its long-double build is too slow for
+    seven gluons, about 15 s per event); cut events are exactly 0 on both sides"""
     me2, mom = proc.eval(n=n, seed=SEED, sqrt_s=ROOTS, want_momenta=True)
     me2 = me2.cpu().numpy()
     ref_mom, ref = reference[0][:n], reference[1][:n]
     assert np.abs(to_aos(mom) - ref_mom).max() < 1e-13 * ROOTS
     zero = ref == 0
     assert np.all(me2[zero] == 0.0)
-    got, ref, mom = me2[~zero], ref[~zero], ref_mom[~zero]
-    err = np.abs(got - ref) / np.abs(ref)
-    bad = err > 1e-12
-    nu = np.zeros(bad.sum())
-    for s in range(8):
-        nu = np.maximum(nu, np.abs(oracle.me2(oracle.GG_5G, rotated(mom[bad], s)) / ref[bad] - 1))
-    print(f"gg->5g FP64 n={n}: {zero.sum()} cut, max rel err {err.max():.2e}, median {np.median(err):.2e}, "
-          f"{bad.sum()} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
-    assert np.all(err[bad] <= 16 * nu)
-    assert bad.mean() < 0.05
+    err = np.abs(me2[~zero] - ref[~zero]) / np.abs(ref[~zero])
+    print(f"gg->5g FP64 n={n}: {zero.sum()} cut, max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() <= 1e-12
 
 
 def test_integrate_matches_its_events(torch, oracle, proc, reference):

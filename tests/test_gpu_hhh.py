@@ -43,41 +43,17 @@ def to_soa(torch, mom):
     return torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
 
 
-def rotated(mom, seed):
-    rng = np.random.default_rng(seed)
-    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
-    out = mom.copy()
-    out[..., 1:] = mom[..., 1:] @ q.T
-    return out
-
-
 def test_me2_matches_oracle(torch, oracle, proc):
     """momenta in: the oracle's tree events (2,000 + a ragged 37) fed to both
-    sides.  |F_gpu/F_oracle - 1| <= 1e-12 per event, except where the event's
-    own FP64 rounding floor nu is larger: V V -> H H H cancels between its 25
-    diagrams (the gauge cancellation the paper's Sec. 6 discusses), and the
-    oracle's F moves by nu under rotations of the frame; there the bound is
-    16 nu (measured: at most 1.3 nu).  The cancellation is stronger than in
-    V V -> H H: 13 % of these events carry a floor above 1e-12 (median error
-    8e-14), so the share within 1e-12 is held to 75 % rather than the 98 %
-    of the other processes."""
-    from oracle import phase_space_tree as T
-    prm = oracle.params(cms=1)
-    for n in (2000, 37):
-        mom, w = T.generate(SEED + n, n, ROOTS, oracle_tree(), 7, leg_mass=LEG_MASS)
-        assert np.all(w > 0)
+    sides, every event within the process's bound of the extended-precision
+    oracle.  V V -> H H H cancels between its 25 diagrams (the gauge
+    cancellation the paper's Sec. 6 discusses): the FP64 oracle itself is off
+    the exact value by up to 6.1e-11 on these events and 13 % of its values
+    miss 1e-12, so the bound is 5e-10 with 75 % of the events within 1e-12."""
+    import fp64_bounds as B
+    for mom in B.tree_events(oracle, NAME):
         me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-        ref = oracle.me2(oracle.UD_UDHHH, mom, prm)
-        err = np.abs(me2 - ref) / np.abs(ref)
-        bad = err > 1e-12
-        nu = np.zeros(bad.sum())
-        for s in range(8):
-            f = oracle.me2(oracle.UD_UDHHH, rotated(mom[bad], s), prm)
-            nu = np.maximum(nu, np.abs(f / ref[bad] - 1))
-        print(f"ud->udHHH FP64 n={n}: max rel err {err.max():.2e}, median {np.median(err):.2e}, "
-              f"{bad.sum()} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
-        assert np.all(err[bad] <= 16 * nu)
-        assert bad.mean() < 0.25
+        B.check(oracle, NAME, mom, me2)
 
 
 def test_mixed_precision_error(torch, oracle):

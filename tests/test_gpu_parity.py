@@ -1,7 +1,11 @@
-"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+"""GPU parity of the HIP path against the oracle, through the C ABI.
 
-FP64 path: |F_gpu - F_oracle| / F_oracle <= 1e-12 per event (the stated
-tolerance).  Mixed path: max and median relative error are reported; the test
+FP64 path: every event within the per-process bound of fp64_bounds.py of the
+oracle's extended-precision (long double) F -- 1e-12 for the configured
+workloads C0, C1 and C2, and for u d -> u d H H (C3), whose gauge cancellations
+already take an independent FP64 evaluation (the FP64 oracle) to 4.9e-12 of
+the exact value, 2e-11 with 98 % of the events within 1e-12.  Mixed path: max
+and median relative error against the same reference are reported; the test
 only guards against gross failure (max < 1e-2).  Sizes: a few thousand events
 (several 256-lane blocks plus a ragged tail) compared element by element, and
 the full workload sizes in the benchmark's launch configuration compared on
@@ -11,6 +15,8 @@ import math
 
 import numpy as np
 import pytest
+
+import fp64_bounds as B
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +56,9 @@ def make(name, precision="fp64"):
     return H.Process(processes.by_name(name), precision=precision)
 
 
-def oracle_me2(oracle, name, mom, cut=True):
+def oracle_me2(oracle, name, mom, cut=True, extended=False):
     pid, _, _, kw, _, _ = CASES[name]
-    f = oracle.me2(getattr(oracle, pid), mom, oracle.params(**kw))
+    f = oracle.me2(getattr(oracle, pid), mom, oracle.params(**kw), extended=extended)
     if cut and name in CUT:
         f = f * oracle.cut_gluons(mom, *CUT[name])
     return f
@@ -73,34 +79,6 @@ def random_rotation(mom, seed):
     return out
 
 
-def rounding_floor(oracle, name, mom, ref):
-    """FP64 rounding noise of the oracle at each event: F is invariant under
-    rotations, so the spread of F over rotated frames measures the rounding
-    error an FP64 evaluation of this event carries."""
-    nu = np.zeros(len(mom))
-    for s in range(8):
-        nu = np.maximum(nu, rel_err(oracle_me2(oracle, name, random_rotation(mom, s), cut=False), ref))
-    return nu
-
-
-def assert_fp64_parity(oracle, name, mom, got, ref):
-    """|F_gpu/F_oracle - 1| <= 1e-12 per event; where the event's own FP64
-    rounding floor nu exceeds that (strong gauge cancellations), the bound is
-    16 nu.  Returns the fraction of events within 1e-12."""
-    zero = ref == 0            # events removed by the generation cut
-    assert np.all(got[zero] == 0.0)
-    got, ref, mom = got[~zero], ref[~zero], mom[~zero]
-    err = rel_err(got, ref)
-    bad = err > FP64_TOL
-    if bad.any():
-        nu = rounding_floor(oracle, name, mom[bad], ref[bad])
-        worst = np.max(err[bad] / np.maximum(nu, 1e-300))
-        print(f"{name}: {bad.sum()} of {len(err)} events above 1e-12 (max {err.max():.3e}); "
-              f"max err / floor = {worst:.2f}")
-        assert np.all(err[bad] <= 16.0 * nu), (err[bad], nu)
-    return 1.0 - bad.mean()
-
-
 @pytest.mark.parametrize("name", list(CASES))
 def test_generated_momenta_match_oracle(torch, oracle, name):
     _, nout, rs, _, seed, _ = CASES[name]
@@ -118,17 +96,12 @@ def test_generated_momenta_match_oracle(torch, oracle, name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_fp64_parity_momenta_in(torch, oracle, name):
-    _, nout, rs, _, seed, _ = CASES[name]
-    n = 3 * 1024 + 37          # several blocks and a ragged tail
-    mom = oracle.generate(seed ^ 0x55, n, nout, rs)
-    ref = oracle_me2(oracle, name, mom)
+    """the parity events (several blocks and a ragged tail), momenta in: every
+    event within the process's bound of the extended-precision oracle"""
+    mom = B.rambo_events(oracle, name)
     p = make(name)
     got = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-    nz = ref != 0
-    err = rel_err(got[nz], ref[nz])
-    print(f"{name} fp64: max rel err {err.max():.3e}, median {np.median(err):.3e} ({nz.sum()} of {n} pass the cut)")
-    frac = assert_fp64_parity(oracle, name, mom, got, ref)
-    assert frac > 0.98
+    B.check(oracle, name, mom, got)
 
 
 # The mixed-precision 120-flow MFMA colour form faulted on the GPU in a variant
@@ -144,7 +117,7 @@ def test_mixed_error_report(torch, oracle, name):
     _, nout, rs, _, seed, _ = CASES[name]
     n = 2048
     mom = oracle.generate(seed ^ 0x66, n, nout, rs)
-    ref = oracle_me2(oracle, name, mom)
+    ref = oracle_me2(oracle, name, mom, extended=True)
     p = make(name, "mixed")
     got = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
     nz = ref != 0
@@ -172,25 +145,32 @@ def test_full_size_sampled(torch, oracle, name):
     for k, i in enumerate(idx[:20]):
         ref = oracle.generate(seed, 1, nout, rs, counter_offset=int(i))[0]
         assert np.max(np.abs(got_mom[k] - ref)) < (1e-10 if nout == 2 else 1e-13) * rs
-    ref = oracle_me2(oracle, name, got_mom)
-    assert_fp64_parity(oracle, name, got_mom, got_me2, ref)
+    B.check(oracle, name, got_mom, got_me2, share=0.95)
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_integrate_matches_oracle(torch, oracle, name):
+    """sigma against the oracle's on the same events, F in extended precision:
+    with every weight >= 0, sigma's relative error is at most the largest
+    per-event one, so the per-event bound holds for it"""
     pid, nout, rs, kw, seed, _ = CASES[name]
     n = 1 << 13
     p = make(name)
     r = p.integrate(n, seed=seed, sqrt_s=rs)
     mom = oracle.generate(seed, n, nout, rs)
-    f = oracle_me2(oracle, name, mom)
+    f = oracle_me2(oracle, name, mom, extended=True)
     proc = p.ir
     sig, err, sw, sw2 = oracle.cross_section(f, oracle.phase_space_volume(rs, nout), rs, proc.n_a_n_b,
                                              proc.symmetry)
     assert r["n_generated"] == n and r["n_accepted"] == int(np.sum(f != 0))
-    # the weighted sum is no better conditioned than its worst events (see assert_fp64_parity)
-    tol = FP64_TOL if name != "ud_udhh_4b" else 1e-11
+    tol = B.BOUND[name]
+    print(f"{name} sigma: rel diff {r['sigma_gev2'] / sig - 1:.2e} (bound {tol:.0e})")
     assert abs(r["sigma_gev2"] / sig - 1) <= tol
+    if name != "gg_4g":   # mixed: see MIXED_MFMA_OFF
+        rm = make(name, "mixed").integrate(n, seed=seed, sqrt_s=rs)
+        print(f"{name} mixed sigma: rel diff {rm['sigma_gev2'] / sig - 1:.2e}")
+        assert rm["n_accepted"] == r["n_accepted"]
+        assert abs(rm["sigma_gev2"] / sig - 1) < 1e-4
     assert abs(r["err_gev2"] / err - 1) <= 1e-9
     assert abs(r["sigma_pb"] / (sig * oracle.HBARC2_PB) - 1) <= tol
 
@@ -237,7 +217,7 @@ def test_edge_cases(torch, oracle):
     for n in (1, 63, 65, 257):
         mom = oracle.generate(5, n, 6, 1000.0)
         got = p.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-        assert rel_err(got, oracle_me2(oracle, "gg_ttbar_6f", mom)).max() <= FP64_TOL
+        B.check(oracle, "gg_ttbar_6f", mom, got, share=0.0)
     with pytest.raises(H.HegetError) as e:
         p.eval(n=-1)
     assert e.value.status == -1
@@ -313,9 +293,9 @@ def test_helicity_table_path_matches_nest(torch, oracle, name):
     t = to_soa(torch, mom)
     nest = H.Process(proc).eval(momenta=t).cpu().numpy()
     table = H.Process(proc, helicities=list(proc.helicities)[::-1]).eval(momenta=t).cpu().numpy()
-    ref = oracle_me2(oracle, name, mom)
-    assert_fp64_parity(oracle, name, mom, table, ref)
-    assert_fp64_parity(oracle, name, mom, nest, ref)
+    ref = B.reference(oracle, name, mom)
+    B.check(oracle, name, mom, table, ref=ref)
+    B.check(oracle, name, mom, nest, ref=ref)
     err = rel_err(nest, table)
     print(f"{name}: nest vs table max rel diff {err.max():.2e}")
     assert np.median(err) < 1e-14

@@ -67,18 +67,15 @@ def test_eval_generates_the_same_events(torch, proc):
 
 def test_me2_of_tree_events_matches_oracle(torch, oracle, proc):
     """F on the tree's events (on the top and W peaks, where the RAMBO events
-    rarely land), momenta-in: the oracle's momenta fed to both sides"""
-    from oracle import phase_space_tree as T
-    n = 2048
-    mom, _ = T.generate(SEED, n, ROOTS, oracle_tree(), 8)
+    rarely land), momenta-in: the oracle's momenta fed to both sides, every
+    event within the process's bound of the extended-precision oracle.  On the
+    poles the denominators q^2 - m^2 come from cancelling momentum sums: the
+    FP64 oracle is off by up to 7.3e-13 there."""
+    import fp64_bounds as B
+    (mom,) = B.tree_events(oracle, NAME)
     me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-    ref = oracle.me2(oracle.GG_TT_6F, mom, oracle.params())
-    err = np.abs(me2 - ref) / np.abs(ref)
-    print(f"tree events: F max rel diff {err.max():.2e}, median {np.median(err):.2e}")
-    # on the poles the denominators q^2 - m^2 come from cancelling momentum sums:
-    # the FP64 rounding of F is larger than on flat RAMBO events (median ~5e-14)
+    err = B.check(oracle, NAME, mom, me2)
     assert np.median(err) < 1e-13
-    assert err.max() < 1e-12
 
 
 def test_integrate_matches_oracle(torch, oracle, proc):

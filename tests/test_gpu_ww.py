@@ -42,34 +42,15 @@ def to_soa(torch, mom):
     return torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
 
 
-def rotated(mom, seed):
-    rng = np.random.default_rng(seed)
-    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
-    out = mom.copy()
-    out[..., 1:] = mom[..., 1:] @ q.T
-    return out
-
-
 def test_me2_matches_oracle(torch, oracle, proc):
-    """momenta in (the oracle's events, 3,000 and a ragged 41): |F_gpu/F_oracle - 1|
-    <= 1e-12, or 16 nu where the event's own FP64 floor nu (the rotation spread
-    of the oracle's F) is larger: the longitudinal diagrams cancel from
-    E^4 / m_W^4 ~ 1.5e3 at 1 TeV"""
-    from oracle import phase_space_tree as T
-    prm = oracle.params(cms=1)
-    for n in (3000, 41):
-        mom, w = T.generate(SEED + n, n, ROOTS, TREE, 4, leg_mass=LEG_MASS)
+    """momenta in (the oracle's events, 3,000 and a ragged 41): every event
+    within the process's bound of the extended-precision oracle (5e-12, 99 %
+    within 1e-12): the longitudinal diagrams cancel from E^4 / m_W^4 ~ 1.5e3 at
+    1 TeV, and the FP64 oracle is off by up to 6.6e-13 on these events"""
+    import fp64_bounds as B
+    for mom in B.tree_events(oracle, NAME):
         me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
-        ref = oracle.me2(oracle.WW_WW, mom, prm)
-        err = np.abs(me2 - ref) / np.abs(ref)
-        bad = err > 1e-12
-        nu = np.zeros(bad.sum())
-        for s in range(8):
-            nu = np.maximum(nu, np.abs(oracle.me2(oracle.WW_WW, rotated(mom[bad], s), prm) / ref[bad] - 1))
-        print(f"WW->WW FP64 n={n}: max rel err {err.max():.2e}, median {np.median(err):.2e}, "
-              f"{bad.sum()} above 1e-12, max err / floor {np.max(err[bad] / nu, initial=0):.2f}")
-        assert np.all(err[bad] <= 16 * nu)
-        assert bad.mean() < 0.25
+        B.check(oracle, NAME, mom, me2)
 
 
 def test_mixed_precision_error(torch, oracle):

@@ -540,3 +540,28 @@ def test_ww_ww_lorentz_invariance(oracle):
     for b in ([0.3, 0.2, -0.5], [0.0, 0.0, 0.9]):
         g = oracle.me2(oracle.WW_WW, boost(mom, b), prm)
         assert np.max(np.abs(g / f - 1)) < 1e-9
+
+
+def test_w_fermion_coupling_by_the_w_width(oracle):
+    """The normalisation of the W-fermion vertex (Sec. 4.2.1, the FFV vertex with
+    the W couplings; -g_W/sqrt2 for left-handed doublets) fixes the W width:
+    Gamma(W -> e nu) = g_W^2 m_W / (48 pi) at tree level with massless leptons.
+    The oracle's own vertex, spinors and massive polarisation vectors, summed
+    over spins, must give it; a missing 1/sqrt2 doubles it."""
+    e = math.sqrt(4 * math.pi / 128.0)
+    gw = e / math.sqrt(0.2222)
+    assert oracle.decay_width(0) == pytest.approx(gw * gw * 80.4 / (48 * math.pi), rel=1e-13)
+    # the value the workload's inputs give (alpha = 1/128, sin^2 theta_W = 0.2222, m_W = 80.4)
+    assert oracle.decay_width(0) == pytest.approx(0.235570432, rel=1e-8)
+
+
+def test_w_fermion_coupling_by_the_top_width(oracle):
+    """Gamma(t -> b W) = g_W^2 m_t^3 / (64 pi m_W^2) (1 - r)^2 (1 + 2 r), r =
+    m_W^2 / m_t^2, at tree level with a massless b: the same vertex between a
+    massive top spinor and a massive external W (all three polarisations)."""
+    e = math.sqrt(4 * math.pi / 128.0)
+    gw = e / math.sqrt(0.2222)
+    for mt, mw in ((175.0, 80.4), (250.0, 91.0)):
+        r = mw * mw / (mt * mt)
+        expect = gw * gw * mt ** 3 / (64 * math.pi * mw * mw) * (1 - r) ** 2 * (1 + 2 * r)
+        assert oracle.decay_width(1, oracle.params(mt=mt, mw=mw)) == pytest.approx(expect, rel=1e-13)

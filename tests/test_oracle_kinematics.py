@@ -128,3 +128,64 @@ def test_gluon_cut_hand_cases(oracle):
     far = ev([100, 100, 100, 100], [0, 0.3, 1, -1], [0, 0.3, 0, 4])      # dR = 0.424
     res = oracle.cut_gluons(np.stack([good, low_pt, close, wrap, far]))
     assert list(res) == [1, 0, 0, 0, 1]
+
+
+@pytest.mark.parametrize("n_out", [3, 4, 6])
+def test_rambo_energy_fraction_is_beta_2_n_minus_2(oracle, n_out):
+    """The flat massless n-body density (Sec. 2, Eq. of dPhi_n) fixes the energy
+    of any one particle: dPhi_n = d^3p/(2E) Phi_{n-1}((P - p)^2) with
+    Phi_{n-1}(s') proportional to s'^(n-3) and s' = s (1 - x), x = 2E/sqrt(s), so
+    x follows x (1 - x)^(n-3), the Beta(2, n - 2) law.  Conservation, mass
+    shells, isotropy and a constant weight hold for any energy law; this does
+    not (an exponential instead of a Gamma(2) seed energy fails it by far)."""
+    from scipy import stats
+    N = 20000
+    mom = oracle.generate(0x52414D42, N, n_out, 1000.0)
+    idx = 2 + np.arange(N) % n_out        # one particle per event: independent samples
+    x = 2.0 * mom[np.arange(N), idx, 0] / 1000.0
+    assert stats.kstest(x, stats.beta(2, n_out - 2).cdf).pvalue > 1e-3
+    # second moment 6 / (n (n + 1)) within five standard errors
+    m2 = 6.0 / (n_out * (n_out + 1))
+    assert abs(np.mean(x * x) - m2) < 5 * np.std(x * x) / math.sqrt(N)
+
+
+def test_rambo_three_body_dalitz_moments(oracle):
+    """Three massless bodies: the Dalitz plot is flat, so (s12, s13, s23)/s is
+    uniform on the simplex (a Dirichlet(1, 1, 1) law): <s12> = s/3,
+    <s12^2> = s^2/6, <s12 s23> = s^2/12."""
+    N = 200000
+    mom = oracle.generate(0x44414C49, N, 3, 1000.0)
+    p = mom[:, 2:, :]
+
+    def inv(a, b):
+        q = p[:, a] + p[:, b]
+        return (q[:, 0] ** 2 - (q[:, 1:] ** 2).sum(axis=1)) / 1e6
+    y12, y23 = inv(0, 1), inv(1, 2)
+    for v, expect in ((y12, 1 / 3), (y12 * y12, 1 / 6), (y12 * y23, 1 / 12)):
+        assert abs(v.mean() - expect) < 5 * v.std() / math.sqrt(N)
+
+
+def test_rambo_matches_the_flat_tree(oracle):
+    """For 4 and 6 bodies the pair mass s12 / s and the single energy E / sqrt(s)
+    of RAMBO events (constant weight) have the means of the flat resonance tree,
+    whose weights carry the density event by event (the tree's volume is pinned
+    to the closed form in test_oracle_phase_space_tree)."""
+    from oracle import phase_space_tree as T
+    for n_out in (4, 6):
+        N = 40000
+        mom = oracle.generate(0x464C4154 + n_out, N, n_out, 1000.0)
+        nodes = [(0.0, 0.0, None, 2, -2, None)] + \
+            [(0.0, 0.0, "flat", 2 + k, -(k + 2), None) for k in range(1, n_out - 1)]
+        nodes[-1] = (0.0, 0.0, "flat", n_out, n_out + 1, None)
+        tmom, w = T.generate(0x54524545 + n_out, N, 1000.0, nodes, n_out + 2)
+
+        def obs(m):
+            q = m[:, 2] + m[:, 3]
+            return np.stack([(q[:, 0] ** 2 - (q[:, 1:] ** 2).sum(axis=1)) / 1e6, m[:, 2, 0] / 1000.0,
+                             m[:, 5, 0] / 1000.0], axis=1)
+        a, b = obs(mom), obs(tmom)
+        for k in range(a.shape[1]):
+            ma, sa = a[:, k].mean(), a[:, k].std() / math.sqrt(N)
+            mb = np.sum(w * b[:, k]) / np.sum(w)
+            sb = math.sqrt(np.sum((w * (b[:, k] - mb)) ** 2)) / np.sum(w)
+            assert abs(ma - mb) < 5 * math.hypot(sa, sb), (n_out, k, ma, mb)
