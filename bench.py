@@ -47,6 +47,38 @@ COUNTERS_FP64 = {"source_digest": "b40c3fc1f6ee5b67dccdc316e30018dfa79ed057ba53b
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 
 
+# Counter measurements of further kernels, (process, precision) -> figures per
+# event from rocprofv3 --pmc runs of `bench.py --profile-leg <prec>
+# --profile-proc <process>` (the summaries under profiles/), tied to the kernel
+# source they were taken on: executed VALU flops (2 FMA + MUL + ADD + TRANS of
+# the precision's SQ_INSTS_VALU_* counters x 64 lanes, per event) and, for the
+# MFMA colour form, MFMA flops (SQ_INSTS_VALU_MFMA_MOPS_* x 512 per event).
+KERNEL_COUNTERS = {
+    # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
+    ("ud_udhh_4b", "mixed"): {
+        "source_digest": "d1ccab3f7f392baaa6c66fbf9a0dcdcbb6d4e0a7cfb55aa67ad6629aba6095bb",
+        "valu_flop_per_event": 45030, "fp64_flop_per_event": 2973, "events": 1 << 21, "kernel_s": 1.356e-3,
+        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
+    ("ud_udhh_4b", "fp64"): {
+        "source_digest": "d1ccab3f7f392baaa6c66fbf9a0dcdcbb6d4e0a7cfb55aa67ad6629aba6095bb",
+        "valu_flop_per_event": 48026, "events": 1 << 21, "kernel_s": 2.482e-3,
+        "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
+    # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
+    ("gg_4g", "fp64"): {
+        "source_digest": "e0b956bacf914371dab169d45fb212339e16d1226719211d72b0a6fef498e92f",
+        "valu_flop_per_event": 4130384, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 190.8e-3,
+        "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
+    ("gg_4g_ddm", "fp64"): {
+        "source_digest": "8ff2a066cb0632199efee22fe47d01d1e8f0191216be8d8728109381bec56ded",
+        "valu_flop_per_event": 4071824, "events": 1 << 20, "kernel_s": 107.7e-3,
+        "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
+    ("gg_4g_ddm", "mixed"): {
+        "source_digest": "8ff2a066cb0632199efee22fe47d01d1e8f0191216be8d8728109381bec56ded",
+        "valu_flop_per_event": 3492111, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 77.9e-3,
+        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
+}
+
+
 def counters_valid(proc_ir):
     from paper_1305_0708_amd import codegen
     return codegen.source_digest(proc_ir) == COUNTERS_FP64["source_digest"]
@@ -59,29 +91,40 @@ def measured_traffic(proc_ir):
     return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
-def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S):
+def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S, seed=SEED):
     """Per step: one heget_integrate (amplitude kernel + reduction).  Also
     times the amplitude kernel alone with HIP events on the launch stream."""
     for _ in range(warmup):
-        proc.integrate(n, seed=SEED, sqrt_s=sqrt_s)
+        proc.integrate(n, seed=seed, sqrt_s=sqrt_s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        r = proc.integrate(n, seed=SEED + k, sqrt_s=sqrt_s)
+        r = proc.integrate(n, seed=seed + k, sqrt_s=sqrt_s)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     # amplitude kernel alone: eval with |M|^2 written, timed with events on the stream it runs on
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    proc.eval(n=n, seed=SEED, sqrt_s=sqrt_s, me2_out=out)
+    proc.eval(n=n, seed=seed, sqrt_s=sqrt_s, me2_out=out)
     ev0.record(stream)
     for k in range(steps):
-        proc.eval(n=n, seed=SEED + k, sqrt_s=sqrt_s, me2_out=out)
+        proc.eval(n=n, seed=seed + k, sqrt_s=sqrt_s, me2_out=out)
     ev1.record(stream)
     ev1.synchronize()
     kern = ev0.elapsed_time(ev1) / 1e3 / steps
     return wall, kern, r
+
+
+def settle_clocks(torch, proc, seconds=0.5):
+    """untimed launches of the headline kernel for about half a second before
+    the warm-up steps, so that the GPU has left its idle clocks when timing
+    starts (the first timed steps of a fresh box otherwise run slow)"""
+    out = torch.empty(N_EVENTS, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        proc.eval(n=N_EVENTS, seed=SEED, sqrt_s=SQRT_S, me2_out=out)
+        torch.cuda.synchronize()
 
 
 def cpu_baseline(oracle, target_seconds=12.0):
@@ -155,14 +198,86 @@ def adaptive_leg(torch, H, processes, passes=6, bins=32):
             "sigma_pb": comb["sigma_pb"], "sigma_err_pb": comb["err_pb"], "chi2_per_dof": chi2}
 
 
-def config_leg(torch, H, pir, workload, flops, steps, warmup, n=N_EVENTS, precisions=("fp64", "mixed")):
-    """integrate steps of n events of one more configuration, per precision"""
-    out = {"workload": workload, "events_per_step": n, "flop_per_event": flops.per_event(pir)}
+def counter_figures(pir, prec, kern_s, n):
+    """executed TFLOP/s of a kernel from counters taken on the same kernel
+    source (None when no counters match it)"""
+    from paper_1305_0708_amd import codegen
+    c = KERNEL_COUNTERS.get((pir.name, prec))
+    if c is None or codegen.source_digest(pir) != c["source_digest"]:
+        return None
+    out = {"flop_per_event": c["valu_flop_per_event"], "source": c["source"],
+           "valu_tflops": c["valu_flop_per_event"] * n / kern_s / 1e12,
+           "valu_peak": FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS}
+    if "mfma_flop_per_event" in c:
+        out["mfma_tflops"] = c["mfma_flop_per_event"] * n / kern_s / 1e12
+        out["mfma_peak"] = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+    return out
+
+
+def config_leg(torch, H, pir, workload, steps, warmup, n=N_EVENTS, precisions=("fp64", "mixed"), seed=SEED):
+    """integrate steps of n events of one more configuration, per precision; a
+    precision the library refuses for this process is reported as refused"""
+    out = {"workload": workload, "events_per_step": n}
     for prec in precisions:
-        proc = H.Process(pir, precision=prec)
-        wall, kern, r = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s)
+        try:
+            proc = H.Process(pir, precision=prec)
+        except H.HegetError as e:
+            out[prec] = {"refused": str(e)}
+            continue
+        wall, kern, r = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s, seed=seed)
         out[prec] = {"events_per_s": n / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
-                     "model_tflops": flops.per_event(pir) * n / kern / 1e12, "sigma_pb": r["sigma_pb"]}
+                     "sigma_pb": r["sigma_pb"], "sigma_err_pb": r["err_pb"], "n_accepted": r["n_accepted"]}
+        cf = counter_figures(pir, prec, kern, n)
+        if cf:
+            out[prec]["counters"] = cf
+        proc.close()
+    return out
+
+
+def oracle_leg(torch, H, oracle, pir, oracle_proc, oracle_kw, nout, seed, cut=None, target_seconds=3.0,
+               precisions=("fp64", "mixed"), extended=False):
+    """The oracle beside the GPU on a bounded sample of the same workload:
+    its events/s on every host core, and the GPU's error against it on the
+    sample's events (the oracle's momenta fed to heget_eval): max and median
+    relative error of |M|^2 per precision, and the relative error of sigma over
+    the sample (the same RAMBO weight on both sides)."""
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    pid, prm = getattr(oracle, oracle_proc), oracle.params(**oracle_kw)
+    probe = oracle.generate(seed, 64, nout, pir.sqrt_s)
+    t0 = time.perf_counter()
+    oracle.me2(pid, probe, prm, threads=cores)
+    rate = 64 / (time.perf_counter() - t0)
+    n = int(min(max(rate * target_seconds, 256), 1 << 18))
+    mom = oracle.generate(seed, n, nout, pir.sqrt_s)
+    t0 = time.perf_counter()
+    f = oracle.me2(pid, mom, prm, threads=cores)
+    dt = time.perf_counter() - t0
+    passed = oracle.cut_gluons(mom, *cut) if cut else np.ones(n, dtype=np.int32)
+    f = f * passed
+    out = {"value": n / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} events of the same workload (first {n} Philox counters), {dt:.1f} s"}
+    if extended:
+        t0 = time.perf_counter()
+        f = oracle.me2(pid, mom, prm, threads=cores, extended=True) * passed
+        out["reference"] = f"long-double oracle on the sample ({time.perf_counter() - t0:.1f} s)"
+    vol = oracle.phase_space_volume(pir.sqrt_s, nout)
+    sig_ref = oracle.cross_section(f, vol, pir.sqrt_s, pir.n_a_n_b, pir.symmetry, passed=passed)[0]
+    soa = torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
+    nz = f != 0
+    for prec in precisions:
+        try:
+            proc = H.Process(pir, precision=prec)
+        except H.HegetError as e:
+            out[f"{prec}_error"] = {"refused": str(e)}
+            continue
+        got = proc.eval(momenta=soa).cpu().numpy()
+        proc.close()
+        err = np.abs(got[nz] - f[nz]) / np.abs(f[nz])
+        sig = oracle.cross_section(got, vol, pir.sqrt_s, pir.n_a_n_b, pir.symmetry, passed=passed)[0]
+        out[f"{prec}_error"] = {"me2_max_rel": float(err.max()), "me2_median_rel": float(np.median(err)),
+                                "sigma_rel": sig / sig_ref - 1.0, "events": int(nz.sum()),
+                                "cut_events_exactly_zero": bool(np.all(got[~nz] == 0.0))}
     return out
 
 
@@ -251,7 +366,7 @@ def main():
 
     import torch
     import paper_1305_0708_amd as H
-    from paper_1305_0708_amd import processes, flops
+    from paper_1305_0708_amd import processes, codegen, flops
 
     proc_ir = processes.gg_ttbar_6f()
     if args.profile_leg:
@@ -265,11 +380,11 @@ def main():
             return
         pir = processes.by_name(args.profile_proc)
         proc = H.Process(pir, precision=args.profile_leg)
-        n = N_EVENTS if args.profile_proc != "gg_5g_ddm" else 1 << 16
+        n = {"gg_5g_ddm": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536}.get(args.profile_proc, N_EVENTS)
         wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
-               "kernel_ms": kern * 1e3, "events_per_launch": n, "flop_per_event": flops.per_event(pir),
-               "events_per_s": n / wall, "n_accepted": r["n_accepted"]}
+               "kernel_ms": kern * 1e3, "events_per_launch": n, "events_per_s": n / wall,
+               "n_accepted": r["n_accepted"], "source_digest": codegen.source_digest(pir)}
         if args.copy_calibration:
             src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
             dst = torch.empty_like(src)
@@ -284,6 +399,7 @@ def main():
     fp64 = H.Process(proc_ir, precision="fp64")
     mixed = H.Process(proc_ir, precision="mixed")
 
+    settle_clocks(torch, fp64)
     wall64, kern64, r64 = time_path(torch, fp64, args.steps, args.warmup)
     wallmx, kernmx, rmx = time_path(torch, mixed, args.steps, args.warmup)
 
@@ -301,9 +417,10 @@ def main():
         mixed_flop_event = COUNTERS_FP64["flop_per_event_mixed"]
         mixed_flop_source = "executed FP32 flops from SQ_INSTS_VALU_*_F32"
     else:
-        flop_event, flop_source = model_flop_event, "IR flop model (counters taken on another kernel source)"
-        mixed_flop_event, mixed_flop_source = model_flop_event, flop_source
-    achieved = flop_event * N_EVENTS / kern64 / 1e12
+        # counters taken on another kernel source: no executed-flop figure
+        flop_event, flop_source = None, "none: the counters were taken on another kernel source"
+        mixed_flop_event, mixed_flop_source = None, flop_source
+    achieved = flop_event * N_EVENTS / kern64 / 1e12 if flop_event else None
     value = N_EVENTS / wall64
     line = {
         "metric": METRIC,
@@ -322,13 +439,13 @@ def main():
                                "per step, 256 helicity combinations, 2 colour flows",
                    "events_per_step": N_EVENTS, "helicities": 256},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(proc_ir),
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": measured_traffic(proc_ir),
                      "traffic_unit": "bytes per launch",
                      "kernel": "amp_gg_ttbar_6f<double>", "kernel_ms": kern64 * 1e3,
                      "flop_per_event": flop_event, "flop_source": flop_source,
                      "model_flop_per_event": model_flop_event},
         "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,
-                  "tflops": mixed_flop_event * N_EVENTS / kernmx / 1e12, "peak": FP32_PEAK_TFLOPS,
+                  "tflops": mixed_flop_event * N_EVENTS / kernmx / 1e12 if mixed_flop_event else None, "peak": FP32_PEAK_TFLOPS,
                   "flop_per_event": mixed_flop_event, "flop_source": mixed_flop_source,
                   "sigma_pb": rmx["sigma_pb"]},
         "helicity_filtered": {"helicities": nk, "fp64_value": N_EVENTS / wall64f,
@@ -342,24 +459,59 @@ def main():
     line["triple_higgs"] = config_leg(
         torch, H, processes.ud_udhhh(), "u d -> u d H H H by W W and Z Z fusion (quartic scalar vertex), "
         "sqrt_s_hat = 2 TeV, 2^20 events per step, 16 helicity combinations, 2 colour flows",
-        flops, args.steps, args.warmup)
+        args.steps, args.warmup)
     line["w_scattering"] = config_leg(
         torch, H, processes.ww_ww(), "W- W+ -> W- W+ (massive external W, weak quartic vertex), "
-        "sqrt_s_hat = 1 TeV, 2^20 events per step, 81 helicity combinations", flops, args.steps, args.warmup)
+        "sqrt_s_hat = 1 TeV, 2^20 events per step, 81 helicity combinations", args.steps, args.warmup)
     line["hadronic_collision"] = config_leg(
         torch, H, processes.gg_ttbar_6f_had(), "gg -> t tbar -> 6f at a 14 TeV hadron collider (parton densities "
         "1), tops in |y| < 2.5 by rapidity, ln(m^2 + pT^2) and azimuth, x_a, x_b from momentum conservation, "
-        "resonance-tree decays, 2^20 events per step", flops, args.steps, args.warmup)
-    # seven gluons: 120 DDM orderings x 128 helicities per event, FP64 (the FP32 MFMA colour form is off)
+        "resonance-tree decays, 2^20 events per step", args.steps, args.warmup)
+    # seven gluons: 120 DDM orderings x 128 helicities per event
     line["seven_gluons"] = config_leg(
         torch, H, processes.by_name("gg_5g_ddm"), "g g -> g g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV, "
         "Delta R > 0.4, 2^16 events per step, 128 helicity combinations, 120 DDM colour flows on MFMA",
-        flops, 3, 1, n=1 << 16, precisions=("fp64",))
+        3, 1, n=1 << 16)
+    # the other configured workloads, each with the oracle timed beside it on a
+    # sample of its events and the GPU's error against the oracle on that sample
+    import oracle as O
+    legs = {}
+    c0 = processes.ee_mumu()
+    legs["c0"] = config_leg(
+        torch, H, c0, "e+ e- -> mu+ mu- via photon and Z, sqrt_s = 200 GeV, 65,536 RAMBO events per step, "
+        "16 helicity combinations", args.steps, args.warmup, n=65536, seed=0x48454745)
+    if not args.no_cpu_baseline:
+        legs["c0"]["oracle"] = oracle_leg(torch, H, O, c0, "EE_MUMU", {}, 2, 0x48454745, target_seconds=1.0,
+                                          extended=True)
+    c2 = processes.by_name("gg_4g")
+    c2d = processes.by_name("gg_4g_ddm")
+    legs["c2"] = config_leg(
+        torch, H, c2, "g g -> g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV and Delta R > 0.4 by rejection, 2^20 RAMBO "
+        "events per step, 64 helicity combinations, 120 trace-basis flows, dense 120 x 120 colour form on MFMA",
+        args.steps, args.warmup, seed=0x48454747)
+    legs["c2"]["ddm_basis"] = config_leg(
+        torch, H, c2d, "the same events and |M|^2 through the 24-flow DDM basis, colour form on VALU",
+        args.steps, args.warmup, seed=0x48454747)
+    if not args.no_cpu_baseline:
+        legs["c2"]["oracle"] = oracle_leg(torch, H, O, c2, "GG_4G", {}, 4, 0x48454747, cut=(20.0, 0.4))
+        legs["c2"]["ddm_basis"]["oracle"] = oracle_leg(torch, H, O, c2d, "GG_4G", {}, 4, 0x48454747,
+                                                       cut=(20.0, 0.4), target_seconds=1.0)
+    c3 = processes.ud_udhh_4b()
+    legs["c3"] = config_leg(
+        torch, H, c3, "u d -> u d H H (W W and Z Z fusion), H -> b bbar, sqrt_s_hat = 2 TeV, 2^21 RAMBO events "
+        "per step, 256 helicity combinations, complex-mass W and Z; mixed precision keeps the propagator "
+        "denominators in FP64", args.steps, args.warmup, n=1 << 21, precisions=("mixed", "fp64"), seed=0x48454748)
+    if not args.no_cpu_baseline:
+        legs["c3"]["oracle"] = oracle_leg(torch, H, O, c3, "UD_UDHH_4B", {"cms": 1}, 6, 0x48454748,
+                                          precisions=("mixed", "fp64"))
+    line["configs"] = legs
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:
         import oracle
         line["cpu_baseline"] = cpu_baseline(oracle)
+        line["mixed"]["error_vs_oracle"] = oracle_leg(torch, H, oracle, proc_ir, "GG_TT_6F", {}, 6, SEED,
+                                                      target_seconds=2.0)
     print(json.dumps(line), flush=True)
 
 

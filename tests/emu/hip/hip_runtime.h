@@ -1,0 +1,118 @@
+// Host stand-in for <hip/hip_runtime.h> used ONLY by the CPU lane emulator
+// (tests/emu): it lets the library's own kernel and host sources compile as
+// plain C++ for x86-64, where every GPU lane is a fiber, every 64 fibers a
+// wavefront and every block a group of fibers run to completion before the
+// next block starts.  Wave-level operations (ballot, shuffle, readfirstlane,
+// the 16x16x4 MFMAs) and barriers are rendezvous points of the fibers of one
+// wave or block; device memory is host memory from malloc, so that
+// AddressSanitizer checks every access the kernels make.  Nothing in the
+// product loads this file.
+#pragma once
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct emu_uint3 {
+  unsigned x, y, z;
+};
+
+typedef double emu_d4 __attribute__((ext_vector_type(4)));
+typedef float emu_f4 __attribute__((ext_vector_type(4)));
+
+namespace emu {
+extern emu_uint3 thread_idx_of_current();
+extern emu_uint3 block_idx, block_dim, grid_dim;
+void wave_barrier();
+void block_barrier();
+bool any(bool v);
+double shfl_xor_f64(double v, int mask);
+float shfl_xor_f32(float v, int mask);
+int shfl_xor_i32(int v, int mask);
+int readfirstlane(int v);
+emu_d4 mfma_f64(double a, double b, emu_d4 c);
+emu_f4 mfma_f32(float a, float b, emu_f4 c);
+void run_grid(dim3 grid, dim3 block, void (*entry)(void*), void* ctx);
+template <class F>
+void launch(dim3 grid, dim3 block, F f) {
+  run_grid(grid, block, [](void* c) { (*static_cast<F*>(c))(); }, &f);
+}
+inline double shfl_xor(double v, int m) { return shfl_xor_f64(v, m); }
+inline float shfl_xor(float v, int m) { return shfl_xor_f32(v, m); }
+inline int shfl_xor(int v, int m) { return shfl_xor_i32(v, m); }
+}  // namespace emu
+
+#define threadIdx (emu::thread_idx_of_current())
+#define blockIdx (emu::block_idx)
+#define blockDim (emu::block_dim)
+#define gridDim (emu::grid_dim)
+#define __syncthreads() emu::block_barrier()
+#define __any(x) emu::any(x)
+#define __shfl_xor(v, m, w) emu::shfl_xor((v), (m))
+#define __builtin_amdgcn_readfirstlane(x) emu::readfirstlane(x)
+#define __builtin_amdgcn_wave_barrier() emu::wave_barrier()
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64((a), (b), (c))
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32((a), (b), (c))
+
+inline unsigned __umulhi(unsigned a, unsigned b) { return unsigned((uint64_t(a) * b) >> 32); }
+using std::max;
+using std::min;
+
+// ---- runtime API subset used by the library's host code ----
+typedef enum hipError_t {
+  hipSuccess = 0,
+  hipErrorInvalidValue = 1,
+  hipErrorOutOfMemory = 2,
+  hipErrorLaunchFailure = 719
+} hipError_t;
+typedef struct emu_stream* hipStream_t;
+typedef enum hipMemcpyKind {
+  hipMemcpyHostToHost = 0,
+  hipMemcpyHostToDevice = 1,
+  hipMemcpyDeviceToHost = 2,
+  hipMemcpyDeviceToDevice = 3,
+  hipMemcpyDefault = 4
+} hipMemcpyKind;
+typedef enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 63 } hipDeviceAttribute_t;
+#define hipHostMallocDefault 0u
+
+hipError_t hipMalloc(void** p, size_t n);
+template <class T>
+inline hipError_t hipMalloc(T** p, size_t n) {
+  return hipMalloc(reinterpret_cast<void**>(p), n);
+}
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
+template <class T>
+inline hipError_t hipHostMalloc(T** p, size_t n, unsigned flags = 0) {
+  return hipHostMalloc(reinterpret_cast<void**>(p), n, flags);
+}
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k);
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st = nullptr);
+hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t st = nullptr);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipDeviceSynchronize();
+hipError_t hipGetDevice(int* d);
+hipError_t hipGetLastError();
+const char* hipGetErrorString(hipError_t e);
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int dev);
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* f, int block, size_t shmem);
+hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void** args, size_t shmem, hipStream_t s);
+#define hipLaunchKernelGGL(k, g, b, sh, st, ...) emu::launch(dim3(g), dim3(b), [=]() { k(__VA_ARGS__); })

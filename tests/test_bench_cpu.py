@@ -1,7 +1,8 @@
 """CPU checks of the benchmark's bookkeeping: the executed-flop and HBM-byte
 counters that bench.py quotes for the dominant kernel were taken on the kernel
-source it would run now (else its roofline would fall back to the IR flop
-model, which counts arithmetic the compiler drops and can exceed the peak)."""
+source it would run now (else its roofline reports no executed-flop figure:
+the IR flop model counts arithmetic the compiler drops and can exceed the
+peak, so it is never used as one)."""
 import os
 import sys
 
@@ -22,3 +23,16 @@ def test_executed_flops_stay_below_the_peak_at_the_quoted_duration():
     # 2^20 events in the traced 1.18-1.24 ms
     tflops = bench.COUNTERS_FP64["flop_per_event"] * (1 << 20) / 1.18e-3 / 1e12
     assert tflops < bench.FP64_PEAK_TFLOPS
+
+
+def test_further_kernel_counters_match_their_kernels():
+    """every kernel counter set bench.py quotes was taken on the kernel source
+    it would run now, and its executed flops stay below the peak at the
+    kernel time its profile quotes"""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1305_0708_amd import codegen, processes
+    for (name, prec), c in bench.KERNEL_COUNTERS.items():
+        assert codegen.source_digest(processes.by_name(name)) == c["source_digest"], (name, prec)
+        peak = bench.FP64_PEAK_TFLOPS if prec == "fp64" else bench.FP32_PEAK_TFLOPS
+        assert c["valu_flop_per_event"] * c["events"] / c["kernel_s"] / 1e12 < peak, (name, prec)
