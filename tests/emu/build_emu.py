@@ -24,8 +24,7 @@ OUT = os.path.join(HERE, "_build")
 SRC = os.path.join(OUT, "src")
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 FLAGS = ["-std=c++17", "-O1", "-g", "-fPIC", "-fsanitize=address", "-fno-omit-frame-pointer",
-         "-Wno-duplicate-decl-specifier", "-Wno-unused-result", "-w",
-         "-I", HERE, "-I", SRC, "-I", os.path.join(ROOT, "include")]
+         "-Wno-duplicate-decl-specifier", "-Wno-unused-result", "-w", "-I"]
 LIB = os.path.join(OUT, "libheget_emu.so")
 
 _ASM = re.compile(r'asm\s+volatile\s*\(\s*""\s*:[^;]*\)\s*;')
@@ -57,13 +56,16 @@ def _copy(name, dst_dir, edits=()):
     return dst
 
 
-def build(processes=("gg_4g", "gg_4g_ddm", "gg_5g_ddm"), force=False, abi_edits=(), out=None):
+def build(processes=("gg_4g", "gg_4g_ddm", "gg_5g_ddm"), force=False, abi_edits=(), out=None, root=None):
     """compile heget_abi and the named processes' generated kernels; abi_edits
-    (old, new) are applied to the copy of heget_abi.hip, and out names another
-    build folder for such a variant"""
-    global OUT, SRC, LIB
+    (old, new) are applied to the copy of heget_abi.hip, out names another
+    build folder for such a variant and root another source tree"""
+    global OUT, SRC, LIB, ROOT, CSRC
     if out:
         OUT, SRC, LIB = out, os.path.join(out, "src"), os.path.join(out, "libheget_emu.so")
+    if root:
+        ROOT, CSRC = root, os.path.join(root, "paper_1305_0708_amd", "csrc")
+    flags = FLAGS[:FLAGS.index("-I")] + ["-I", HERE, "-I", SRC, "-I", os.path.join(ROOT, "include")]
     sys.path.insert(0, ROOT)
     from paper_1305_0708_amd import build as hb
     hb.generate_sources()
@@ -80,11 +82,11 @@ def build(processes=("gg_4g", "gg_4g_ddm", "gg_5g_ddm"), force=False, abi_edits=
     def compile_one(src):
         obj = os.path.join(OUT, os.path.basename(src) + ".o")
         with open(src, "rb") as f:
-            stamp = hashlib.sha256(f.read()).hexdigest() + " ".join(FLAGS)
+            stamp = hashlib.sha256(f.read()).hexdigest() + " ".join(flags)
         stamp_file = obj + ".stamp"
         if not force and os.path.exists(obj) and os.path.exists(stamp_file) and open(stamp_file).read() == stamp:
             return obj
-        cmd = [CXX] + FLAGS + ["-x", "c++", "-c", src, "-o", obj]
+        cmd = [CXX] + flags + ["-x", "c++", "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"emulator build failed for {src}:\n{r.stderr[-6000:]}")

@@ -14,7 +14,7 @@ import sys
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(os.path.dirname(HERE))
+ROOT = os.environ.get("EMU_ROOT") or os.path.dirname(os.path.dirname(HERE))   # the source tree built
 sys.path.insert(0, ROOT)
 sys.modules["torch"] = None      # the emulated library takes host pointers
 

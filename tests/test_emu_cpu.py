@@ -1,0 +1,70 @@
+"""The MFMA colour-form kernels on the CPU lane emulator (tests/emu): the
+library's generated kernels and host code built for x86-64 with
+AddressSanitizer on every access, one fiber per lane, the wave operations and
+the two MFMA lane layouts emulated.  Ragged launches (n = 45: one block of 45
+lanes; n = 300: two blocks, the second with 44 active lanes and three waves
+with none) must make no invalid access, give the same bits with the lanes run
+in ascending and in descending order (no lane reads what another wrote without
+a barrier), and match the FP64 oracle: within 1e-12 in FP64, at FP32's scale in
+mixed precision.  The emulated library lifts the create-time refusal of mixed
+precision for these kernels (its copy of heget_abi.hip only), so that the FP32
+MFMA path the GPU does not run is still checked on the CPU."""
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(HERE, "emu")
+OUT = os.path.join(EMU, "_build", "mixed_allowed")
+LIFT = [("if (prec == HEGET_MIXED && entry->colour_mfma)\n    return fail(", "if (false)\n    return fail(")]
+
+
+@pytest.fixture(scope="module")
+def emu_lib():
+    sys.path.insert(0, EMU)
+    import build_emu
+    if not os.path.exists(build_emu.CXX) or not build_emu.asan_runtime():
+        pytest.skip("host clang++ with the AddressSanitizer runtime not available")
+    lib = build_emu.build(processes=("gg_4g", "gg_5g_ddm"), abi_edits=LIFT, out=OUT)
+    return lib, build_emu.asan_runtime()
+
+
+def run(emu_lib, name, prec, n, seed, order, cus):
+    lib, asan = emu_lib
+    out = os.path.join(OUT, f"run_{name}_{prec}_{n}_{order}.npz")
+    env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               EMU_LANE_ORDER=str(order), EMU_CUS=str(cus))
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_emu.py"), lib, name, prec, str(n), hex(seed), out],
+                       env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, f"emulated {name} {prec} n={n}: rc {r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
+    d = np.load(out)
+    return d["me2"], d["mom"]
+
+
+@pytest.mark.parametrize("name,prec,n,cus", [
+    ("gg_4g", "fp64", 300, 1),      # one persistent block walks both 256-event blocks
+    ("gg_4g", "mixed", 300, 2),
+    ("gg_4g", "mixed", 45, 1),
+    ("gg_5g_ddm", "mixed", 45, 1),
+])
+def test_mfma_colour_form_on_ragged_launches(emu_lib, oracle, name, prec, n, cus):
+    seed, nout, pid = {"gg_4g": (0x48454747, 4, oracle.GG_4G), "gg_5g_ddm": (0x47474735, 5, oracle.GG_5G)}[name]
+    me2, mom = run(emu_lib, name, prec, n, seed, 0, cus)
+    if name == "gg_4g":
+        me2_rev, _ = run(emu_lib, name, prec, n, seed, 1, cus)
+        assert np.array_equal(me2, me2_rev), "results depend on the order the lanes run in"
+    ref_mom = oracle.generate(seed, n, nout, 1000.0)
+    assert np.abs(np.transpose(mom, (2, 0, 1)) - ref_mom).max() < 1e-13 * 1000.0
+    ref = oracle.me2(pid, ref_mom) * oracle.cut_gluons(ref_mom, 20.0, 0.4)
+    nz = ref != 0
+    assert np.all(me2[~nz] == 0.0)
+    err = np.abs(me2[nz] - ref[nz]) / ref[nz]
+    print(f"emulated {name} {prec} n={n}: max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    if prec == "fp64":
+        assert err.max() <= 1e-12
+    else:
+        assert np.median(err) < 1e-5 and err.max() < 1e-4
