@@ -277,6 +277,24 @@ heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, i
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
                              void* stream);
 
+/* heget_integrate for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, counters, reduction order and result as heget_integrate (bit for
+ * bit), with the per-block partial sums and the reduced sums in a fixed scratch
+ * array of the library instead of buffers of the handle; the result is read
+ * back into host memory of the call itself.  The call allocates nothing and
+ * calls no allocating routine.  n is at most HEGET_NOALLOC_MAX_EVENTS (the
+ * scratch holds 24 bytes per 256 events: 6 MiB per GPU, held until the process
+ * ends).  Every call on one GPU shares that GPU's scratch: calls that overlap
+ * on one GPU (from several threads or streams) race and must not be made.
+ * The scratch's address is looked up once per device, by heget_process_create
+ * or by this call's first use on a device.  Synchronises `stream`; fills *out.
+ * Errors: HEGET_E_INVALID (null handle or out, n < 2, n above the limit,
+ * sqrt_s <= 0), HEGET_E_HIP. */
+#define HEGET_NOALLOC_MAX_EVENTS (INT64_C(1) << 26)
+heget_status heget_integrate_noalloc(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed,
+                                     heget_result* out, void* stream);
+
 /* Adaptive Monte Carlo integration (the role of the BASES integrator in the
  * paper's runs, Sec. 1 and 6): `iterations` passes of n events each, iteration
  * k drawing counters k n .. (k + 1) n - 1 from `seed`; the uniforms of the

@@ -163,6 +163,15 @@ class Process:
         check(self._lib.heget_integrate(self._h, n, float(sqrt_s), seed, ctypes.byref(r), self._stream(stream)))
         return {k: getattr(r, k) for k, _ in r._fields_}
 
+    def integrate_noalloc(self, n, seed=0, sqrt_s=None, stream=None):
+        """heget_integrate_noalloc: heget_integrate with no allocation in the
+        call (the library's fixed scratch; n <= HEGET_NOALLOC_MAX_EVENTS)"""
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        r = _lib.heget_result()
+        check(self._lib.heget_integrate_noalloc(self._h, n, float(sqrt_s), seed, ctypes.byref(r),
+                                                self._stream(stream)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
     @property
     def grid_dims(self):
         """uniforms per event that an adaptive grid maps (0 for RAMBO processes)"""

@@ -7,11 +7,12 @@ LIB_PATH = os.path.join(_HERE, "libheget.so")
 
 HEGET_OK, HEGET_E_INVALID, HEGET_E_IR, HEGET_E_OOM, HEGET_E_HIP, HEGET_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 HEGET_FP64, HEGET_MIXED = 0, 1
+HEGET_NOALLOC_MAX_EVENTS = 1 << 26     # include/heget.h
 
 EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "heget_integrate",
             "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error", "heget_generate",
             "heget_uniforms",
-            "heget_integrate_adaptive", "heget_process_grid_dims",
+            "heget_integrate_adaptive", "heget_process_grid_dims", "heget_integrate_noalloc",
             "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
             "heget_server_destroy"]
 
@@ -114,6 +115,9 @@ def load(path=None):
     L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.POINTER(heget_result), vp]
     L.heget_integrate.restype = ctypes.c_int
+    L.heget_integrate_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                          ctypes.POINTER(heget_result), vp]
+    L.heget_integrate_noalloc.restype = ctypes.c_int
     L.heget_integrate_adaptive.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_uint64, ctypes.POINTER(heget_result),
                                            ctypes.POINTER(heget_result), ctypes.POINTER(ctypes.c_double),

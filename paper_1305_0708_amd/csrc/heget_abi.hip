@@ -425,6 +425,35 @@ __global__ __launch_bounds__(256) void reduce_partials(const double* partials, i
   heget::reduce_triples(partials, nblocks, out);
 }
 
+// Scratch of heget_integrate_noalloc: the per-block partial sums (w, w^2,
+// accepted) of one call and its three reduced sums, for callers that cannot
+// allocate.  Every GPU the library runs on holds its own copy (6 MiB) until the
+// process ends.  Host code must use the address hipGetSymbolAddress returns for
+// the current device, never the array's name.
+constexpr int64_t kNoAllocMaxBlocks = HEGET_NOALLOC_MAX_EVENTS / 256;
+__device__ __align__(256) double scratch[3 * kNoAllocMaxBlocks + 3];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array, looked up once per device.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 
@@ -688,6 +717,14 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
       return fail(HEGET_E_HIP, "upload of the colour tables failed");
     }
   }
+  {
+    // set-up of heget_integrate_noalloc's scratch on this device
+    double* sp = nullptr;
+    if (hipError_t e = scratch_address(&sp)) {
+      release(p);
+      return fail(HEGET_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+    }
+  }
   *out = p;
   return HEGET_OK;
 }
@@ -813,6 +850,42 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
   }
   if (rc != HEGET_OK) return rc;
   heget::detail::fill_result(p->h_res, n, out);
+  return HEGET_OK;
+}
+
+heget_status heget_integrate_noalloc(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
+                                     void* stream) {
+  g_err.clear();
+  if (!p || !out) return fail(HEGET_E_INVALID, "null argument");
+  if (n < 2) return fail(HEGET_E_INVALID, "need n >= 2 events");
+  if (n > HEGET_NOALLOC_MAX_EVENTS)
+    return fail(HEGET_E_INVALID, "n = " + std::to_string(n) + " exceeds the no-allocation limit of " +
+                                     std::to_string(int64_t(HEGET_NOALLOC_MAX_EVENTS)) + " events");
+  if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* d_part = nullptr;
+  HIP_TRY(scratch_address(&d_part));
+  const int64_t nblocks = (n + 255) / 256;
+  // every block writes its own partial triple and the reduction its three sums:
+  // nothing in the scratch has to start at zero
+  KernelArgs a = base_args(p);
+  a.n = n;
+  a.mom_stride = n;
+  a.seed = seed;
+  a.sqrt_s = sqrt_s;
+  a.weight_factor = heget::detail::weight_factor(p, sqrt_s);
+  a.partials = d_part;
+  heget_status rc = launch(p, a, st);
+  double h[3] = {0.0, 0.0, 0.0};
+  if (rc == HEGET_OK) {
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, d_part + 3 * nblocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d_part + 3 * nblocks, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate_noalloc: ") + hipGetErrorString(e));
+  }
+  if (rc != HEGET_OK) return rc;
+  heget::detail::fill_result(h, n, out);
   return HEGET_OK;
 }
 
