@@ -204,7 +204,11 @@ typedef struct {
   int64_t n_generated, n_accepted;
 } heget_result;
 
-/* Validate the IR, derive the couplings and propagator table from ir->sm,
+/* The process as the paper's amplitude generator hands it over (Sec. 5.1-5.2:
+ * the HEGET call sequence converted one to one from the HELAS calls, the
+ * process's particles, graphs and colour bases; Sec. 4: the external-line and
+ * vertex functions; Sec. 5.4: the colour matrix).
+ * Validate the IR, derive the couplings and propagator table from ir->sm,
  * upload the helicity table and bind the compiled kernel whose structure
  * (legs, calls, jamps, colour matrix) matches the IR.  prec selects FP64 or the
  * mixed path (FP32 wavefunctions, vertex chain and colour sum; FP64 momenta,
@@ -216,10 +220,16 @@ typedef struct {
  * allocates. */
 heget_status heget_process_create(const heget_process_ir* ir, heget_precision prec, heget_process_t* out);
 
-/* Release the handle and its device tables (synchronises the device first). */
+/* Release the handle and its device tables (synchronises the device first).
+ * No passage of the paper: resource release only. */
 heget_status heget_process_destroy(heget_process_t p);
 
-/* Evaluate n events on `stream` (asynchronous; hipStream_t passed as void*).
+/* The integrand of Sec. 2 at n phase-space points: for each point the squared
+ * amplitude summed over the helicities and colour indices of every external
+ * particle (Sec. 2, the LO partonic cross-section formula; the per-point
+ * evaluation one thread each, Sec. 3), from the external wavefunctions and
+ * vertex chain of Sec. 4 and the colour matrix of Sec. 5.4.
+ * Evaluate n events on `stream` (asynchronous; hipStream_t passed as void*).
  * momenta_in: device FP64 SoA [n_legs][4][n] physical momenta (E, px, py, pz),
  *   or NULL to generate them: incoming partons along +z / -z with energy
  *   sqrt_s / 2 each, final state by RAMBO from Philox4x32-10 with key `seed`
@@ -262,7 +272,12 @@ heget_status heget_generate(heget_process_t p, int64_t n, uint64_t seed, uint64_
 heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, int32_t n_u, double* u_out,
                             void* stream);
 
-/* Monte Carlo cross section from n events generated from `seed` (counters
+/* The LO partonic cross section of Sec. 2 (the flux, spin and colour averages
+ * and the integral of the summed squared amplitude over the n-body phase
+ * space) as a plain Monte Carlo estimate over points generated one per thread
+ * with no retry (Sec. 3); the paper integrates with BASES on the GPU (Sec. 6),
+ * whose adaptive grid heget_integrate_adaptive provides.
+ * Monte Carlo cross section from n events generated from `seed` (counters
  * 0 .. n-1) by the process's phase space (RAMBO or its resonance tree):
  * sigma = (1/N) sum_i w_i with w_i = dPhi_n,i * pass_i * F_i / (2 lambda^(1/2) N_pol n_a n_b S),
  * lambda^(1/2) = lambda^(1/2)(s, m_a^2, m_b^2) the flux of the incoming legs (s when
