@@ -42,7 +42,7 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "b40c3fc1f6ee5b67dccdc316e30018dfa79ed057ba53b95336d1c0b393be727a",
+COUNTERS_FP64 = {"source_digest": "4bdbfcbdca571f691e6da214d136e0d12ce4687624a426bc78953bc3f20b2d1d",
                  "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
                  "flop_per_event": 41174, "flop_per_event_mixed": 37949}
 
@@ -56,25 +56,29 @@ COUNTERS_FP64 = {"source_digest": "b40c3fc1f6ee5b67dccdc316e30018dfa79ed057ba53b
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "d1ccab3f7f392baaa6c66fbf9a0dcdcbb6d4e0a7cfb55aa67ad6629aba6095bb",
+        "source_digest": "56a9605993eb477b6ac08ebab86e8848849fb9381032f897239c92b22cb44a3f",
         "valu_flop_per_event": 45030, "fp64_flop_per_event": 2973, "events": 1 << 21, "kernel_s": 1.356e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "d1ccab3f7f392baaa6c66fbf9a0dcdcbb6d4e0a7cfb55aa67ad6629aba6095bb",
+        "source_digest": "56a9605993eb477b6ac08ebab86e8848849fb9381032f897239c92b22cb44a3f",
         "valu_flop_per_event": 48026, "events": 1 << 21, "kernel_s": 2.482e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "e0b956bacf914371dab169d45fb212339e16d1226719211d72b0a6fef498e92f",
-        "valu_flop_per_event": 4130384, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 190.8e-3,
+        "source_digest": "42b128e340daac72b6b49c54fea6134f5d56834f63350bc833606cef434deba7",
+        "valu_flop_per_event": 4130384, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 185.4e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "8ff2a066cb0632199efee22fe47d01d1e8f0191216be8d8728109381bec56ded",
-        "valu_flop_per_event": 4071824, "events": 1 << 20, "kernel_s": 107.7e-3,
+        "source_digest": "8abf8f5f99600faf61140712efa23eb4da3b2a5d5acd30958dc4ddf8f21f93c9",
+        "valu_flop_per_event": 4071824, "events": 1 << 20, "kernel_s": 104.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "8ff2a066cb0632199efee22fe47d01d1e8f0191216be8d8728109381bec56ded",
-        "valu_flop_per_event": 3492111, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 77.9e-3,
+        "source_digest": "8abf8f5f99600faf61140712efa23eb4da3b2a5d5acd30958dc4ddf8f21f93c9",
+        "valu_flop_per_event": 3492111, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 77.1e-3,
+        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
+    ("gg_4g_cf", "mixed"): {
+        "source_digest": "e668564ce3a5a92f33ecb7c389e667d2932d9d16fc321f7944091bd4c9a56bb9",
+        "valu_flop_per_event": 4480143, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 101.5e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 
@@ -302,10 +306,11 @@ def phase_space_leg(torch, proc, steps, warmup):
 
 
 SERVE_SEED = 0x48454749
-# the four configurations; the engine runs mixed precision, where C2 uses its
-# 24-flow DDM-basis kernel (same |M|^2; the 120-flow FP32 MFMA kernel is kept
-# off the GPU for now), the unbatched FP64 baseline the 120-flow MFMA kernel
-SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g_ddm", "ud_udhh_4b")
+# the four configurations; the engine runs mixed precision, where C2 keeps its
+# 120-flow trace basis with the colour matrix compressed to its distinct
+# factors (FP32 on VALU); the unbatched FP64 baseline runs the 120-flow dense
+# form on MFMA
+SERVE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g_cf", "ud_udhh_4b")
 SERVE_BASELINE_PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_4g", "ud_udhh_4b")
 SERVE_WEIGHTS = (40, 30, 20, 10)
 SERVE_SQRT_S = (200.0, 1000.0, 1000.0, 2000.0)
@@ -325,10 +330,20 @@ def serve_leg(n_requests, rate=200.0):
     serve.replay_unbatched(fp64, warm)
     _, eng = serve.replay_engine(srv, reqs)
     st = srv.stats()
+    # capacity: the same requests all at once (an arrival rate above any
+    # capacity), so the engine is never idle; the offered stream's utilisation
+    # is its event rate over that capacity
+    burst = [serve.Request(0.0, r.process, r.n, r.seed, r.sqrt_s) for r in reqs]
+    _, cap = serve.replay_engine(srv, burst)
     srv.close()
+    offered = sum(r.n for r in reqs) / reqs[-1].t_arrival
     _, base = serve.replay_unbatched(fp64, reqs)
     eng.update({"precision": "mixed", "launches": st["launches"], "segments": st["segments"],
-                "max_busy_slots": st["max_busy_slots"], "arena_high_water_bytes": st["arena_high_water"]})
+                "max_busy_slots": st["max_busy_slots"], "arena_high_water_bytes": st["arena_high_water"],
+                "offered_events_per_s": offered,
+                "capacity": {"events_per_s": cap["events_per_s"], "wall_s": cap["wall_s"], "p50_s": cap["p50_s"],
+                             "p99_s": cap["p99_s"], "kind": "every request submitted at t = 0"},
+                "utilisation": offered / cap["events_per_s"]})
     base.update({"precision": "fp64", "kind": "unbatched: one heget_integrate at a time in arrival order"})
     return {"workload": f"{n_requests} Poisson requests at {rate:g}/s over "
                         f"{'/'.join(SERVE_PROCESSES)} (baseline {'/'.join(SERVE_BASELINE_PROCESSES)}) "
@@ -343,7 +358,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests in the serving replay (0: skip it)")
     ap.add_argument("--profile-leg", choices=["fp64", "mixed"], default=None,
                     help="run only this precision's steps (for rocprofv3 of the dominant kernel)")
@@ -380,7 +395,7 @@ def main():
             return
         pir = processes.by_name(args.profile_proc)
         proc = H.Process(pir, precision=args.profile_leg)
-        n = {"gg_5g_ddm": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536}.get(args.profile_proc, N_EVENTS)
+        n = {"gg_5g_ddm": 1 << 16, "gg_5g_cf": 1 << 16, "gg_5g_split": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536}.get(args.profile_proc, N_EVENTS)
         wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
                "kernel_ms": kern * 1e3, "events_per_launch": n, "events_per_s": n / wall,
@@ -471,7 +486,15 @@ def main():
     line["seven_gluons"] = config_leg(
         torch, H, processes.by_name("gg_5g_ddm"), "g g -> g g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV, "
         "Delta R > 0.4, 2^16 events per step, 128 helicity combinations, 120 DDM colour flows on MFMA",
-        3, 1, n=1 << 16)
+        3, 1, n=1 << 16, precisions=("fp64",))
+    line["seven_gluons"]["split"] = config_leg(
+        torch, H, processes.by_name("gg_5g_split"), "the same FP64 program divided into two kernels (the orderings' "
+        "amplitudes to the workspace, then the colour form), launched per round of resident blocks", 3, 1,
+        n=1 << 16, precisions=("fp64",))
+    line["seven_gluons"]["compressed"] = config_leg(
+        torch, H, processes.by_name("gg_5g_cf"), "the same, the 120 x 120 colour matrix compressed to its 14 "
+        "distinct factors (1,318 multiplications per form); mixed precision on VALU", 3, 1, n=1 << 16,
+        precisions=("mixed",))
     # the other configured workloads, each with the oracle timed beside it on a
     # sample of its events and the GPU's error against the oracle on that sample
     import oracle as O
@@ -489,6 +512,11 @@ def main():
         torch, H, c2, "g g -> g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV and Delta R > 0.4 by rejection, 2^20 RAMBO "
         "events per step, 64 helicity combinations, 120 trace-basis flows, dense 120 x 120 colour form on MFMA",
         args.steps, args.warmup, seed=0x48454747)
+    legs["c2"]["compressed"] = config_leg(
+        torch, H, processes.by_name("gg_4g_cf"), "the same events through the same 120 trace-basis flows, the colour "
+        "matrix compressed to its 15 distinct factors (1,509 multiplications per form instead of 7,260 "
+        "multiply-adds); mixed precision runs it on VALU, FP64 keeps the dense MFMA form", args.steps, args.warmup,
+        precisions=("mixed",), seed=0x48454747)
     legs["c2"]["ddm_basis"] = config_leg(
         torch, H, c2d, "the same events and |M|^2 through the 24-flow DDM basis, colour form on VALU",
         args.steps, args.warmup, seed=0x48454747)
@@ -496,6 +524,9 @@ def main():
         legs["c2"]["oracle"] = oracle_leg(torch, H, O, c2, "GG_4G", {}, 4, 0x48454747, cut=(20.0, 0.4))
         legs["c2"]["ddm_basis"]["oracle"] = oracle_leg(torch, H, O, c2d, "GG_4G", {}, 4, 0x48454747,
                                                        cut=(20.0, 0.4), target_seconds=1.0)
+        legs["c2"]["compressed"]["oracle"] = oracle_leg(torch, H, O, processes.by_name("gg_4g_cf"), "GG_4G", {}, 4,
+                                                        0x48454747, cut=(20.0, 0.4), target_seconds=1.0,
+                                                        precisions=("mixed",))
     c3 = processes.ud_udhh_4b()
     legs["c3"] = config_leg(
         torch, H, c3, "u d -> u d H H (W W and Z Z fusion), H -> b bbar, sqrt_s_hat = 2 TeV, 2^21 RAMBO events "

@@ -193,6 +193,18 @@ typedef struct {
    * collision at fixed sqrt_s (rest frame).  Part of the kernel's structure. */
   double ps_hadron_ymax;
   double ps_hadron_ptmin;
+  /* Colour form of the compiled kernel: 0 dense (the colour matrix as given;
+   * on MFMA for templates with n_flows >= 32), 1 compressed (Sec. 5.4: each
+   * row's entries grouped by their distinct colour factors, one multiplication
+   * per factor and row, on VALU; FP64 kernels of bases with n_flows >= 32 keep
+   * the dense MFMA form).  Part of the kernel's structure. */
+  int32_t colour_form;
+  /* Division of the amplitude program (Sec. 5.3): 0 fused (one kernel), 1 split
+   * (ordering templates only: the orderings' amplitudes in one kernel, written
+   * to the handle's workspace, the colour form and the weights in a second one,
+   * the two launched one after the other for each round of resident blocks).
+   * Part of the kernel's structure. */
+  int32_t division;
 } heget_process_ir;
 
 typedef struct heget_process* heget_process_t;

@@ -66,7 +66,8 @@ class _IRBuffers:
             len(orders), self.orders if orders else None, self.flow_map if flat_m else None,
             len(tree), self.ps_nodes if tree else None, float(proc.ps_window),
             float(proc.ps_hadronic[0]) if proc.ps_hadronic else 0.0,
-            float(proc.ps_hadronic[1]) if proc.ps_hadronic else 0.0)
+            float(proc.ps_hadronic[1]) if proc.ps_hadronic else 0.0,
+            ir.COLOUR_FORMS[proc.colour_form], ir.DIVISIONS[proc.division])
 
 
 def uniforms(n, n_u, seed=0, counter_offset=0, stream=None):

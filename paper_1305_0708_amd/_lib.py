@@ -61,7 +61,8 @@ class heget_process_ir(ctypes.Structure):
                 ("flow_map", ctypes.POINTER(ctypes.c_int8)),
                 ("n_ps_nodes", ctypes.c_int32), ("ps_nodes", ctypes.POINTER(heget_ps_node)),
                 ("ps_window", ctypes.c_double), ("ps_hadron_ymax", ctypes.c_double),
-                ("ps_hadron_ptmin", ctypes.c_double)]
+                ("ps_hadron_ptmin", ctypes.c_double), ("colour_form", ctypes.c_int32),
+                ("division", ctypes.c_int32)]
 
 
 class heget_result(ctypes.Structure):

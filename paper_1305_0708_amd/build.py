@@ -20,7 +20,8 @@ FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", CSRC, "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
-PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "gg_ttbar_6f_had", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm")
+PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "gg_ttbar_6f_had", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm",
+             "gg_4g_cf", "gg_5g_cf", "gg_5g_split")
 
 
 def generate_sources():

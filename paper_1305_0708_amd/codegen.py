@@ -46,6 +46,10 @@ TEMPLATE_EARLY_VERTEX_SUM = True
 TEMPLATE_EARLY_CURRENT_SUMS = True
 # MFMA colour form: 16-event chunks of a wave per pass (each fragment load serves them all)
 COLOUR_CHUNKS = 2
+# MFMA colour form: the fragments of the triangle held in registers for the whole
+# colour-form phase (loaded once per block of events) instead of streamed from L2
+# for every chunk and helicity
+COLOUR_RESIDENT = True
 # amplitude rows of the MFMA colour form above this many bytes (FP64) are not
 # staged in LDS: the workspace holds them in the colour form's layout
 DIRECT_ROWS_BYTES = 128 * 1024
@@ -145,7 +149,14 @@ class Gen:
         tree = p.ps_tree is not None
         if tree:
             self._emit_ps_tree(w)
-        w("template <class T>")
+        split = p.division == "split"
+        self._split = split
+        if split:
+            w("// PHASE 0: the whole program; 1: the orderings' amplitudes only (to the")
+            w("// workspace); 2: the colour form and the outputs only (from the workspace)")
+            w("template <class T, int PHASE = 0>")
+        else:
+            w("template <class T>")
         w(f"__device__ __forceinline__ void body_{p.name}(const KernelArgs& a, int64_t blk) {{")
         w("  const int64_t i = blk * blockDim.x + threadIdx.x;")
         w("  const bool active = i < a.n;")
@@ -168,7 +179,10 @@ class Gen:
         else:
             w(f"      rambo<{self.nout}>(a.seed, a.counter_offset + uint64_t(i), a.sqrt_s, p + 2);")
         w("    }")
-        w("    if (a.mom_out) store_momenta<%d>(a, i, p);" % self.nl)
+        if split:
+            w("    if (PHASE != 2 && a.mom_out) store_momenta<%d>(a, i, p);" % self.nl)
+        else:
+            w("    if (a.mom_out) store_momenta<%d>(a, i, p);" % self.nl)
         w("  } else {")
         w("#pragma unroll")
         w(f"    for (int k = 0; k < {self.nl}; ++k) p[k] = {{1.0, 0.0, 0.0, 1.0}};")
@@ -197,10 +211,14 @@ class Gen:
             self._emit_ordered(w)
         else:
             self._emit_straight(w)
+        if split:
+            w("  if constexpr (PHASE != 1) {")
         w("  if (a.me2_out && active) a.me2_out[i] = me2;")
         if tree:
             w("  if (a.w_out && active) a.w_out[i] = pass ? me2 * a.weight_factor * psw : 0.0;")
         w(f"  if (a.partials) block_partials(a, blk, pass ? me2 * a.weight_factor{' * psw' if tree else ''} : 0.0, pass);")
+        if split:
+            w("  }")
         w("}")
         w("")
         if self.ordered:
@@ -216,6 +234,21 @@ class Gen:
             w("    __syncthreads();")
             w("  }")
             w("}")
+            if split:
+                w("")
+                w("// split division: block b of a round evaluates block block_base + b of the")
+                w("// launch into workspace slot b (the orderings' amplitudes), then the")
+                w("// colour-form kernel of the same round reads that slot")
+                w("template <class T>")
+                w(f"__global__ __launch_bounds__(256) void amp_{p.name}_chain(KernelArgs a) {{")
+                w(f"  body_{p.name}<T, 1>(a, a.block_base + blockIdx.x);")
+                w("}")
+                w("template <class T>")
+                w(f"__global__ __launch_bounds__(256) void amp_{p.name}_colour(KernelArgs a) {{")
+                if p.uses_colour_mfma():
+                    w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
+                w(f"  body_{p.name}<T, 2>(a, a.block_base + blockIdx.x);")
+                w("}")
         else:
             w("// one launch: block b evaluates events 256 b ... 256 b + 255")
             w("template <class T>")
@@ -267,7 +300,13 @@ class Gen:
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
           f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}, '
-          f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}, {self.ps_dims()}}};')
+          f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}, {self.ps_dims()}, '
+          f'{int(p.mixed_uses_mfma())}, '
+          + (f'reinterpret_cast<const void*>(&amp_{p.name}_chain<double>), '
+             f'reinterpret_cast<const void*>(&amp_{p.name}_chain<float>), '
+             f'reinterpret_cast<const void*>(&amp_{p.name}_colour<double>), '
+             f'reinterpret_cast<const void*>(&amp_{p.name}_colour<float>)'
+             if p.division == "split" else 'nullptr, nullptr, nullptr, nullptr') + '};')
         w("static const Registrar reg(&entry);")
         w("")
         w("}  // namespace heget")
@@ -443,7 +482,7 @@ class Gen:
         for c in p.calls:
             self._call(w, c, "      ")
         self._jamps(w, "      ")
-        self._colour(w, lambda f: f"J{f}")
+        self._colour_form(w, lambda f: f"J{f}")
         w("    }")
         w("  }")
 
@@ -523,7 +562,7 @@ class Gen:
                 else:
                     self._nest_item(w, it, ind)
             self._emit_tables(w, sc, tables, ind, lvl)
-        self._colour(w, lambda f: f"J{f}", ind)
+        self._colour_form(w, lambda f: f"J{f}", ind)
         for L in reversed(sc.order):
             if len(sc.choices[L]) > 1:
                 ind = ind[:-2]
@@ -798,6 +837,8 @@ class Gen:
             w("  // this block's workspace slot: A[o][h][256] of its events")
         w("  cx<T>* const work = static_cast<cx<T>*>(a.work) + size_t(blockIdx.x) * size_t(a.work_stride);")
         w("  const int nh = a.n_hel;")
+        if self._split:
+            w("  if constexpr (PHASE != 2) {")
         w("  if (pass) {")
         w("#pragma unroll 1")
         w(f"    for (int o = 0; o < {no}; ++o) {{")
@@ -838,8 +879,44 @@ class Gen:
             w("    for (int h = 0; h < nh; ++h)")
             w(f"      for (int r = 0; r < {2 * no}; ++r) wr[(size_t(h) * {2 * no} + r) * 256] = T(0);")
         w("  }")
+        if self._split:
+            w("  }")
         w("  double me2 = 0.0;")
-        if mf and self._direct_rows:
+        if self._split:
+            w("  if constexpr (PHASE != 1) {")
+        self._emit_colour_phase(w, mf, no)
+        if self._split:
+            w("  }")
+
+    def _emit_colour_phase(self, w, mf, no):
+        """phase 2 of an ordering template: the colour form per helicity over the
+        orderings' amplitudes in the workspace"""
+        p = self.p
+        if mf and p.colour_form == "compressed":
+            # FP32: the compressed colour form on VALU (no MFMA in the FP32 kernel);
+            # FP64: the dense MFMA form (the flows' FP64 values would not fit registers)
+            w("  if constexpr (sizeof(T) == 4) {")
+            self._emit_valu_colour_from_work(w)
+            w("  } else {")
+            self._emit_mfma_colour(w)
+            w("  }")
+        elif mf:
+            self._emit_mfma_colour(w)
+        else:
+            w("  if (pass) {")
+            w("    for (int h = 0; h < nh; ++h) {")
+            for o in range(no):
+                w(f"      const cx<T> A{o} = work[(size_t({o}) * nh + h) * 256 + threadIdx.x];")
+            self._colour_form(w, lambda f: f"A{f}")
+            w("    }")
+            w("  }")
+
+    def _emit_mfma_colour(self, w):
+        """the MFMA colour form over the orderings' amplitudes in the workspace
+        (direct rows) or staged per helicity in LDS rows"""
+        p = self.p
+        no = len(p.orderings)
+        if self._direct_rows:
             nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
             w("  // the MFMA colour form needs every lane of the wavefront; it reads the wave's")
             w("  // columns of the workspace rows, written above by the wave's own lanes")
@@ -848,14 +925,24 @@ class Gen:
             w("    __builtin_amdgcn_wave_barrier();")
             w("    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\");")
             w("    const T* const rows = reinterpret_cast<const T*>(work);")
-            w("    for (int h = 0; h < nh; ++h)")
-            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
-              f"(rows + size_t(h) * {2 * no * 256}, a.cstep, a));")
+            if COLOUR_RESIDENT:
+                w(f"    ResidentFrags<T, {nks}, {nfo}> fr;")
+                w("    fr.load(a.cfrag);")
+                w("    for (int h = 0; h < nh; ++h)")
+                w(f"      me2 += double(colour_form_resident<T, {nks}, {nfo}, {self.cterm_cap()}>"
+                  f"(fr, rows + size_t(h) * {2 * no * 256}, a.cstep));")
+            else:
+                w("    for (int h = 0; h < nh; ++h)")
+                w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
+                  f"(rows + size_t(h) * {2 * no * 256}, a.cstep, a));")
             w("  }")
-        elif mf:
+        else:
             nks, nfo = (p.n_flows + 3) // 4, (p.n_flows + 15) // 16
             w("  // the MFMA colour form needs every lane of the wavefront: failed lanes take part with zeros")
             w("  if (__any(pass)) {")
+            if COLOUR_RESIDENT:
+                w(f"    ResidentFrags<T, {nks}, {nfo}> fr;")
+                w("    fr.load(a.cfrag);")
             w("    for (int h = 0; h < nh; ++h) {")
             w(f"      for (int o = 0; o < {no}; ++o) {{")
             w("        const cx<T> v = pass ? work[(size_t(o) * nh + h) * 256 + threadIdx.x] : cx<T>{T(0), T(0)};")
@@ -865,19 +952,41 @@ class Gen:
             w("      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");")
             w("      __builtin_amdgcn_wave_barrier();")
             w("      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");")
-            w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
-              f"(&lds_rows[0][0], a.cstep, a));")
+            if COLOUR_RESIDENT:
+                w(f"      me2 += double(colour_form_resident<T, {nks}, {nfo}, {self.cterm_cap()}>"
+                  f"(fr, &lds_rows[0][0], a.cstep));")
+            else:
+                w(f"      me2 += double(colour_form_mfma<T, {nks}, {nfo}, {self.cterm_cap()}, {COLOUR_CHUNKS}>"
+                  f"(&lds_rows[0][0], a.cstep, a));")
             w("      __builtin_amdgcn_wave_barrier();")
             w("    }")
             w("  }")
+
+    def _emit_valu_colour_from_work(self, w):
+        """the VALU colour form of the IR over the orderings' amplitudes in the
+        workspace, flows formed through the flow map (FP32 kernels of MFMA-sized
+        bases with the compressed form)"""
+        p = self.p
+        no = len(p.orderings)
+        w("    if (pass) {")
+        w("      const T* const rows = reinterpret_cast<const T*>(work);")
+        w("      for (int h = 0; h < nh; ++h) {")
+        for o in range(no):
+            if self._direct_rows:
+                w(f"        const cx<T> A{o} = {{rows[(size_t(h) * {2 * no} + {2 * o}) * 256 + threadIdx.x], "
+                  f"rows[(size_t(h) * {2 * no} + {2 * o + 1}) * 256 + threadIdx.x]}};")
+            else:
+                w(f"        const cx<T> A{o} = work[(size_t({o}) * nh + h) * 256 + threadIdx.x];")
+        if p.flow_map is not None:
+            for f, row in enumerate(p.flow_map):
+                terms = [_coef_expr(c, f"A{o}") for o, c in enumerate(row) if c]
+                w(f"        const cx<T> J{f} = {' + '.join(terms)};")
+            J = lambda f: f"J{f}"
         else:
-            w("  if (pass) {")
-            w("    for (int h = 0; h < nh; ++h) {")
-            for o in range(no):
-                w(f"      const cx<T> A{o} = work[(size_t({o}) * nh + h) * 256 + threadIdx.x];")
-            self._colour(w, lambda f: f"A{f}")
-            w("    }")
-            w("  }")
+            J = lambda f: f"A{f}"
+        self._colour_form(w, J, ind="        ")
+        w("      }")
+        w("    }")
 
     def _work_store(self, h, value):
         """store of ordering o's amplitude at helicity h in the workspace slot"""
@@ -1263,8 +1372,43 @@ class Gen:
         w(f"{ind}me2 += double(cs) * {_c(Fraction(1, den))};")
 
 
+    def _colour_compressed(self, w, J, ind="      "):
+        """me2 += Re(J^dagger C J) with the rows of C decomposed into their
+        distinct colour factors (the paper's Sec. 5.4): row f sums the flows
+        g >= f that share a factor first, then multiplies each such sum once,
+        T_f = sum_k c_k (sum over g >= f with C'_fg = c_k of J_g), where C' is C
+        on the diagonal and 2 C above it; |M|^2 = sum_f Re(J_f^* T_f)."""
+        p = self.p
+        den = p.colour_denominator()
+        n = p.n_flows
+        w(f"{ind}T cs = T(0);")
+        for f in range(n):
+            groups = {}
+            for g in range(f, n):
+                v = Fraction(p.colour[f][g]) * den * (1 if g == f else 2)
+                if v != 0:
+                    groups.setdefault(v, []).append(g)
+            if not groups:
+                continue
+            w(f"{ind}{{")
+            w(f"{ind}  cx<T> t = {{T(0), T(0)}};")
+            for v, gs in groups.items():
+                w(f"{ind}  t = t + T({_c(v)}) * ({' + '.join(J(g) for g in gs)});")
+            w(f"{ind}  cs += {J(f)}.r * t.r + {J(f)}.i * t.i;")
+            w(f"{ind}}}")
+        w(f"{ind}me2 += double(cs) * {_c(Fraction(1, den))};")
+
+    def _colour_form(self, w, J, ind="      "):
+        """the IR's colour form on VALU"""
+        if self.p.colour_form == "compressed":
+            self._colour_compressed(w, J, ind)
+        else:
+            self._colour(w, J, ind)
+
+
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-_DEVICE_HEADERS = ("generated_common.hpp", "heget_device.hpp", "kernel_args.hpp", "phase_space.hpp")
+_DEVICE_HEADERS = ("generated_common.hpp", "heget_device.hpp", "kernel_args.hpp", "phase_space.hpp",
+                   "colour_mfma.hpp")
 
 
 def source_digest(proc):

@@ -177,4 +177,96 @@ __device__ inline T colour_form_mfma(const T* jl, const int* cstep, const Kernel
   return result;
 }
 
+// Number of colour fragments of the upper triangle of 16 x 16 blocks: output
+// tile fo reads the k-steps 4 fo .. NKS - 1.
+constexpr int tri_fragments(int nks, int nfo) {
+  int n = 0;
+  for (int fo = 0; fo < nfo; ++fo) n += nks > 4 * fo ? nks - 4 * fo : 0;
+  return n;
+}
+constexpr int tri_offset(int nks, int fo) {
+  int n = 0;
+  for (int f = 0; f < fo; ++f) n += nks > 4 * f ? nks - 4 * f : 0;
+  return n;
+}
+
+// The colour fragments of the triangle, one value per lane each, held in
+// registers for a whole colour-form phase (every helicity and every chunk of
+// the wave's events reuses them); loaded once per phase from the table built at
+// process creation ([nfo][nks][64], the lower blocks zero and never read).
+template <class T, int NKS, int NFO>
+struct ResidentFrags {
+  static constexpr int kCount = tri_fragments(NKS, NFO);
+  T v[kCount];
+  __device__ __forceinline__ void load(const void* cfrag) {
+    const T* f = static_cast<const T*>(cfrag);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int fo = 0; fo < NFO; ++fo)
+#pragma unroll
+      for (int s = 4 * fo; s < NKS; ++s) v[tri_offset(NKS, fo) + s - 4 * fo] = f[(fo * NKS + s) * 64 + lane];
+  }
+};
+
+// The same quadratic form as colour_form_mfma, with the fragments taken from
+// registers: per 16-event chunk the B operands of every k-step are gathered
+// once, then the output tiles run in pairs (four independent accumulations)
+// over the resident fragments.  Every lane of the wavefront must call it.
+template <class T, int NKS, int NFO, int NTERM>
+__device__ inline T colour_form_resident(const ResidentFrags<T, NKS, NFO>& fr, const T* jl, const int* cstep) {
+  static_assert(NKS >= 1 && NKS <= 4 * NFO, "k-steps must fit the output tiles");
+  const uint32_t* terms = ColourLds<T, NTERM>::term();
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, col = lane & 15;
+  const int wbase = tid - lane;
+  T result = T(0);
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int ev = wbase + 16 * c + col;
+    T xr[4 * NFO], xi[4 * NFO];
+#pragma unroll
+    for (int s = 0; s < 4 * NFO; ++s) {
+      xr[s] = T(0);
+      xi[s] = T(0);
+      if (s < NKS) {
+        const int nt = __builtin_amdgcn_readfirstlane(cstep[2 * s]);
+        const int off = __builtin_amdgcn_readfirstlane(cstep[2 * s + 1]);
+        for (int t = 0; t < nt; ++t) {
+          const uint32_t e = terms[4 * (off + t) + g];
+          const int o = int(e & 0xffffu);
+          const T cf = T(int(int16_t(uint16_t(e >> 16))));
+          xr[s] += cf * jl[(2 * o) * 256 + ev];
+          xi[s] += cf * jl[(2 * o + 1) * 256 + ev];
+        }
+      }
+    }
+    T part = T(0);
+#pragma unroll
+    for (int fo = 0; fo < NFO; fo += 2) {
+      const bool two = fo + 1 < NFO;
+      typename Mfma<T>::acc zr0{T(0), T(0), T(0), T(0)}, zi0 = zr0, zr1 = zr0, zi1 = zr0;
+#pragma unroll
+      for (int s = 4 * fo; s < NKS; ++s) {
+        const T a0 = fr.v[tri_offset(NKS, fo) + s - 4 * fo];
+        zr0 = Mfma<T>::step(a0, xr[s], zr0);
+        zi0 = Mfma<T>::step(a0, xi[s], zi0);
+        if (two && s >= 4 * (fo + 1)) {
+          const T a1 = fr.v[tri_offset(NKS, fo + 1) + s - 4 * (fo + 1)];
+          zr1 = Mfma<T>::step(a1, xr[s], zr1);
+          zi1 = Mfma<T>::step(a1, xi[s], zi1);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part += zr0[r] * xr[4 * fo + r] + zi0[r] * xi[4 * fo + r];
+      if (two) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part += zr1[r] * xr[4 * fo + 4 + r] + zi1[r] * xi[4 * fo + 4 + r];
+      }
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == c) result = part;
+  }
+  return result;
+}
+
 }  // namespace heget

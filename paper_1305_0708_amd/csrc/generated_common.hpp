@@ -27,6 +27,12 @@ struct GenEntry {
   int cterm_cap;              // capacity of the kernel's LDS term table (words)
   const void* generate;       // the process's own phase-space kernel (resonance tree), or null (RAMBO)
   int ps_dims;                // uniforms per event of the resonance tree (0: RAMBO)
+  int colour_mfma_mixed;      // 1: the FP32 (mixed) kernel's colour form runs on MFMA too
+  // split division: the orderings' kernels and the colour-form kernels (null when fused)
+  const void* chain_fp64;
+  const void* chain_mixed;
+  const void* colour_fp64;
+  const void* colour_mixed;
 };
 
 // The launch arguments of one request's segment in a fused launch.

@@ -124,6 +124,10 @@ uint64_t fingerprint(const heget_process_ir* ir) {
     H.f64(ir->ps_hadron_ymax);
     H.f64(ir->ps_hadron_ptmin);
   }
+  if (ir->colour_form != 0 || ir->division != 0) {
+    H.i32(ir->colour_form);
+    H.i32(ir->division);
+  }
   return H.h;
 }
 
@@ -144,6 +148,9 @@ const OpSig kSig[HEGET_N_OPS] = {
 };
 
 heget_status validate(const heget_process_ir* ir) {
+  if (ir->colour_form != 0 && ir->colour_form != 1) return fail(HEGET_E_IR, "unknown colour form");
+  if (ir->division != 0 && ir->division != 1) return fail(HEGET_E_IR, "unknown division");
+  if (ir->division == 1 && ir->n_orderings == 0) return fail(HEGET_E_IR, "the split division needs orderings");
   if (ir->n_legs < 3 || ir->n_legs > 12 || !ir->legs) return fail(HEGET_E_IR, "n_legs must be 3..12");
   if (!ir->legs[0].incoming || !ir->legs[1].incoming)
     return fail(HEGET_E_IR, "legs 0 and 1 must be the incoming partons");
@@ -462,8 +469,26 @@ heget_status heget::detail::launch(heget_process_t p, KernelArgs& a, hipStream_t
   const int block = 256;
   int64_t grid = (a.n + block - 1) / block;
   if (grid > 0x7fffffff) return fail(HEGET_E_INVALID, "n too large for one launch");
-  if (p->entry->persistent) grid = std::min<int64_t>(grid, p->grid_cap);   // one workspace slot per block
-  const void* fn = p->prec == HEGET_FP64 ? p->entry->kernel_fp64 : p->entry->kernel_mixed;
+  const GenEntry* e = p->entry;
+  if (e->chain_fp64) {
+    // split division: per round of resident blocks (one workspace slot each), the
+    // orderings' kernel then the colour-form kernel, in order on the stream
+    const bool f64 = p->prec == HEGET_FP64;
+    const void* chain = f64 ? e->chain_fp64 : e->chain_mixed;
+    const void* colour = f64 ? e->colour_fp64 : e->colour_mixed;
+    const int64_t nb = grid;
+    for (int64_t base = 0; base < nb; base += p->grid_cap) {
+      const int64_t g = std::min<int64_t>(p->grid_cap, nb - base);
+      a.block_base = base;
+      void* args[] = {&a};
+      HIP_TRY(hipLaunchKernel(chain, dim3(unsigned(g)), dim3(block), args, 0, stream));
+      HIP_TRY(hipLaunchKernel(colour, dim3(unsigned(g)), dim3(block), args, 0, stream));
+    }
+    a.block_base = 0;
+    return HEGET_OK;
+  }
+  if (e->persistent) grid = std::min<int64_t>(grid, p->grid_cap);   // one workspace slot per block
+  const void* fn = p->prec == HEGET_FP64 ? e->kernel_fp64 : e->kernel_mixed;
   void* args[] = {&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(block), args, 0, stream));
   return HEGET_OK;
@@ -630,7 +655,7 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   // accesses on the GPU (an FP32 colour form over FP32 rows, and an FP32 chain
   // feeding an FP64 colour form) with no cause found in their code: refused
   // until one is, so that no caller launches them.
-  if (prec == HEGET_MIXED && entry->colour_mfma)
+  if (prec == HEGET_MIXED && entry->colour_mfma_mixed)
     return fail(HEGET_E_UNSUPPORTED, "mixed precision is switched off for processes whose colour form runs on "
                 "MFMA (an unexplained GPU fault); use FP64, or a basis with the VALU colour form");
   heget_process* p = new heget_process();
@@ -683,6 +708,12 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
     // ordering amplitudes of every resident block's 256 events, all orderings and helicities
     p->n_orderings = ir->n_orderings;
     p->grid_cap = heget::detail::resident_blocks(prec == HEGET_FP64 ? entry->kernel_fp64 : entry->kernel_mixed);
+    if (entry->chain_fp64) {
+      // split: both kernels of a round must fit the workspace's slots
+      const bool f64 = prec == HEGET_FP64;
+      p->grid_cap = std::min(heget::detail::resident_blocks(f64 ? entry->chain_fp64 : entry->chain_mixed),
+                             heget::detail::resident_blocks(f64 ? entry->colour_fp64 : entry->colour_mixed));
+    }
     p->work_stride = int64_t(ir->n_orderings) * ir->n_hel * 256;
     const size_t wb = size_t(p->grid_cap) * size_t(p->work_stride) * heget::detail::complex_bytes(p);
     if (hipMalloc(&p->d_work, wb) != hipSuccess) {

@@ -53,6 +53,7 @@ struct KernelArgs {
   const BatchTable* batch;   // fused launches of the serving engine, else null
   void* work;                // persistent kernels: gridDim.x slots of work_stride complex values
   int64_t work_stride;       //   (ordering amplitudes [n_orderings][n_hel][256] per block)
+  int64_t block_base;        // split kernels: the launch's block b evaluates events of block block_base + b
 };
 
 // One request's share of a fused launch: virtual blocks [block_begin, next

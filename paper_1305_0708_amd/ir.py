@@ -43,6 +43,8 @@ OUT_KIND = {"fvi": F, "fvo": F, "jio": V, "fsi": F, "fso": F, "hio": S, "jvv": V
 # ops whose output carries the momentum of their first input (not the sum)
 LINEAR_OPS = {"vadd", "vsub"}
 MFMA_MIN_FLOWS = 32
+COLOUR_FORMS = {"dense": 0, "compressed": 1}
+DIVISIONS = {"fused": 0, "split": 1}
 # input kinds per op (in argument order)
 IN_KINDS = {
     "iov": (F, F, V), "fvi": (F, V), "fvo": (F, V), "jio": (F, F),
@@ -157,11 +159,28 @@ class Process:
     # at the hadronic sqrt_s, its two daughters generated in rapidity within
     # +-y_max, ln(m^2 + pT^2) from pt_min and azimuth; x_a, x_b follow.
     ps_hadronic: Optional[Tuple[float, float]] = None
+    # Colour form of the code generator: "dense" (the colour matrix as it is) or
+    # "compressed" (the paper's Sec. 5.4 decomposition: each row's entries
+    # grouped by their distinct colour factors, one multiplication per factor
+    # and row).  The compressed form runs on VALU with the flows' values in
+    # registers: in FP32 always, in FP64 where they fit (bases below
+    # MFMA_MIN_FLOWS flows; larger FP64 bases keep the dense MFMA form).
+    colour_form: str = "dense"
+    # Division of the amplitude program (the paper's Sec. 5.3): "fused" (one
+    # kernel) or "split" (ordering templates: the orderings' amplitudes in one
+    # kernel, written to device memory, the colour form in a second one,
+    # launched one after the other per round of resident blocks).
+    division: str = "fused"
 
     def uses_colour_mfma(self):
-        """The colour quadratic form runs on MFMA for ordering templates with
-        at least MFMA_MIN_FLOWS flows; small colour bases stay on VALU."""
+        """The FP64 colour quadratic form runs on MFMA for ordering templates
+        with at least MFMA_MIN_FLOWS flows; small colour bases stay on VALU."""
         return self.orderings is not None and self.n_flows >= MFMA_MIN_FLOWS
+
+    def mixed_uses_mfma(self):
+        """The FP32 (mixed-precision) colour form runs on MFMA: the dense form of
+        an MFMA-sized basis; the compressed form never does."""
+        return self.uses_colour_mfma() and self.colour_form == "dense"
 
     @property
     def n_legs(self):
@@ -182,6 +201,12 @@ class Process:
         return d
 
     def validate(self):
+        if self.colour_form not in COLOUR_FORMS:
+            raise ValueError(f"unknown colour form {self.colour_form}")
+        if self.division not in DIVISIONS:
+            raise ValueError(f"unknown division {self.division}")
+        if self.division == "split" and self.orderings is None:
+            raise ValueError("the split division applies to ordering templates")
         kinds = {i: leg.kind for i, leg in enumerate(self.legs)}
         amps = set()
         for k, c in enumerate(self.calls):
@@ -312,6 +337,9 @@ class Process:
             i32(1)
             f64(self.ps_hadronic[0])
             f64(self.ps_hadronic[1])
+        if self.colour_form != "dense" or self.division != "fused":
+            i32(COLOUR_FORMS[self.colour_form])
+            i32(DIVISIONS[self.division])
         return bytes(b)
 
     def fingerprint(self):

@@ -263,6 +263,20 @@ def by_name(name):
     if name in gluon:
         # the colour matrices of the larger bases take seconds to build: built once, copied out
         return copy.deepcopy(_gluons(*gluon[name]))
+    # the same processes with the colour form compressed to its distinct colour
+    # factors (Sec. 5.4): the FP32 kernels run it on VALU
+    compressed = {"gg_4g_cf": "gg_4g", "gg_5g_cf": "gg_5g_ddm"}
+    if name in compressed:
+        p = by_name(compressed[name])
+        p.name, p.colour_form = name, "compressed"
+        return p.validate()
+    # the amplitude program divided into two kernels (Sec. 5.3): the orderings'
+    # amplitudes, then the colour form
+    split = {"gg_5g_split": "gg_5g_ddm"}
+    if name in split:
+        p = by_name(split[name])
+        p.name, p.division = name, "split"
+        return p.validate()
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
             "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww,
             "gg_ttbar_6f_had": gg_ttbar_6f_had}[name]()

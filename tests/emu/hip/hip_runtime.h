@@ -23,6 +23,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) __attribute__((aligned(n)))
 
 struct dim3 {
   unsigned x, y, z;
@@ -79,6 +80,7 @@ typedef enum hipError_t {
   hipSuccess = 0,
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
+  hipErrorInvalidDevice = 101,
   hipErrorLaunchFailure = 719
 } hipError_t;
 typedef struct emu_stream* hipStream_t;
@@ -115,4 +117,7 @@ const char* hipGetErrorString(hipError_t e);
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int dev);
 hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* f, int block, size_t shmem);
 hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void** args, size_t shmem, hipStream_t s);
+// a __device__ variable is host memory here: its address is the symbol's
+#define HIP_SYMBOL(x) (&(x))
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 #define hipLaunchKernelGGL(k, g, b, sh, st, ...) emu::launch(dim3(g), dim3(b), [=]() { k(__VA_ARGS__); })

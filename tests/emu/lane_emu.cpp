@@ -361,6 +361,10 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int
   *n = 1;
   return hipSuccess;
 }
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void** args, size_t, hipStream_t) {
   using K = void (*)(heget::KernelArgs);
   K k = reinterpret_cast<K>(const_cast<void*>(f));

@@ -40,6 +40,7 @@ X_ORACLE = {
     "gg_ttbar_6f_bw": 7.3e-13,
 }
 X_ORACLE["gg_4g_ddm"] = X_ORACLE["gg_4g"]
+X_ORACLE["gg_4g_cf"] = X_ORACLE["gg_4g"]
 
 
 def _ladder(x):
@@ -58,7 +59,8 @@ def bound(name):
 
 BOUND = {name: bound(name) for name in X_ORACLE}
 # share of the parity events that must also be within 1e-12
-SHARE = {"ee_mumu": 1.0, "gg_ttbar_6f": 0.99, "gg_4g": 0.99, "gg_4g_ddm": 0.99, "ud_udhh_4b": 0.98,
+SHARE = {"ee_mumu": 1.0, "gg_ttbar_6f": 0.99, "gg_4g": 0.99, "gg_4g_ddm": 0.99, "gg_4g_cf": 0.99,
+         "ud_udhh_4b": 0.98,
          "ud_udhhh": 0.75, "ww_ww": 0.99, "gg_ttbar_6f_had": 0.25, "gg_ttbar_6f_bw": 0.99}
 
 # ---------------------------------------------------------------- event sets
@@ -68,6 +70,7 @@ RAMBO = {   # name -> (oracle id, final legs, sqrt_s, params, seed, cut)
     "ud_udhh_4b": ("UD_UDHH_4B", 6, 2000.0, {"cms": 1}, 0x48454748, None),
     "gg_4g": ("GG_4G", 4, 1000.0, {}, 0x48454747, (20.0, 0.4)),
     "gg_4g_ddm": ("GG_4G", 4, 1000.0, {}, 0x48454747, (20.0, 0.4)),
+    "gg_4g_cf": ("GG_4G", 4, 1000.0, {}, 0x48454747, (20.0, 0.4)),
 }
 N_PARITY = 3 * 1024 + 37          # several 256-lane blocks and a ragged tail
 

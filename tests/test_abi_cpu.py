@@ -125,12 +125,14 @@ def test_adaptive_entry_points_reject_a_null_handle(lib):
     assert lib.heget_process_grid_dims(None) == -1
 
 
-@pytest.mark.parametrize("name,expect", [("gg_4g", -5), ("gg_5g_ddm", -5), ("gg_4g_ddm", None)])
+@pytest.mark.parametrize("name,expect", [("gg_4g", -5), ("gg_5g_ddm", -5), ("gg_4g_ddm", None), ("gg_4g_cf", None),
+                                         ("gg_5g_cf", None)])
 def test_mixed_precision_on_the_mfma_colour_form_is_refused(name, expect):
-    """the mixed kernels of processes whose colour form runs on MFMA are refused
-    at create, before any allocation (HEGET_E_UNSUPPORTED); a process with the
-    VALU colour form gets past the check (then, without a GPU, HEGET_E_OOM at
-    the first device allocation)"""
+    """the mixed kernels of processes whose FP32 colour form runs on MFMA are
+    refused at create, before any allocation (HEGET_E_UNSUPPORTED); a process
+    whose FP32 colour form runs on VALU (a small basis, or the compressed form
+    of a large one) gets past the check (then, without a GPU, HEGET_E_OOM at the
+    first device allocation)"""
     import paper_1305_0708_amd as H
     import torch
     from paper_1305_0708_amd import processes
@@ -138,3 +140,21 @@ def test_mixed_precision_on_the_mfma_colour_form_is_refused(name, expect):
     if expect is None:
         expect = 0 if torch.cuda.is_available() else -3
     assert st == expect
+
+
+@pytest.mark.parametrize("name", ["gg_4g_cf", "gg_5g_cf"])
+def test_compressed_form_keeps_mfma_out_of_the_fp32_kernel(name):
+    """the generated source of a compressed colour form: the FP32 branch calls
+    no MFMA colour form (the FP64 branch keeps the dense one), and the kernel's
+    registry entry says so"""
+    from paper_1305_0708_amd import codegen, processes
+    pir = processes.by_name(name)
+    assert pir.uses_colour_mfma() and not pir.mixed_uses_mfma()
+    src = codegen.Gen(pir).emit()
+    a = src.index("if constexpr (sizeof(T) == 4) {")
+    b = src.index("} else {", a)
+    fp32 = src[a:b]
+    assert "colour_form_" not in fp32 and "Mfma" not in fp32 and "cs += " in fp32
+    assert "colour_form_resident" in src[b:] or "colour_form_mfma" in src[b:]
+    entry = next(l for l in src.splitlines() if l.startswith("static const GenEntry entry"))
+    assert entry.endswith(", 0, nullptr, nullptr, nullptr, nullptr};")   # colour_mfma_mixed = 0, fused

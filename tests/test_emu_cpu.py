@@ -20,7 +20,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 EMU = os.path.join(HERE, "emu")
 OUT = os.path.join(EMU, "_build", "mixed_allowed")
-LIFT = [("if (prec == HEGET_MIXED && entry->colour_mfma)\n    return fail(", "if (false)\n    return fail(")]
+LIFT = [("if (prec == HEGET_MIXED && entry->colour_mfma_mixed)\n    return fail(", "if (false)\n    return fail(")]
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,7 @@ def emu_lib():
     import build_emu
     if not os.path.exists(build_emu.CXX) or not build_emu.asan_runtime():
         pytest.skip("host clang++ with the AddressSanitizer runtime not available")
-    lib = build_emu.build(processes=("gg_4g", "gg_5g_ddm"), abi_edits=LIFT, out=OUT)
+    lib = build_emu.build(processes=("gg_4g", "gg_5g_ddm", "gg_4g_cf"), abi_edits=LIFT, out=OUT)
     return lib, build_emu.asan_runtime()
 
 
@@ -50,11 +50,13 @@ def run(emu_lib, name, prec, n, seed, order, cus):
     ("gg_4g", "mixed", 300, 2),
     ("gg_4g", "mixed", 45, 1),
     ("gg_5g_ddm", "mixed", 45, 1),
+    ("gg_4g_cf", "mixed", 300, 2),  # the colour form compressed to its distinct factors, FP32 on VALU
 ])
 def test_mfma_colour_form_on_ragged_launches(emu_lib, oracle, name, prec, n, cus):
-    seed, nout, pid = {"gg_4g": (0x48454747, 4, oracle.GG_4G), "gg_5g_ddm": (0x47474735, 5, oracle.GG_5G)}[name]
+    seed, nout, pid = {"gg_4g": (0x48454747, 4, oracle.GG_4G), "gg_4g_cf": (0x48454747, 4, oracle.GG_4G),
+                       "gg_5g_ddm": (0x47474735, 5, oracle.GG_5G)}[name]
     me2, mom = run(emu_lib, name, prec, n, seed, 0, cus)
-    if name == "gg_4g":
+    if name != "gg_5g_ddm":
         me2_rev, _ = run(emu_lib, name, prec, n, seed, 1, cus)
         assert np.array_equal(me2, me2_rev), "results depend on the order the lanes run in"
     ref_mom = oracle.generate(seed, n, nout, 1000.0)

@@ -105,3 +105,56 @@ def test_mixed_precision_error(torch, oracle, reference):
     assert err.max() < 1e-1
     assert r["n_accepted"] == int(np.sum(~zero))
     assert abs(r["sigma_gev2"] / sig - 1) < 1e-3
+
+
+def test_compressed_colour_form_mixed(torch, oracle, reference):
+    """gg_5g_cf: the same process with its 120 x 120 colour matrix compressed to
+    its distinct colour factors (Sec. 5.4), which the FP32 kernel runs on VALU
+    (no MFMA in it): cut events exactly 0, F at FP32's scale against the FP64
+    oracle, sigma from its own integrate step; and its FP64 kernel (the dense
+    MFMA form) within 1e-12"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    pir = processes.by_name("gg_5g_cf")
+    ref = reference[1]
+    zero = ref == 0
+    f64 = H.Process(pir).eval(n=N_REF, seed=SEED, sqrt_s=ROOTS).cpu().numpy()
+    assert np.all(f64[zero] == 0.0)
+    assert (np.abs(f64[~zero] - ref[~zero]) / ref[~zero]).max() <= 1e-12
+    mixed = H.Process(pir, precision="mixed")
+    me2 = mixed.eval(n=N_REF, seed=SEED, sqrt_s=ROOTS).cpu().numpy()
+    assert np.all(me2[zero] == 0.0)
+    err = np.abs(me2[~zero] - ref[~zero]) / np.abs(ref[~zero])
+    r = mixed.integrate(N_REF, seed=SEED, sqrt_s=ROOTS)
+    sig, _, _, _ = oracle.cross_section(ref, oracle.phase_space_volume(ROOTS, 5), ROOTS, pir.n_a_n_b,
+                                        pir.symmetry)
+    print(f"gg->5g compressed mixed: max rel err {err.max():.2e}, median {np.median(err):.2e}; "
+          f"sigma rel {r['sigma_gev2'] / sig - 1:.2e}")
+    assert np.all(np.isfinite(me2))
+    assert np.median(err) < 1e-4 and err.max() < 1e-2
+    assert r["n_accepted"] == int(np.sum(~zero))
+    assert abs(r["sigma_gev2"] / sig - 1) < 1e-3
+
+
+def test_split_division_matches_fused(torch, oracle, proc, reference):
+    """gg_5g_split: the amplitude program divided into two kernels (Sec. 5.3),
+    the orderings' amplitudes to the workspace and then the colour form, run in
+    rounds of resident blocks: every event within 1e-12 of the oracle and of the
+    fused kernel, on two ragged launches, and sigma from its integrate step"""
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import processes
+    pir = processes.by_name("gg_5g_split")
+    split = H.Process(pir)
+    ref = reference[1]
+    zero = ref == 0
+    for n in (N_REF, 45):
+        got = split.eval(n=n, seed=SEED, sqrt_s=ROOTS).cpu().numpy()
+        fused = proc.eval(n=n, seed=SEED, sqrt_s=ROOTS).cpu().numpy()
+        z = zero[:n]
+        assert np.all(got[z] == 0.0)
+        assert (np.abs(got[~z] - ref[:n][~z]) / ref[:n][~z]).max() <= 1e-12
+        assert (np.abs(got[~z] - fused[~z]) / fused[~z]).max() <= 1e-12
+    r = split.integrate(N_REF, seed=SEED, sqrt_s=ROOTS)
+    sig, _, _, _ = oracle.cross_section(ref, oracle.phase_space_volume(ROOTS, 5), ROOTS, pir.n_a_n_b, pir.symmetry)
+    assert r["n_accepted"] == int(np.sum(~zero))
+    assert abs(r["sigma_gev2"] / sig - 1) <= 1e-12

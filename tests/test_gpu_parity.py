@@ -29,8 +29,10 @@ CASES = {
     "ud_udhh_4b": ("UD_UDHH_4B", 6, 2000.0, {"cms": 1}, 0x48454748, 1 << 21),
     "gg_4g": ("GG_4G", 4, 1000.0, {}, 0x48454747, 1 << 20),        # 120 trace flows, MFMA colour form
     "gg_4g_ddm": ("GG_4G", 4, 1000.0, {}, 0x48454747, 1 << 20),    # 24 DDM flows, VALU colour form
+    # 120 trace flows, colour form compressed to its distinct factors: FP32 on VALU, FP64 on MFMA
+    "gg_4g_cf": ("GG_4G", 4, 1000.0, {}, 0x48454747, 1 << 20),
 }
-CUT = {"gg_4g": (20.0, 0.4), "gg_4g_ddm": (20.0, 0.4)}   # generation cut: failing events have |M|^2 = 0
+CUT = {"gg_4g": (20.0, 0.4), "gg_4g_ddm": (20.0, 0.4), "gg_4g_cf": (20.0, 0.4)}   # generation cut: failing events have |M|^2 = 0
 
 
 @pytest.fixture(scope="module")
@@ -250,18 +252,19 @@ def test_c0_closed_form_on_gpu(torch):
 
 
 def test_colour_bases_agree(torch, oracle):
-    """The 120-flow trace basis contracted on MFMA and the 24-flow DDM basis on
-    VALU give the same |M|^2 (the colour sum is basis independent), in FP64
-    and, within the mixed path's precision, in FP32."""
+    """The 120-flow trace basis and the 24-flow DDM basis on VALU give the same
+    |M|^2 (the colour sum is basis independent): in FP64 with the trace basis's
+    dense form on MFMA, and, within the mixed path's precision, in FP32 with its
+    form compressed to the distinct colour factors on VALU."""
     mom = oracle.generate(0xC0105, 2000, 4, 1000.0)
     t = to_soa(torch, mom)
-    for prec, tol in (("fp64", 1e-12),):      # mixed: see MIXED_MFMA_OFF
-        a = make("gg_4g", prec).eval(momenta=t).cpu().numpy()
+    for prec, name, tol in (("fp64", "gg_4g", 1e-12), ("mixed", "gg_4g_cf", 1e-4)):   # mixed gg_4g: MIXED_MFMA_OFF
+        a = make(name, prec).eval(momenta=t).cpu().numpy()
         b = make("gg_4g_ddm", prec).eval(momenta=t).cpu().numpy()
         assert np.array_equal(a == 0, b == 0)
         nz = b != 0
         err = rel_err(a[nz], b[nz])
-        print(f"{prec}: trace/MFMA vs DDM/VALU max rel diff {err.max():.3e}, median {np.median(err):.3e}")
+        print(f"{prec}: trace basis ({name}) vs DDM basis max rel diff {err.max():.3e}, median {np.median(err):.3e}")
         assert err.max() < tol
 
 

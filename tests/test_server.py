@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 
 # C2 in mixed precision runs its DDM-basis kernel here (the 120-flow FP32 MFMA
 # kernel is kept off the GPU for now, see test_gpu_parity.MIXED_MFMA_OFF)
-NAMES = ["ee_mumu", "gg_ttbar_6f", "gg_4g_ddm", "ud_udhh_4b"]
-SQRT_S = {"ee_mumu": 200.0, "gg_ttbar_6f": 1000.0, "gg_4g_ddm": 1000.0, "ud_udhh_4b": 2000.0}
+NAMES = ["ee_mumu", "gg_ttbar_6f", "gg_4g_cf", "ud_udhh_4b"]
+SQRT_S = {"ee_mumu": 200.0, "gg_ttbar_6f": 1000.0, "gg_4g_cf": 1000.0, "ud_udhh_4b": 2000.0}
 
 
 @pytest.fixture(scope="module")
