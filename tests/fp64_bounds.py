@@ -7,7 +7,7 @@ about kappa * 5e-20, kappa the event's cancellation factor.
 
 No FP64 evaluation reaches 1e-12 on every event of every process: where the
 amplitude cancels between diagrams (the longitudinal weak bosons of u d -> u d
-H H and u d -> u d H H H, whose gauge cancellations the paper's Sec. 6
+H H and u d -> u d H H H, whose gauge cancellations the paper's Sec. 7
 discusses) or where the invariants come from large, cancelling lab-frame
 components (the hadronic collision), rounding at 1.1e-16 is amplified beyond
 it.  The FP64 oracle itself, an independent FP64 evaluation of the same
