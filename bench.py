@@ -42,9 +42,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "4bdbfcbdca571f691e6da214d136e0d12ce4687624a426bc78953bc3f20b2d1d",
-                 "fetch_kib": 470.5, "fetch_scale": 2.0, "write_kib": 192.0, "write_scale": 1.0,
-                 "flop_per_event": 41174, "flop_per_event_mixed": 37949}
+COUNTERS_FP64 = {"source_digest": "8a50181d071452a02355c329da1f36dc329492141e6c4e8e64e9f07fa60e6dce",
+                 "fetch_kib": 480.5, "fetch_scale": 2.0, "write_kib": 8192.0, "write_scale": 1.0,
+                 "flop_per_event": 29268, "flop_per_event_mixed": 26619}
 
 
 # Counter measurements of further kernels, (process, precision) -> figures per
@@ -56,29 +56,29 @@ COUNTERS_FP64 = {"source_digest": "4bdbfcbdca571f691e6da214d136e0d12ce4687624a42
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "56a9605993eb477b6ac08ebab86e8848849fb9381032f897239c92b22cb44a3f",
-        "valu_flop_per_event": 45030, "fp64_flop_per_event": 2973, "events": 1 << 21, "kernel_s": 1.356e-3,
+        "source_digest": "a420982d5fde68c72343aa46b979f5968c39cae79180d809c490b139b84c580c",
+        "valu_flop_per_event": 20012, "fp64_flop_per_event": 2818, "events": 1 << 21, "kernel_s": 0.848e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "56a9605993eb477b6ac08ebab86e8848849fb9381032f897239c92b22cb44a3f",
-        "valu_flop_per_event": 48026, "events": 1 << 21, "kernel_s": 2.482e-3,
+        "source_digest": "a420982d5fde68c72343aa46b979f5968c39cae79180d809c490b139b84c580c",
+        "valu_flop_per_event": 22830, "events": 1 << 21, "kernel_s": 1.862e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "42b128e340daac72b6b49c54fea6134f5d56834f63350bc833606cef434deba7",
-        "valu_flop_per_event": 4130384, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 185.4e-3,
+        "source_digest": "ed41d8cca4c2dc7d108ca2bcab2762e8a67565983ea5773729391468a5af4ff7",
+        "valu_flop_per_event": 3664405, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.9e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "8abf8f5f99600faf61140712efa23eb4da3b2a5d5acd30958dc4ddf8f21f93c9",
-        "valu_flop_per_event": 4071824, "events": 1 << 20, "kernel_s": 104.6e-3,
+        "source_digest": "ee27ad6794e02406920daa721a942580566f63b62c9de9a578fb72afb1f2e4d9",
+        "valu_flop_per_event": 3608085, "events": 1 << 20, "kernel_s": 96.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "8abf8f5f99600faf61140712efa23eb4da3b2a5d5acd30958dc4ddf8f21f93c9",
-        "valu_flop_per_event": 3492111, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 77.1e-3,
+        "source_digest": "ee27ad6794e02406920daa721a942580566f63b62c9de9a578fb72afb1f2e4d9",
+        "valu_flop_per_event": 2911487, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 65.6e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "e668564ce3a5a92f33ecb7c389e667d2932d9d16fc321f7944091bd4c9a56bb9",
-        "valu_flop_per_event": 4480143, "fp64_flop_per_event": 146129, "events": 1 << 20, "kernel_s": 101.5e-3,
+        "source_digest": "3c5ff0b7d61754224dabbedce5f0b8e7e5d52a12bef07e6cf0087903d1ecbae7",
+        "valu_flop_per_event": 3890815, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 90.1e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 

@@ -20,6 +20,15 @@ FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", CSRC, "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
+# device code only (host-side argument checks keep IEEE NaN semantics): the
+# kernels' values are finite and the sign of a zero never reaches a result, so
+# the compiler may drop the arithmetic on the structural zeros of fixed-helicity
+# massless spinors and chiral couplings (x * 0 -> 0, x + 0 -> x); no
+# reassociation is allowed, so compensated sums and the order of every other
+# operation stay as written.  Every unit gets them, so that kernels sharing
+# device code (the phase space) compile it alike.
+GEN_FLAGS = ["-Xarch_device", "-fno-signed-zeros", "-Xarch_device", "-ffinite-math-only"]
+
 PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "gg_ttbar_6f_had", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm",
              "gg_4g_cf", "gg_5g_cf", "gg_5g_split")
 
@@ -41,7 +50,7 @@ def _compile(src, force=False):
         [os.path.join(os.path.dirname(CSRC), "..", "include", "heget.h")]
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
         return obj
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC] + FLAGS + GEN_FLAGS + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")

@@ -221,58 +221,49 @@ class Gen:
             w("  }")
         w("}")
         w("")
-        if self.ordered:
-            w("// one launch: a persistent grid (one workspace slot per block) walks the")
-            w("// 256-event blocks of the launch")
-            w("template <class T>")
-            w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
-            if p.uses_colour_mfma():
-                w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
-            w("  const int64_t nb = (a.n + 255) / 256;")
-            w("  for (int64_t vb = blockIdx.x; vb < nb; vb += gridDim.x) {")
-            w(f"    body_{p.name}<T>(a, vb);")
-            w("    __syncthreads();")
-            w("  }")
-            w("}")
-            if split:
-                w("")
-                w("// split division: block b of a round evaluates block block_base + b of the")
-                w("// launch into workspace slot b (the orderings' amplitudes), then the")
-                w("// colour-form kernel of the same round reads that slot")
-                w("template <class T>")
-                w(f"__global__ __launch_bounds__(256) void amp_{p.name}_chain(KernelArgs a) {{")
-                w(f"  body_{p.name}<T, 1>(a, a.block_base + blockIdx.x);")
-                w("}")
-                w("template <class T>")
-                w(f"__global__ __launch_bounds__(256) void amp_{p.name}_colour(KernelArgs a) {{")
-                if p.uses_colour_mfma():
-                    w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
-                w(f"  body_{p.name}<T, 2>(a, a.block_base + blockIdx.x);")
-                w("}")
-        else:
-            w("// one launch: block b evaluates events 256 b ... 256 b + 255")
-            w("template <class T>")
-            w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
-            w(f"  body_{p.name}<T>(a, blockIdx.x);")
-            w("}")
-        w("")
-        w("// fused launch of several requests (serving engine): a persistent grid")
-        w("// walks the virtual blocks of the batch table")
+        # One kernel per arithmetic type serves a launch of one request and the
+        # serving engine's fused launches: a grid-stride loop over virtual blocks
+        # takes the launch's own blocks, or the batch table's segments when the
+        # launch carries one.  The body has this single call site, so a request
+        # gets the same compiled code, and the same bits, alone and in a mix.
+        w("// one launch: the grid walks the 256-event blocks of the launch (persistent")
+        w("// kernels: one workspace slot per block), or, for a fused launch of the")
+        w("// serving engine, the virtual blocks of its batch table")
         w("template <class T>")
-        w(f"__global__ __launch_bounds__(256) void amp_{p.name}_batch(KernelArgs a) {{")
+        w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
         if p.uses_colour_mfma():
             w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
         w("  const BatchTable* bt = a.batch;")
-        w("  const int64_t total = bt->total_blocks;")
-        w("  const int nseg = bt->n_seg;")
+        w("  const int64_t total = bt ? bt->total_blocks : (a.n + 255) / 256;")
+        w("  const int nseg = bt ? bt->n_seg : 0;")
         w("  int s = 0;")
         w("  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {")
-        w("    while (s + 1 < nseg && bt->seg[s + 1].block_begin <= vb) ++s;")
-        w("    KernelArgs b = segment_args(a, bt->seg[s]);")
-        w(f"    body_{p.name}<T>(b, bt->seg[s].block_offset + (vb - bt->seg[s].block_begin));")
+        w("    KernelArgs b = a;")
+        w("    int64_t blk = vb;")
+        w("    if (bt) {")
+        w("      while (s + 1 < nseg && bt->seg[s + 1].block_begin <= vb) ++s;")
+        w("      b = segment_args(a, bt->seg[s]);")
+        w("      blk = bt->seg[s].block_offset + (vb - bt->seg[s].block_begin);")
+        w("    }")
+        w(f"    body_{p.name}<T>(b, blk);")
         w("    __syncthreads();")
         w("  }")
         w("}")
+        if split:
+            w("")
+            w("// split division: block b of a round evaluates block block_base + b of the")
+            w("// launch into workspace slot b (the orderings' amplitudes), then the")
+            w("// colour-form kernel of the same round reads that slot")
+            w("template <class T>")
+            w(f"__global__ __launch_bounds__(256) void amp_{p.name}_chain(KernelArgs a) {{")
+            w(f"  body_{p.name}<T, 1>(a, a.block_base + blockIdx.x);")
+            w("}")
+            w("template <class T>")
+            w(f"__global__ __launch_bounds__(256) void amp_{p.name}_colour(KernelArgs a) {{")
+            if p.uses_colour_mfma():
+                w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
+            w(f"  body_{p.name}<T, 2>(a, a.block_base + blockIdx.x);")
+            w("}")
         w("")
         if tree:
             w("// the phase-space step alone (heget_generate): momenta and per-event weights")
@@ -297,8 +288,8 @@ class Gen:
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
-          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<double>), '
-          f'reinterpret_cast<const void*>(&amp_{p.name}_batch<float>), {canon}, {n_canon}, '
+          f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
+          f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {canon}, {n_canon}, '
           f'{int(self.ordered)}, {self.cterm_cap() if mf else 0}, '
           f'{f"reinterpret_cast<const void*>(&gen_{p.name})" if tree else "nullptr"}, {self.ps_dims()}, '
           f'{int(p.mixed_uses_mfma())}, '
@@ -1416,7 +1407,10 @@ def source_digest(proc):
     it includes: it changes whenever the compiled kernel can change, so a
     measurement tied to one kernel can tell that it has gone stale."""
     import hashlib
+    from . import build
     h = hashlib.sha256(Gen(proc).emit().encode())
+    flags = [f for k, f in enumerate(build.FLAGS) if f != "-I" and (k == 0 or build.FLAGS[k - 1] != "-I")]
+    h.update(" ".join(flags + build.GEN_FLAGS).encode())   # the compile flags, less include paths
     for name in _DEVICE_HEADERS:
         with open(os.path.join(_CSRC, name), "rb") as f:
             h.update(f.read())

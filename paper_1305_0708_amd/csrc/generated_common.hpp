@@ -19,7 +19,8 @@ struct GenEntry {
   const void* kernel_mixed;   // T = float, FP64 momenta and denominators
   int colour_mfma;            // 1: the colour form runs on MFMA and needs the tables below
   int nks, nfo;               // its k-steps (ceil(n_flows / 4)) and output tiles (ceil(n_flows / 16))
-  const void* batch_fp64;     // fused persistent variants reading KernelArgs::batch
+  const void* batch_fp64;     // the kernels of fused launches (the same kernels: a launch whose
+                              // KernelArgs::batch is set walks the batch table)
   const void* batch_mixed;
   const int8_t* hel_canon;    // full helicity product the kernel's loop nest sums, or null
   int n_hel_canon;            // its rows (n_legs entries each)

@@ -171,6 +171,11 @@ class Process:
     # kernel, written to device memory, the colour form in a second one,
     # launched one after the other per round of resident blocks).
     division: str = "fused"
+    # Helicity combinations of the innermost helicity loops the kernel unrolls
+    # (a code-generation setting, not part of the structure: unrolled loops
+    # take table entries and the helicities of massless spinors as constants,
+    # at the price of code size and registers)
+    nest_unroll: int = 8
 
     def uses_colour_mfma(self):
         """The FP64 colour quadratic form runs on MFMA for ordering templates

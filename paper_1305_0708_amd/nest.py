@@ -121,7 +121,8 @@ def plan(proc):
     return Plan(order, choices, call_level, {L: pos[L] for L in range(nl)}, _cost(order, *args), bra_level)
 
 
-# innermost loops unrolled up to this many helicity combinations
+# innermost loops unrolled up to this many helicity combinations, unless the
+# process sets its own (ir.Process.nest_unroll)
 UNROLL_INNER_COMBINATIONS = 8
 # tables of calls: at most this many words per lane (in the arithmetic type)
 TABLE_WORDS = 48
@@ -144,6 +145,7 @@ class Schedule:
     choices: List[Tuple[int, ...]]
     items: List[Item]          # in dependency order
     flops_per_event: int       # model flops of the loop nest, per event
+    unroll: int = 8            # helicity combinations of the innermost loops the kernel unrolls
 
 
 # each combined bra joins its jamp group's sum right after it is formed (bras
@@ -320,16 +322,16 @@ def schedule(proc):
     nf = proc.n_flows
     colour = nf * 4 + (nf * (nf - 1) // 2) * 4 + 2
     total = sum(it.flops * mult[it.level] for it in items) + colour * mult[inner]
-    return Schedule(pl.order, pl.choices, items, total)
+    return Schedule(pl.order, pl.choices, items, total, proc.nest_unroll)
 
 
 def unrolled_levels(sc):
-    """the innermost loop levels, up to UNROLL_INNER_COMBINATIONS helicity
-    combinations, that the kernel unrolls (constant helicities there)"""
+    """the innermost loop levels, up to sc.unroll helicity combinations (the
+    process's setting), that the kernel unrolls (constant helicities there)"""
     unrolled, combos = set(), 1
     for lvl in reversed(range(len(sc.order))):
         n = len(sc.choices[sc.order[lvl]])
-        if combos * n > UNROLL_INNER_COMBINATIONS:
+        if combos * n > sc.unroll:
             break
         combos *= n
         unrolled.add(lvl)

@@ -66,8 +66,11 @@ def gg_ttbar_6f(sqrt_s=1000.0):
     ]
     jamp = [[(1, 1.0), (0, -1.0)], [(2, 1.0), (0, 1.0)]]
     colour = [[Fraction(16, 3), Fraction(-2, 3)], [Fraction(-2, 3), Fraction(16, 3)]]
+    # the two gluon loops unrolled beside the three innermost fermion loops: the gluon
+    # tables of the nest are then taken by constant index, not selected per loop
     return Process("gg_ttbar_6f", legs, cpl, calls, n_amps=3, n_flows=2, jamp=jamp, colour=colour,
-                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64, symmetry=1).validate()
+                   helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64, symmetry=1,
+                   nest_unroll=32).validate()
 
 
 def gg_ttbar_6f_bw(sqrt_s=1000.0):
@@ -135,7 +138,7 @@ def ud_udhh_4b(sqrt_s=2000.0):
     colour = [[Fraction(cq[a % 2][b % 2] * cq[a // 2][b // 2]) for b in range(4)] for a in range(4)]
     return Process("ud_udhh_4b", legs, cpl, calls, n_amps=amp, n_flows=4, jamp=jamp, colour=colour,
                    helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=9, symmetry=4,
-                   sm_overrides={"complex_mass": 1}).validate()
+                   sm_overrides={"complex_mass": 1}, nest_unroll=32).validate()
 
 
 def ud_udhhh(sqrt_s=2000.0):

@@ -70,12 +70,18 @@ def test_me2_of_tree_events_matches_oracle(torch, oracle, proc):
     rarely land), momenta-in: the oracle's momenta fed to both sides, every
     event within the process's bound of the extended-precision oracle.  On the
     poles the denominators q^2 - m^2 come from cancelling momentum sums: the
-    FP64 oracle is off by up to 7.3e-13 there."""
+    FP64 oracle is off by up to 7.3e-13 there, by 1.1e-13 at the median.  The
+    median is held to twice that of the FP64 oracle on the same events: no FP64
+    evaluation is expected to beat an independent one by more than the change
+    of operation order allows."""
     import fp64_bounds as B
     (mom,) = B.tree_events(oracle, NAME)
     me2 = proc.eval(momenta=to_soa(torch, mom)).cpu().numpy()
     err = B.check(oracle, NAME, mom, me2)
-    assert np.median(err) < 1e-13
+    ref = B.reference(oracle, NAME, mom)
+    x = np.abs(B.reference(oracle, NAME, mom, extended=False) - ref) / np.abs(ref)
+    print(f"median: GPU {np.median(err):.3e}, FP64 oracle {np.median(x):.3e}")
+    assert np.median(err) <= 2.0 * np.median(x)
 
 
 def test_integrate_matches_oracle(torch, oracle, proc):

@@ -91,11 +91,20 @@ def test_tables_are_valid(name):
 
 
 def test_c1_tables_and_stash_in_the_generated_kernel():
-    """C1: the gg -> g* current is tabulated before the loops over both gluon
-    helicities and the top current over gluon 1 inside the b-quark loop; the
-    stash fits its budget and the flop model counts the tables."""
+    """C1 with its five innermost loops unrolled (its own setting) needs no
+    tables: the gluon states are constants of the unrolled code.  With only the
+    three fermion loops unrolled, the gg -> g* current is tabulated before the
+    loops over both gluon helicities and the top current over gluon 1 inside
+    the b-quark loop; the stash fits its budget and the flop model counts the
+    tables."""
+    import dataclasses
     from paper_1305_0708_amd import codegen
-    p = processes.by_name("gg_ttbar_6f")
+    c1 = processes.by_name("gg_ttbar_6f")
+    sc1 = nest.schedule(c1)
+    assert len(nest.unrolled_levels(sc1)) == 5
+    assert nest.tables(c1, sc1, nest.unrolled_levels(sc1)) == {}
+    assert "t12_" not in codegen.Gen(c1).emit()
+    p = dataclasses.replace(c1, nest_unroll=8)
     src = codegen.Gen(p).emit()
     assert "jvvxxx<T, false>(x0m, Qs0, x1m, Qs1" in src
     assert "(c0 ? (c1 ? t12_3 : t12_2) : (c1 ? t12_1 : t12_0))" in src
