@@ -13,6 +13,9 @@ lives in the C++ sources next to this file:
   with explicit Dirac matrices and brute-force SU(3) colour sums.
 * ``gluons.cpp``     -- colour-ordered Berends-Giele recursion for n gluons and
   the trace-basis colour matrix by brute force.
+* ``quark_lines.cpp`` -- u ubar -> t tbar + n gluons (n <= 3): every tree
+  diagram with explicit Dirac matrices, colour summed over explicit SU(3)
+  indices through the diagrams' colour matrix.
 * ``phase_space_tree.py`` -- (numpy) the resonance phase space of the paper's
   Appendix A at a fixed collision energy: nested two-body decays with
   Breit-Wigner mapped invariant masses.
@@ -38,6 +41,8 @@ _LIB_LD_PATH = os.path.join(_HERE, "_build", "liboracle_ld.so")
 EE_MUMU, GG_TT_6F, GG_4G, UD_UDHH_4B = 0, 1, 2, 3
 GG_GG, GG_GGG, UU_TT, GG_TT, UU_UUHH_4B, WW_HH, ZZ_HH = 10, 11, 12, 13, 14, 16, 17
 UD_UDHHH, WW_HHH, ZZ_HHH, WW_WW, GG_5G = 4, 18, 19, 20, 21
+# u ubar -> t tbar + 1, 2, 3 gluons by Feynman diagrams (quark_lines.cpp); UU_TT_DIAG: no gluon
+UU_TTG, UU_TTGG, UU_TTGGG, UU_TT_DIAG = 22, 23, 24, 25
 
 
 class Params(ctypes.Structure):
@@ -93,6 +98,7 @@ def lib(extended=False):
         L.or_gluon_colour_matrix_fierz.argtypes = [ctypes.c_int, dp]
         L.or_trace_me2.argtypes = [ctypes.c_int, P(Params), dp, dp]
         L.or_nlegs.argtypes = [ctypes.c_int]
+        L.or_uu_tt_gluons_diagrams.argtypes = [ctypes.c_int]
         L.or_selfcheck_spinors.argtypes = [dp, ctypes.c_double]
         L.or_selfcheck_spinors.restype = ctypes.c_double
         L.or_decay_width.argtypes = [ctypes.c_int, P(Params), dp]
@@ -159,6 +165,12 @@ def cut_gluons(mom, pt_min=20.0, dr_min=0.4):
 
 def nlegs(proc):
     return lib().or_nlegs(proc)
+
+
+def uu_tt_gluons_diagrams(n_gluons):
+    """the number of tree diagrams u ubar -> t tbar + n gluons sums (a four-gluon
+    vertex counted once per colour structure)"""
+    return lib().or_uu_tt_gluons_diagrams(n_gluons)
 
 
 def me2(proc, mom, prm=None, threads=0, extended=False):

@@ -21,6 +21,16 @@ int gluon_count(int proc) {
     default: return 0;
   }
 }
+// 1 + the number of gluons of a u ubar -> t tbar + gluons process, else 0
+int uu_tt_count(int proc) {
+  switch (proc) {
+    case OR_UU_TT_DIAG: return 1;
+    case OR_UU_TTG: return 2;
+    case OR_UU_TTGG: return 3;
+    case OR_UU_TTGGG: return 4;
+    default: return 0;
+  }
+}
 void load(const double* mom, int nl, Vec4* p) {
   for (int k = 0; k < nl; ++k)
     for (int m = 0; m < 4; ++m) p[k][m] = mom[4 * k + m];
@@ -29,6 +39,7 @@ void load(const double* mom, int nl, Vec4* p) {
 
 extern "C" int or_nlegs(int proc) {
   if (int n = gluon_count(proc)) return n;
+  if (int k = uu_tt_count(proc)) return 3 + k;
   const ProcDef* P = find_proc(proc);
   return P ? P->nlegs : -1;
 }
@@ -36,6 +47,20 @@ extern "C" int or_nlegs(int proc) {
 extern "C" int or_eval(int proc, const or_params* prm, int64_t n_events, const double* mom, double* me2,
                        int n_threads) {
   const SM sm(*prm);
+  if (int k = uu_tt_count(proc)) {
+    const int ngl = k - 1;
+    uu_tt_gluons_me2(ngl, sm, nullptr);   // builds the diagrams and the colour matrix once
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n_events; ++i) {
+      Vec4 p[8];
+      load(mom + i * (4 + ngl) * 4, 4 + ngl, p);
+      me2[i] = double(uu_tt_gluons_me2(ngl, sm, p));
+    }
+    return 0;
+  }
   const int ng = gluon_count(proc);
   const ProcDef* P = ng ? nullptr : find_proc(proc);
   if (!ng && !P) return -1;
@@ -146,6 +171,8 @@ extern "C" int or_gluon_partial(int n, const or_params* prm, const double* mom, 
   out[1] = a.imag();
   return 0;
 }
+
+extern "C" int or_uu_tt_gluons_diagrams(int ng) { return ng < 0 || ng > 3 ? -1 : uu_tt_gluons_diagrams(ng); }
 
 extern "C" int or_gluon_colour_matrix(int n, double* C) {
   if (n < 3 || n > 6) return -1;

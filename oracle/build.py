@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liboracle.so")
 LIB_LD = os.path.join(OUT_DIR, "liboracle_ld.so")
-SOURCES = ["kinematics.cpp", "processes.cpp", "gluons.cpp", "api.cpp"]
+SOURCES = ["kinematics.cpp", "processes.cpp", "gluons.cpp", "quark_lines.cpp", "api.cpp"]
 FLAGS = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unused-function"]
 
 

@@ -51,7 +51,10 @@ enum {
   OR_WW_HHH = 18,       /* W- W+ -> H H H with on-shell external W (unitarity check) */
   OR_ZZ_HHH = 19,       /* Z Z -> H H H with on-shell external Z */
   OR_WW_WW = 20,        /* W- W+ -> W- W+ with on-shell external W; legs W- W+ W- W+ */
-  OR_GG_5G = 21         /* g g -> g g g g g (Berends-Giele; colour matrix by Fierz expansion) */
+  OR_GG_5G = 21,        /* g g -> g g g g g (Berends-Giele; colour matrix by Fierz expansion) */
+  /* u ubar -> t tbar + n gluons by Feynman diagrams; legs u ubar t tbar g ... */
+  OR_UU_TTG = 22, OR_UU_TTGG = 23, OR_UU_TTGGG = 24,
+  OR_UU_TT_DIAG = 25    /* n = 0 through the same diagram code (compare OR_UU_TT) */
 };
 
 int or_nlegs(int proc);

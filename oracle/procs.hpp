@@ -34,4 +34,8 @@ cd gluon_partial(int n, const SM& sm, const Vec4* p, const int* hel, const int* 
 const std::vector<real>& gluon_colour_matrix(int n);
 std::vector<real> fierz_colour_matrix(int n);
 
+// u ubar -> t tbar + n gluons by Feynman diagrams (quark_lines.cpp)
+real uu_tt_gluons_me2(int ng, const SM& sm, const Vec4* p);
+int uu_tt_gluons_diagrams(int ng);
+
 }  // namespace orc

@@ -39,6 +39,10 @@ X_ORACLE = {
     "gg_ttbar_6f_had": 3.9e-9,
     "gg_ttbar_6f_bw": 7.3e-13,
 }
+# u ubar -> t tbar + 1, 2, 3 gluons on the events passing the cut (unbounded
+# soft and collinear cancellations sit outside it)
+X_ORACLE.update({"uu_ttg": 3.4e-14, "uu_ttgg": 2.2e-14, "uu_ttggg": 4.1e-14})
+X_ORACLE["uu_ttggg_cf"] = X_ORACLE["uu_ttggg"]
 X_ORACLE["gg_4g_ddm"] = X_ORACLE["gg_4g"]
 X_ORACLE["gg_4g_cf"] = X_ORACLE["gg_4g"]
 
@@ -61,7 +65,8 @@ BOUND = {name: bound(name) for name in X_ORACLE}
 # share of the parity events that must also be within 1e-12
 SHARE = {"ee_mumu": 1.0, "gg_ttbar_6f": 0.99, "gg_4g": 0.99, "gg_4g_ddm": 0.99, "gg_4g_cf": 0.99,
          "ud_udhh_4b": 0.98,
-         "ud_udhhh": 0.75, "ww_ww": 0.99, "gg_ttbar_6f_had": 0.25, "gg_ttbar_6f_bw": 0.99}
+         "ud_udhhh": 0.75, "ww_ww": 0.99, "gg_ttbar_6f_had": 0.25, "gg_ttbar_6f_bw": 0.99,
+         "uu_ttg": 0.99, "uu_ttgg": 0.99, "uu_ttggg": 0.99, "uu_ttggg_cf": 0.99}
 
 # ---------------------------------------------------------------- event sets
 RAMBO = {   # name -> (oracle id, final legs, sqrt_s, params, seed, cut)
@@ -95,6 +100,26 @@ TREES = {   # name -> (oracle id, params, sqrt_s, tree, n_legs, leg masses, hadr
 }
 
 
+def _tt_gluons_tree(ng):
+    """u ubar -> t tbar + ng gluons: the collision -> t + X, X -> tbar + Y, ...
+    in flat two-body steps (the product's tree for these processes)"""
+    fin = list(range(2, 4 + ng))
+    nodes = []
+    for k in range(len(fin) - 1):
+        d1 = fin[k + 1] if k == len(fin) - 2 else -(k + 2)
+        nodes.append((0.0, 0.0, None if k == 0 else "flat", fin[k], d1, None))
+    return nodes
+
+
+for _ng, _name, _sets in ((1, "uu_ttg", [(0x54544701, 1024 + 37)]), (2, "uu_ttgg", [(0x54544702, 512 + 37)]),
+                          (3, "uu_ttggg", [(0x54544703, 256 + 44)]), (3, "uu_ttggg_cf", [(0x54544703, 256 + 44)])):
+    TREES[_name] = ({1: "UU_TTG", 2: "UU_TTGG", 3: "UU_TTGGG"}[_ng], {}, 1000.0, _tt_gluons_tree(_ng), 4 + _ng,
+                    [0, 0, MT, MT] + [0] * _ng, None, _sets)
+# generation cuts of the parity references: (pT min, Delta R min) on every final leg
+CUTS = {name: v[5] for name, v in RAMBO.items() if v[5] is not None}
+CUTS.update({name: (20.0, 0.4) for name in ("uu_ttg", "uu_ttgg", "uu_ttggg", "uu_ttggg_cf")})
+
+
 def rambo_events(oracle, name, n=N_PARITY, salt=0x55):
     _, nout, rs, _, seed, _ = RAMBO[name]
     return oracle.generate(seed ^ salt, n, nout, rs)
@@ -124,7 +149,7 @@ def oracle_id(oracle, name):
 def reference(oracle, name, mom, extended=True):
     """F per event (the cut applied for gluon processes): long double by default"""
     f = oracle.me2(oracle_id(oracle, name), mom, oracle_params(oracle, name), extended=extended)
-    cut = RAMBO.get(name, (None,) * 6)[5]
+    cut = CUTS.get(name)
     if cut is not None:
         f = f * oracle.cut_gluons(mom, *cut)
     return f
