@@ -56,13 +56,22 @@ COUNTERS_FP64 = {"source_digest": "8a50181d071452a02355c329da1f36dc329492141e6c4
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "a420982d5fde68c72343aa46b979f5968c39cae79180d809c490b139b84c580c",
-        "valu_flop_per_event": 20012, "fp64_flop_per_event": 2818, "events": 1 << 21, "kernel_s": 0.848e-3,
+        "source_digest": "3a21049b453be33fc3deebd728892f19c6c59c625fafb3d903bbe693f2093587",
+        "valu_flop_per_event": 16188, "fp64_flop_per_event": 2818, "events": 1 << 21, "kernel_s": 0.702e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "a420982d5fde68c72343aa46b979f5968c39cae79180d809c490b139b84c580c",
-        "valu_flop_per_event": 22830, "events": 1 << 21, "kernel_s": 1.862e-3,
+        "source_digest": "3a21049b453be33fc3deebd728892f19c6c59c625fafb3d903bbe693f2093587",
+        "valu_flop_per_event": 19006, "events": 1 << 21, "kernel_s": 1.365e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
+    # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
+    ("uu_ttggg", "fp64"): {
+        "source_digest": "1fb61a4c3ce3211e1dc3981ff683a543d13741de94e7d4d258de0be1bd5ea2f9",
+        "valu_flop_per_event": 25152814, "events": 1 << 18, "kernel_s": 506.0e-3,
+        "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
+    ("uu_ttggg", "mixed"): {
+        "source_digest": "1fb61a4c3ce3211e1dc3981ff683a543d13741de94e7d4d258de0be1bd5ea2f9",
+        "valu_flop_per_event": 23745920, "fp64_flop_per_event": 1334190, "events": 1 << 18, "kernel_s": 163.6e-3,
+        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
         "source_digest": "ed41d8cca4c2dc7d108ca2bcab2762e8a67565983ea5773729391468a5af4ff7",
@@ -285,6 +294,56 @@ def oracle_leg(torch, H, oracle, pir, oracle_proc, oracle_kw, nout, seed, cut=No
     return out
 
 
+def tree_oracle_leg(torch, H, oracle, pir, oracle_proc, seed, target_seconds=3.0, precisions=("fp64", "mixed")):
+    """oracle_leg for a process whose phase space is a tree of flat two-body
+    steps with massive final legs: the oracle's own tree generator gives the
+    sample's momenta and weights"""
+    import numpy as np
+    from oracle import phase_space_tree as T
+    from paper_1305_0708_amd import ir as IR
+    assert all(node[1] == IR.PS_FLAT and node[0] == IR.P_ZERO for node in pir.ps_tree)
+    nodes = [(0.0, 0.0, None if k == 0 else "flat", d0, d1, None) for k, (_, _, d0, d1) in enumerate(pir.ps_tree)]
+    prm = oracle.params()
+    masses = [prm.mt if leg.particle == IR.P_TOP else 0.0 for leg in pir.legs]
+    cores = len(os.sched_getaffinity(0))
+    pid, nl = getattr(oracle, oracle_proc), pir.n_legs
+    probe, _ = T.generate(seed, 32, pir.sqrt_s, nodes, nl, leg_mass=masses)
+    oracle.me2(pid, probe[:1], prm, threads=cores)    # builds the diagrams and the colour matrix
+    t0 = time.perf_counter()
+    oracle.me2(pid, probe, prm, threads=cores)
+    rate = 32 / (time.perf_counter() - t0)
+    n = int(min(max(rate * target_seconds, 256), 1 << 16))
+    mom, w = T.generate(seed, n, pir.sqrt_s, nodes, nl, leg_mass=masses)
+    t0 = time.perf_counter()
+    f = oracle.me2(pid, mom, prm, threads=cores)
+    dt = time.perf_counter() - t0
+    passed = oracle.cut_gluons(mom, pir.cut_pt, pir.cut_dr) if pir.cut_enabled else np.ones(n, dtype=np.int32)
+    passed = passed * (w > 0)
+    f = f * passed
+    out = {"value": n / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} events of the same workload (first {n} Philox counters of the tree), {dt:.1f} s"}
+    sig_ref = oracle.cross_section(f, w, pir.sqrt_s, pir.n_a_n_b, pir.symmetry, passed=passed)[0]
+    soa = torch.from_numpy(np.ascontiguousarray(np.transpose(mom, (1, 2, 0)))).cuda()
+    nz = f != 0
+    for prec in precisions:
+        proc = H.Process(pir, precision=prec)
+        got = proc.eval(momenta=soa).cpu().numpy()
+        proc.close()
+        err = np.abs(got[nz] - f[nz]) / np.abs(f[nz])
+        sig = oracle.cross_section(got, w, pir.sqrt_s, pir.n_a_n_b, pir.symmetry, passed=passed)[0]
+        out[f"{prec}_error"] = {"me2_max_rel": float(err.max()), "me2_median_rel": float(np.median(err)),
+                                "sigma_rel": sig / sig_ref - 1.0, "events": int(nz.sum()),
+                                "cut_events_exactly_zero": bool(np.all(got[~nz] == 0.0))}
+    return out
+
+
+def compression_text(pir):
+    c = pir.colour_compression()
+    return (f"the {c['flows']} x {c['flows']} colour matrix compressed to its {c['distinct_factors']} distinct "
+            f"factors ({c['compressed_multiplications']:,} multiplications per form instead of "
+            f"{c['dense_multiply_adds']:,} multiply-adds)")
+
+
 def phase_space_leg(torch, proc, steps, warmup):
     """heget_generate alone (Philox -> RAMBO -> SoA momenta), the HBM-bound
     kernel of the path: 32 bytes per leg per event written."""
@@ -395,7 +454,8 @@ def main():
             return
         pir = processes.by_name(args.profile_proc)
         proc = H.Process(pir, precision=args.profile_leg)
-        n = {"gg_5g_ddm": 1 << 16, "gg_5g_cf": 1 << 16, "gg_5g_split": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536}.get(args.profile_proc, N_EVENTS)
+        n = {"gg_5g_ddm": 1 << 16, "gg_5g_cf": 1 << 16, "gg_5g_split": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536,
+             "uu_ttggg": 1 << 18, "uu_ttggg_cf": 1 << 18}.get(args.profile_proc, N_EVENTS)
         wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
                "kernel_ms": kern * 1e3, "events_per_launch": n, "events_per_s": n / wall,
@@ -492,9 +552,21 @@ def main():
         "amplitudes to the workspace, then the colour form), launched per round of resident blocks", 3, 1,
         n=1 << 16, precisions=("fp64",))
     line["seven_gluons"]["compressed"] = config_leg(
-        torch, H, processes.by_name("gg_5g_cf"), "the same, the 120 x 120 colour matrix compressed to its 14 "
-        "distinct factors (1,318 multiplications per form); mixed precision on VALU", 3, 1, n=1 << 16,
-        precisions=("mixed",))
+        torch, H, processes.by_name("gg_5g_cf"), f"the same, {compression_text(processes.by_name('gg_5g_cf'))}; "
+        "mixed precision on VALU", 3, 1, n=1 << 16, precisions=("mixed",))
+    # u ubar -> t tbar g g g: the paper's long amplitude (Sec. 5.3-5.5) from its Feynman diagrams
+    ql = processes.by_name("uu_ttggg")
+    ncur = sum(1 for c in ql.calls if c.op not in ("iov",))
+    line["long_amplitude"] = config_leg(
+        torch, H, ql, f"u ubar -> t tbar g g g, sqrt_s_hat = 1 TeV, stable tops, pT > 20 GeV and Delta R > 0.4 "
+        f"on every final leg, flat two-body tree phase space, 2^18 events per step, 128 helicity combinations; "
+        f"{ql.n_amps} Feynman diagrams as {ncur} current calls and {ql.n_amps} amplitude calls, {ql.n_flows} "
+        f"colour flows, dense colour form; the program divided into {ql.row_parts} device functions, helicity "
+        f"rows one at a time", 3, 1, n=1 << 18, seed=0x54544703)
+    line["long_amplitude"]["colour"] = ql.colour_compression()
+    line["long_amplitude"]["compressed"] = config_leg(
+        torch, H, processes.by_name("uu_ttggg_cf"), f"the same with {compression_text(ql)}", 3, 1, n=1 << 18,
+        seed=0x54544703)
     # the other configured workloads, each with the oracle timed beside it on a
     # sample of its events and the GPU's error against the oracle on that sample
     import oracle as O
@@ -513,10 +585,9 @@ def main():
         "events per step, 64 helicity combinations, 120 trace-basis flows, dense 120 x 120 colour form on MFMA",
         args.steps, args.warmup, seed=0x48454747)
     legs["c2"]["compressed"] = config_leg(
-        torch, H, processes.by_name("gg_4g_cf"), "the same events through the same 120 trace-basis flows, the colour "
-        "matrix compressed to its 15 distinct factors (1,509 multiplications per form instead of 7,260 "
-        "multiply-adds); mixed precision runs it on VALU, FP64 keeps the dense MFMA form", args.steps, args.warmup,
-        precisions=("mixed",), seed=0x48454747)
+        torch, H, processes.by_name("gg_4g_cf"), f"the same events through the same 120 trace-basis flows, "
+        f"{compression_text(processes.by_name('gg_4g_cf'))}; mixed precision runs it on VALU, FP64 keeps the dense "
+        "MFMA form", args.steps, args.warmup, precisions=("mixed",), seed=0x48454747)
     legs["c2"]["ddm_basis"] = config_leg(
         torch, H, c2d, "the same events and |M|^2 through the 24-flow DDM basis, colour form on VALU",
         args.steps, args.warmup, seed=0x48454747)
@@ -535,6 +606,8 @@ def main():
     if not args.no_cpu_baseline:
         legs["c3"]["oracle"] = oracle_leg(torch, H, O, c3, "UD_UDHH_4B", {"cms": 1}, 6, 0x48454748,
                                           precisions=("mixed", "fp64"))
+    if not args.no_cpu_baseline:
+        line["long_amplitude"]["oracle"] = tree_oracle_leg(torch, H, O, ql, "UU_TTGGG", 0x54544703)
     line["configs"] = legs
     if args.serve_requests > 0:
         line["serve"] = serve_leg(args.serve_requests)

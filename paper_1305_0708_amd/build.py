@@ -30,7 +30,7 @@ FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
 GEN_FLAGS = ["-Xarch_device", "-fno-signed-zeros", "-Xarch_device", "-ffinite-math-only"]
 
 PROCESSES = ("ee_mumu", "gg_ttbar_6f", "gg_ttbar_6f_bw", "gg_ttbar_6f_had", "ud_udhh_4b", "ud_udhhh", "ww_ww", "gg_4g", "gg_4g_ddm", "gg_5g_ddm",
-             "gg_4g_cf", "gg_5g_cf", "gg_5g_split")
+             "gg_4g_cf", "gg_5g_cf", "gg_5g_split", "uu_ttg", "uu_ttgg", "uu_ttggg", "uu_ttggg_cf")
 
 
 def generate_sources():

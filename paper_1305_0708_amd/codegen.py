@@ -149,6 +149,8 @@ class Gen:
         tree = p.ps_tree is not None
         if tree:
             self._emit_ps_tree(w)
+        if p.helicity_schedule == "rows":
+            self._emit_row_parts(w)
         split = p.division == "split"
         self._split = split
         if split:
@@ -280,11 +282,15 @@ class Gen:
         w("")
         mf = p.uses_colour_mfma()
         nks, nfo = ((p.n_flows + 3) // 4, (p.n_flows + 15) // 16) if mf else (0, 0)
-        rows = ir.all_helicities(p.legs)
-        flat = ", ".join(str(h) for row in rows for h in row)
-        w(f"// the full helicity product in canonical order: tables equal to it run the loop nest")
-        w(f"static const int8_t hel_canon[] = {{{flat}}};")
-        canon, n_canon = "hel_canon", len(rows)
+        if p.helicity_schedule == "rows":
+            # no loop nest: every table is summed row by row
+            canon, n_canon = "nullptr", 0
+        else:
+            rows = ir.all_helicities(p.legs)
+            flat = ", ".join(str(h) for row in rows for h in row)
+            w(f"// the full helicity product in canonical order: tables equal to it run the loop nest")
+            w(f"static const int8_t hel_canon[] = {{{flat}}};")
+            canon, n_canon = "hel_canon", len(rows)
         w(f'static const GenEntry entry = {{0x{fp:016x}ull, "{p.name}", {self.nl}, '
           f'reinterpret_cast<const void*>(&amp_{p.name}<double>), '
           f'reinterpret_cast<const void*>(&amp_{p.name}<float>), {int(mf)}, {nks}, {nfo}, '
@@ -452,9 +458,151 @@ class Gen:
                 self._kin[f"d{n}_{pid}"] = "cx<T>"
 
     # ---------------------------------------------------------- straight-line
+    def _row_groups(self):
+        """the amplitude calls of the rows schedule in groups of consecutive
+        amplitudes, one per part of the function division (one group: no
+        division)"""
+        p = self.p
+        amps = [i for i, c in enumerate(p.calls) if c.op in AMP_OPS]
+        size = -(-len(amps) // max(1, p.row_parts))
+        return [amps[i:i + size] for i in range(0, len(amps), size)]
+
+    def _closure(self, idxs):
+        """the calls that the given calls need, in IR order"""
+        calls = self.p.calls
+        producer = {c.out: i for i, c in enumerate(calls) if c.op not in AMP_OPS}
+        need, stack = set(), list(idxs)
+        while stack:
+            i = stack.pop()
+            if i in need:
+                continue
+            need.add(i)
+            stack.extend(producer[x] for x in calls[i].ins if x in producer)
+        return sorted(need)
+
+    def _emit_row_calls(self, w, ind, idxs, acc):
+        """one helicity row's calls idxs (IR order) with the external states,
+        momentum sums and denominators they need, formed in place from the LDS
+        momenta behind an opaque index (not hoisted out of the row loop); each
+        amplitude is added to its flows, acc(f), as soon as it is formed"""
+        p, nl = self.p, self.nl
+        flows_of = {}
+        for f, terms in enumerate(p.jamp):
+            for ai, cc in terms:
+                flows_of.setdefault(ai, []).append((f, cc))
+        loaded, done = set(), set()
+
+        def phys(k):
+            if k not in loaded:
+                loaded.add(k)
+                w(f"{ind}const mom pr{k} = pm_{p.name}[opaque_int({k})][threadIdx.x];")
+            return f"pr{k}"
+
+        def qsum(sub):
+            n = self.sname(sub)
+            if f"qs{n}" not in done:
+                done.add(f"qs{n}")
+                terms = (phys(x) if p.legs[x].incoming else f"(-{phys(x)})" for x in sub)
+                w(f"{ind}const mom qs{n} = {' + '.join(terms)};")
+            return f"qs{n}"
+
+        legs = sorted({x for i in idxs for x in p.calls[i].ins if x < nl})
+        for k in legs:
+            leg = p.legs[k]
+            pk = phys(k)
+            if leg.kind == F:
+                fn = "ixxxxx" if _flowing_in(leg) else "oxxxxx"
+                massless = "true" if leg.particle == P_ZERO else "false"
+                w(f"{ind}const wf<T> w{k} = cvtw<T>({fn}<double, {massless}>(tv<double>({pk}), pe{leg.particle}.m, "
+                  f"hh[{k}], {leg.flow}));")
+            elif leg.kind == V:
+                nsv = -1 if leg.incoming else 1
+                w(f"{ind}const wf<T> w{k} = vxxxxx<T>(tv<T>({pk}), T(pe{leg.particle}.m), hh[{k}], {nsv});")
+            else:
+                w(f"{ind}const cx<T> w{k} = sxxxxx<T>();")
+        for i in idxs:
+            c = p.calls[i]
+            subs = [self.subset[x] for x in c.ins]
+            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+                subs.append(self.subset[c.out])
+            for sub in subs:
+                n = self.sname(sub)
+                if sub in self.need_q and f"Qs{n}" not in done:
+                    done.add(f"Qs{n}")
+                    w(f"{ind}const vec<T> Qs{n} = tv<T>({qsum(sub)});")
+            if c.op not in AMP_OPS and c.op not in LINEAR_OPS:
+                sub, pid = self.subset[c.out], c.prop
+                n = self.sname(sub)
+                if f"d{n}_{pid}" not in done:
+                    done.add(f"d{n}_{pid}")
+                    w(f"{ind}const cx<T> d{n}_{pid} = cvt<T>(inv_denominator({qsum(sub)}, "
+                      f"cx<double>{{pe{pid}.pole_r, pe{pid}.pole_i}}));")
+            self._call(w, c, ind)
+            if c.op in AMP_OPS:
+                for f, cc in flows_of.get(c.out, []):
+                    w(f"{ind}{acc(f)} = {acc(f)} + {_coef_expr(cc, f'amp{c.out}')};")
+
+    def _emit_row_parts(self, w):
+        """the function division of the rows schedule (the paper's Sec. 5.3):
+        each group of amplitudes in a device function of its own, not inlined,
+        that forms the currents its amplitudes need (a current two groups share
+        is formed in each) and adds the amplitudes to the flows J (in the
+        caller's memory).  Each part is compiled and register-allocated alone."""
+        p = self.p
+        w(f"// the event's physical momenta, one column per lane, read by every part")
+        w(f"__shared__ mom pm_{p.name}[{self.nl}][256];")
+        w("")
+        groups = self._row_groups()
+        if len(groups) < 2:
+            return
+        for k, grp in enumerate(groups):
+            idxs = self._closure(grp)
+            w(f"// part {k}: amplitudes {p.calls[grp[0]].out} .. {p.calls[grp[-1]].out} ({len(idxs)} calls)")
+            w("template <class T>")
+            w(f"__device__ __noinline__ void rows_{p.name}_part{k}(const KernelArgs& a, const int8_t* hh, cx<T>* J) {{")
+            cpls = sorted({p.calls[i].cpl for i in idxs if p.calls[i].cpl >= 0})
+            for c in cpls:
+                w(f"  const cx<T> g{c}_0 = mk<T>(T(a.cpl[{4 * c}]), T(a.cpl[{4 * c + 1}]));")
+                w(f"  const cx<T> g{c}_1 = mk<T>(T(a.cpl[{4 * c + 2}]), T(a.cpl[{4 * c + 3}]));")
+            pids = sorted({p.calls[i].prop for i in idxs} | {leg.particle for leg in p.legs} | {P_ZERO})
+            for pid in pids:
+                w(f"  const PropEntry pe{pid} = a.prop[{pid}];")
+            self._emit_row_calls(w, "  ", idxs, lambda f: f"J[{f}]")
+            w("}")
+            w("")
+
+    def _emit_rows(self, w):
+        """the helicity table row by row (the rows schedule): the momenta are
+        copied to LDS, then per row the calls run in IR order, in one piece or
+        as the parts of the function division, and the colour form sums the
+        row's flows"""
+        p, nl = self.p, self.nl
+        for k in range(nl):
+            w(f"  pm_{p.name}[{k}][threadIdx.x] = p[{k}];")
+        w("  double me2 = 0.0;")
+        w("  if (pass) {")
+        w("    for (int h = 0; h < a.n_hel; ++h) {")
+        w(f"      const int8_t* hh = a.hel + h * {nl};")
+        groups = self._row_groups()
+        if len(groups) < 2:
+            w(f"      cx<T> {', '.join(f'J{f} = mk<T>(T(0), T(0))' for f in range(p.n_flows))};")
+            self._emit_row_calls(w, "      ", list(range(len(p.calls))), lambda f: f"J{f}")
+            self._colour_form(w, lambda f: f"J{f}", "      ")
+        else:
+            w(f"      cx<T> J[{p.n_flows}];")
+            w(f"      for (int f = 0; f < {p.n_flows}; ++f) J[f] = mk<T>(T(0), T(0));")
+            for k in range(len(groups)):
+                w(f"      rows_{p.name}_part{k}<T>(a, hh, J);")
+            self._colour_form(w, lambda f: f"J[{f}]", "      ")
+        w("    }")
+        w("  }")
+
     def _emit_straight(self, w):
         p = self.p
         self._kin = {}
+        if p.helicity_schedule == "rows":
+            self._emit_rows(w)
+            return
         for k in range(self.nl):
             if (k,) in self.need_q:
                 w(f"  const vec<T> Qs{k} = tv<T>(q{k});")

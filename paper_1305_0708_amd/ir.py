@@ -176,6 +176,19 @@ class Process:
     # take table entries and the helicities of massless spinors as constants,
     # at the price of code size and registers)
     nest_unroll: int = 8
+    # Helicity schedule of the code generator (not part of the structure):
+    # "nest" sums the full helicity product as a loop nest over the legs (each
+    # call in the innermost loop its inputs need); "rows" evaluates the
+    # helicity table row by row, every call in IR order with its momenta and
+    # denominators formed where they are used and each amplitude added to its
+    # flows at once, so that the live set follows the program (the paper's
+    # recycling of temporaries, Sec. 5.5): for diagram sums too large for the
+    # nest's registers.
+    helicity_schedule: str = "nest"
+    # Function division of the rows schedule (the paper's Sec. 5.3, a
+    # code-generation setting): the amplitudes in this many groups, each
+    # evaluated by a device function of its own (1: one piece)
+    row_parts: int = 1
 
     def uses_colour_mfma(self):
         """The FP64 colour quadratic form runs on MFMA for ordering templates
@@ -198,6 +211,21 @@ class Process:
                 m = max(m, c.out)
         return m + 1
 
+    def colour_compression(self):
+        """What the compressed colour form (Sec. 5.4) saves: the distinct
+        factors it multiplies by (the non-zero entries on and above the
+        diagonal, the off-diagonal ones doubled), the multiply-adds of the
+        dense form (one per such entry) and the multiplications of the
+        compressed one (one per distinct factor of each row)."""
+        n = self.n_flows
+        distinct, mults = set(), 0
+        for f in range(n):
+            vals = {Fraction(self.colour[f][g]) * (1 if g == f else 2) for g in range(f, n) if self.colour[f][g] != 0}
+            distinct |= vals
+            mults += len(vals)
+        return {"flows": n, "distinct_factors": len(distinct), "dense_multiply_adds": n * (n + 1) // 2,
+                "compressed_multiplications": mults}
+
     def colour_denominator(self):
         d = 1
         for row in self.colour:
@@ -210,6 +238,10 @@ class Process:
             raise ValueError(f"unknown colour form {self.colour_form}")
         if self.division not in DIVISIONS:
             raise ValueError(f"unknown division {self.division}")
+        if self.helicity_schedule not in ("nest", "rows"):
+            raise ValueError(f"unknown helicity schedule {self.helicity_schedule}")
+        if self.helicity_schedule == "rows" and self.orderings is not None:
+            raise ValueError("the rows schedule applies to diagram call lists, not ordering templates")
         if self.division == "split" and self.orderings is None:
             raise ValueError("the split division applies to ordering templates")
         kinds = {i: leg.kind for i, leg in enumerate(self.legs)}

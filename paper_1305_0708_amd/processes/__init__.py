@@ -11,6 +11,7 @@ Leg order (the momentum layout of heget_eval):
   gg_ttbar_6f  g g b e+ nu_e bbar mu- nu_mu~      (t -> b e+ nu_e, tbar -> bbar mu- nu_mu~)
   ud_udhh_4b   u d u d b bbar b bbar              (H -> b bbar twice)
   gg_4g        g g g g g g   (120 trace-basis flows; gg_4g_ddm: the 24 evaluated orderings as flows)
+  uu_ttggg     u ubar t tbar g g g   (393 Feynman diagrams, 48 colour flows; uu_ttg, uu_ttgg: 1, 2 gluons)
 """
 import copy
 import dataclasses
@@ -85,8 +86,10 @@ def gg_ttbar_6f_bw(sqrt_s=1000.0):
             (P_TOP, BW, 5, -5),                # t~ -> b~ W-
             (P_W, BW, 3, 4),                   # W+ -> e+ nu_e
             (P_W, BW, 6, 7)]                   # W- -> mu- nu_mu~
+    # with the resonance tree's weight in the kernel, the 64-combination unroll
+    # measured a little faster than 32
     return dataclasses.replace(gg_ttbar_6f(sqrt_s), name="gg_ttbar_6f_bw", ps_tree=tree,
-                               ps_window=20.0).validate()
+                               ps_window=20.0, nest_unroll=64).validate()
 
 
 def ud_udhh_4b(sqrt_s=2000.0):
@@ -138,7 +141,7 @@ def ud_udhh_4b(sqrt_s=2000.0):
     colour = [[Fraction(cq[a % 2][b % 2] * cq[a // 2][b // 2]) for b in range(4)] for a in range(4)]
     return Process("ud_udhh_4b", legs, cpl, calls, n_amps=amp, n_flows=4, jamp=jamp, colour=colour,
                    helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=9, symmetry=4,
-                   sm_overrides={"complex_mass": 1}, nest_unroll=32).validate()
+                   sm_overrides={"complex_mass": 1}, nest_unroll=64).validate()
 
 
 def ud_udhhh(sqrt_s=2000.0):
@@ -210,7 +213,7 @@ def ud_udhhh(sqrt_s=2000.0):
             (P_ZERO, ir.PS_FLAT, 5, 6)]
     return Process("ud_udhhh", legs, cpl, calls, n_amps=amp, n_flows=2, jamp=jamp, colour=colour,
                    helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=9, symmetry=6,
-                   sm_overrides={"complex_mass": 1}, ps_tree=tree).validate()
+                   sm_overrides={"complex_mass": 1}, ps_tree=tree, nest_unroll=64).validate()
 
 
 def ww_ww(sqrt_s=1000.0):
@@ -268,7 +271,7 @@ def by_name(name):
         return copy.deepcopy(_gluons(*gluon[name]))
     # the same processes with the colour form compressed to its distinct colour
     # factors (Sec. 5.4): the FP32 kernels run it on VALU
-    compressed = {"gg_4g_cf": "gg_4g", "gg_5g_cf": "gg_5g_ddm"}
+    compressed = {"gg_4g_cf": "gg_4g", "gg_5g_cf": "gg_5g_ddm", "uu_ttggg_cf": "uu_ttggg"}
     if name in compressed:
         p = by_name(compressed[name])
         p.name, p.colour_form = name, "compressed"
@@ -280,6 +283,11 @@ def by_name(name):
         p = by_name(split[name])
         p.name, p.division = name, "split"
         return p.validate()
+    # u ubar -> t tbar + n gluons: every Feynman diagram, its colour in a basis of flows
+    quark_lines = {"uu_ttg": 1, "uu_ttgg": 2, "uu_ttggg": 3}
+    if name in quark_lines:
+        from .quark_lines import uu_ttbar_gluons
+        return uu_ttbar_gluons(quark_lines[name])
     return {"ee_mumu": ee_mumu, "gg_ttbar_6f": gg_ttbar_6f, "gg_ttbar_6f_bw": gg_ttbar_6f_bw,
             "ud_udhh_4b": ud_udhh_4b, "ud_udhhh": ud_udhhh, "ww_ww": ww_ww,
             "gg_ttbar_6f_had": gg_ttbar_6f_had}[name]()

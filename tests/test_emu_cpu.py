@@ -70,3 +70,44 @@ def test_mfma_colour_form_on_ragged_launches(emu_lib, oracle, name, prec, n, cus
         assert err.max() <= 1e-12
     else:
         assert np.median(err) < 1e-5 and err.max() < 1e-4
+
+
+# ---------------------------------------------------- diagram call lists (quark lines)
+QL_OUT = os.path.join(EMU, "_build", "quark_lines")
+
+
+@pytest.fixture(scope="module")
+def emu_ql():
+    sys.path.insert(0, EMU)
+    import build_emu
+    if not os.path.exists(build_emu.CXX) or not build_emu.asan_runtime():
+        pytest.skip("host clang++ with the AddressSanitizer runtime not available")
+    lib = build_emu.build(processes=("uu_ttg", "uu_ttgg"), out=QL_OUT)
+    return lib, build_emu.asan_runtime()
+
+
+@pytest.mark.parametrize("name,prec", [("uu_ttg", "fp64"), ("uu_ttgg", "fp64"), ("uu_ttgg", "mixed")])
+def test_quark_line_kernels(emu_ql, oracle, name, prec):
+    """u ubar -> t tbar + 1 gluon (the helicity loop nest) and + 2 gluons (the
+    helicity rows one at a time, the program divided into two device
+    functions) on the oracle's momenta: no invalid access, events failing the
+    cut exactly 0, the rest within 1e-12 of the oracle in FP64 (FP32's scale
+    in mixed precision)"""
+    import fp64_bounds as B
+    lib, asan = emu_ql
+    mom = B.tree_events(oracle, name)[0][:45]
+    path = os.path.join(QL_OUT, f"mom_{name}.npy")
+    np.save(path, np.ascontiguousarray(np.transpose(mom, (1, 2, 0))))
+    out = os.path.join(QL_OUT, f"run_{name}_{prec}.npz")
+    env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", EMU_LANE_ORDER="0",
+               EMU_CUS="1")
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_emu.py"), lib, name, prec, str(len(mom)), "0x1", out,
+                        path], env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, f"emulated {name} {prec}: rc {r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
+    me2 = np.load(out)["me2"]
+    ref = B.reference(oracle, name, mom, extended=False)
+    nz = ref != 0
+    assert np.all(me2[~nz] == 0.0)
+    err = np.abs(me2[nz] - ref[nz]) / ref[nz]
+    print(f"emulated {name} {prec}: max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() <= (1e-12 if prec == "fp64" else 1e-5)
