@@ -42,9 +42,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "8a50181d071452a02355c329da1f36dc329492141e6c4e8e64e9f07fa60e6dce",
-                 "fetch_kib": 480.5, "fetch_scale": 2.0, "write_kib": 8192.0, "write_scale": 1.0,
-                 "flop_per_event": 29268, "flop_per_event_mixed": 26619}
+COUNTERS_FP64 = {"source_digest": "978850fecfaaa50a3f6dc706724da479e05629fa51c68b4d3855e850938012c5",
+                 "fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 8192.0, "write_scale": 1.0,
+                 "flop_per_event": 18297, "flop_per_event_mixed": 15987}
 
 
 # Counter measurements of further kernels, (process, precision) -> figures per
@@ -56,38 +56,34 @@ COUNTERS_FP64 = {"source_digest": "8a50181d071452a02355c329da1f36dc329492141e6c4
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "3a21049b453be33fc3deebd728892f19c6c59c625fafb3d903bbe693f2093587",
-        "valu_flop_per_event": 16188, "fp64_flop_per_event": 2818, "events": 1 << 21, "kernel_s": 0.702e-3,
+        "source_digest": "676cc10eb2eadc4dcf18963f2bd83d0df21702cad2a54c5b228360f22767fdd2",
+        "valu_flop_per_event": 7503, "fp64_flop_per_event": 2770, "events": 1 << 21, "kernel_s": 0.481e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "3a21049b453be33fc3deebd728892f19c6c59c625fafb3d903bbe693f2093587",
-        "valu_flop_per_event": 19006, "events": 1 << 21, "kernel_s": 1.365e-3,
+        "source_digest": "676cc10eb2eadc4dcf18963f2bd83d0df21702cad2a54c5b228360f22767fdd2",
+        "valu_flop_per_event": 10273, "events": 1 << 21, "kernel_s": 0.745e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
-        "source_digest": "1fb61a4c3ce3211e1dc3981ff683a543d13741de94e7d4d258de0be1bd5ea2f9",
-        "valu_flop_per_event": 25152814, "events": 1 << 18, "kernel_s": 506.0e-3,
+        "source_digest": "014b1dbe93b8a767249ecfa14906abcf8d24a314a1eb90c384a8c2f7dab6ed59",
+        "valu_flop_per_event": 26981422, "events": 1 << 18, "kernel_s": 275.4e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
-    ("uu_ttggg", "mixed"): {
-        "source_digest": "1fb61a4c3ce3211e1dc3981ff683a543d13741de94e7d4d258de0be1bd5ea2f9",
-        "valu_flop_per_event": 23745920, "fp64_flop_per_event": 1334190, "events": 1 << 18, "kernel_s": 163.6e-3,
-        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "ed41d8cca4c2dc7d108ca2bcab2762e8a67565983ea5773729391468a5af4ff7",
-        "valu_flop_per_event": 3664405, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.9e-3,
+        "source_digest": "965f809e37b1dd662ba03e1fd50c641cc574c826fa3bf4ab6e713d2e4dac43a0",
+        "valu_flop_per_event": 3664405, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.8e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "ee27ad6794e02406920daa721a942580566f63b62c9de9a578fb72afb1f2e4d9",
-        "valu_flop_per_event": 3608085, "events": 1 << 20, "kernel_s": 96.6e-3,
+        "source_digest": "83651882e11e0714b034447b2debce77d8af645ea7f1811f650fbcc07220d2e6",
+        "valu_flop_per_event": 3608085, "events": 1 << 20, "kernel_s": 96.1e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "ee27ad6794e02406920daa721a942580566f63b62c9de9a578fb72afb1f2e4d9",
-        "valu_flop_per_event": 2911487, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 65.6e-3,
+        "source_digest": "83651882e11e0714b034447b2debce77d8af645ea7f1811f650fbcc07220d2e6",
+        "valu_flop_per_event": 2911487, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 66.1e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "3c5ff0b7d61754224dabbedce5f0b8e7e5d52a12bef07e6cf0087903d1ecbae7",
-        "valu_flop_per_event": 3890815, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 90.1e-3,
+        "source_digest": "98da5af308d957512950f5b76a1237de33acd541d7000bc48f74d95bda42d4b2",
+        "valu_flop_per_event": 3890815, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 90.8e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 

@@ -86,6 +86,20 @@ def _coef_expr(c, a):
     return f"(mk<T>(T({_c(c.real)}), T({_c(c.imag)})) * {a})"
 
 
+def _coupling_decls(k, kind, ind="  "):
+    """the two coupling values of coupling k, with the parts that the
+    library's coupling of this kind fixes at zero (or equal) as constants"""
+    im = lambda j: f"T(a.cpl[{4 * k + j}])" if kind in ir.CPL_COMPLEX else "T(0)"
+    g0 = f"{ind}const cx<T> g{k}_0 = mk<T>(T(a.cpl[{4 * k}]), {im(1)});"
+    if kind in ir.CPL_G1_EQ_G0:
+        g1 = f"{ind}const cx<T> g{k}_1 = g{k}_0;"
+    elif kind in ir.CPL_G1_FREE:
+        g1 = f"{ind}const cx<T> g{k}_1 = mk<T>(T(a.cpl[{4 * k + 2}]), {im(3)});"
+    else:
+        g1 = f"{ind}const cx<T> g{k}_1 = mk<T>(T(0), T(0));"
+    return [g0, g1]
+
+
 def _flowing_in(leg):
     return (leg.incoming and leg.flow > 0) or ((not leg.incoming) and leg.flow < 0)
 
@@ -196,8 +210,8 @@ class Gen:
             w(f"  const bool pass = {live};")
         w("  // couplings and propagator data (uniform)")
         for k, c in enumerate(p.couplings):
-            w(f"  const cx<T> g{k}_0 = mk<T>(T(a.cpl[{4 * k}]), T(a.cpl[{4 * k + 1}]));")
-            w(f"  const cx<T> g{k}_1 = mk<T>(T(a.cpl[{4 * k + 2}]), T(a.cpl[{4 * k + 3}]));")
+            for line in _coupling_decls(k, c.kind):
+                w(line)
         used = sorted({c.prop for c in p.calls} | {leg.particle for leg in p.legs} | {P_ZERO})
         for pid in used:
             w(f"  const PropEntry pe{pid} = a.prop[{pid}];")
@@ -458,14 +472,22 @@ class Gen:
                 self._kin[f"d{n}_{pid}"] = "cx<T>"
 
     # ---------------------------------------------------------- straight-line
-    def _row_groups(self):
+    def _row_groups(self, parts):
         """the amplitude calls of the rows schedule in groups of consecutive
         amplitudes, one per part of the function division (one group: no
         division)"""
-        p = self.p
-        amps = [i for i, c in enumerate(p.calls) if c.op in AMP_OPS]
-        size = -(-len(amps) // max(1, p.row_parts))
+        amps = [i for i, c in enumerate(self.p.calls) if c.op in AMP_OPS]
+        size = -(-len(amps) // max(1, parts))
         return [amps[i:i + size] for i in range(0, len(amps), size)]
+
+    def _row_divisions(self):
+        """(precision test, function-name tag, groups) of the FP64 and FP32
+        kernels: one division for both when they have the same number of parts"""
+        p = self.p
+        n64, n32 = p.row_parts, p.row_parts_mixed or p.row_parts
+        if n64 == n32:
+            return [("true", "", self._row_groups(n64))]
+        return [("sizeof(T) == 8", "d", self._row_groups(n64)), ("sizeof(T) == 4", "f", self._row_groups(n32))]
 
     def _closure(self, idxs):
         """the calls that the given calls need, in IR order"""
@@ -552,18 +574,22 @@ class Gen:
         w(f"// the event's physical momenta, one column per lane, read by every part")
         w(f"__shared__ mom pm_{p.name}[{self.nl}][256];")
         w("")
-        groups = self._row_groups()
-        if len(groups) < 2:
-            return
+        for _, tag, groups in self._row_divisions():
+            if len(groups) > 1:
+                self._emit_parts_of(w, tag, groups)
+
+    def _emit_parts_of(self, w, tag, groups):
+        p = self.p
         for k, grp in enumerate(groups):
             idxs = self._closure(grp)
-            w(f"// part {k}: amplitudes {p.calls[grp[0]].out} .. {p.calls[grp[-1]].out} ({len(idxs)} calls)")
+            w(f"// part {k}{f' ({tag})' if tag else ''}: amplitudes {p.calls[grp[0]].out} .. {p.calls[grp[-1]].out} "
+              f"({len(idxs)} calls)")
             w("template <class T>")
-            w(f"__device__ __noinline__ void rows_{p.name}_part{k}(const KernelArgs& a, const int8_t* hh, cx<T>* J) {{")
+            w(f"__device__ __noinline__ void rows_{p.name}{tag}_part{k}(const KernelArgs& a, const int8_t* hh, cx<T>* J) {{")
             cpls = sorted({p.calls[i].cpl for i in idxs if p.calls[i].cpl >= 0})
             for c in cpls:
-                w(f"  const cx<T> g{c}_0 = mk<T>(T(a.cpl[{4 * c}]), T(a.cpl[{4 * c + 1}]));")
-                w(f"  const cx<T> g{c}_1 = mk<T>(T(a.cpl[{4 * c + 2}]), T(a.cpl[{4 * c + 3}]));")
+                for line in _coupling_decls(c, p.couplings[c].kind):
+                    w(line)
             pids = sorted({p.calls[i].prop for i in idxs} | {leg.particle for leg in p.legs} | {P_ZERO})
             for pid in pids:
                 w(f"  const PropEntry pe{pid} = a.prop[{pid}];")
@@ -583,17 +609,19 @@ class Gen:
         w("  if (pass) {")
         w("    for (int h = 0; h < a.n_hel; ++h) {")
         w(f"      const int8_t* hh = a.hel + h * {nl};")
-        groups = self._row_groups()
-        if len(groups) < 2:
-            w(f"      cx<T> {', '.join(f'J{f} = mk<T>(T(0), T(0))' for f in range(p.n_flows))};")
-            self._emit_row_calls(w, "      ", list(range(len(p.calls))), lambda f: f"J{f}")
-            self._colour_form(w, lambda f: f"J{f}", "      ")
-        else:
-            w(f"      cx<T> J[{p.n_flows}];")
-            w(f"      for (int f = 0; f < {p.n_flows}; ++f) J[f] = mk<T>(T(0), T(0));")
-            for k in range(len(groups)):
-                w(f"      rows_{p.name}_part{k}<T>(a, hh, J);")
-            self._colour_form(w, lambda f: f"J[{f}]", "      ")
+        for cond, tag, groups in self._row_divisions():
+            w(f"      if constexpr ({cond}) {{")
+            if len(groups) < 2:
+                w(f"        cx<T> {', '.join(f'J{f} = mk<T>(T(0), T(0))' for f in range(p.n_flows))};")
+                self._emit_row_calls(w, "        ", list(range(len(p.calls))), lambda f: f"J{f}")
+                self._colour_form(w, lambda f: f"J{f}", "        ")
+            else:
+                w(f"        cx<T> J[{p.n_flows}];")
+                w(f"        for (int f = 0; f < {p.n_flows}; ++f) J[f] = mk<T>(T(0), T(0));")
+                for k in range(len(groups)):
+                    w(f"        rows_{p.name}{tag}_part{k}<T>(a, hh, J);")
+                self._colour_form(w, lambda f: f"J[{f}]", "        ")
+            w("      }")
         w("    }")
         w("  }")
 

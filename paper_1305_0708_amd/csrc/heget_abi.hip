@@ -336,6 +336,21 @@ void coupling_values(const heget_sm& sm, const heget_coupling& c, double out[4])
   out[3] = g1.imag();
 }
 
+// The generated kernels take what coupling_values fixes by construction as
+// constants (every kind real but W W H and Z Z H; g1 = g0 for the vector
+// couplings; g1 = 0 for the W-fermion and the boson vertices): a change here
+// that broke it would give wrong amplitudes, so create checks the values.
+bool coupling_structure_ok(int kind, const double v[4]) {
+  if (kind != HEGET_CPL_WWH && kind != HEGET_CPL_ZZH && (v[1] != 0.0 || v[3] != 0.0)) return false;
+  switch (kind) {
+    case HEGET_CPL_GAMMA_FF:
+    case HEGET_CPL_G_QQ:
+    case HEGET_CPL_HBB: return v[2] == v[0] && v[3] == v[1];
+    case HEGET_CPL_Z_FF: return true;
+    default: return v[2] == 0.0 && v[3] == 0.0;
+  }
+}
+
 void prop_table(const heget_sm& sm, PropEntry t[HEGET_N_PARTICLES]) {
   const Derived d = derive(sm);
   auto fill = [](PropEntry& e, double m, double w, cd pole, cd num) {
@@ -671,7 +686,13 @@ heget_status heget_process_create(const heget_process_ir* ir, heget_precision pr
   p->hel.assign(ir->helicities, ir->helicities + size_t(ir->n_hel) * ir->n_legs);
   p->hel_nest = heget::detail::is_full_product(entry, ir->helicities, ir->n_hel, ir->n_legs) ? 1 : 0;
   std::vector<double> cpl(size_t(ir->n_couplings) * 4);
-  for (int k = 0; k < ir->n_couplings; ++k) coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
+  for (int k = 0; k < ir->n_couplings; ++k) {
+    coupling_values(ir->sm, ir->couplings[k], &cpl[4 * k]);
+    if (!coupling_structure_ok(ir->couplings[k].kind, &cpl[4 * k])) {
+      release(p);
+      return fail(HEGET_E_UNSUPPORTED, "coupling " + std::to_string(k) + " breaks the structure the kernels assume");
+    }
+  }
   PropEntry prop[HEGET_N_PARTICLES];
   prop_table(ir->sm, prop);
   p->hadronic = ir->ps_hadron_ymax > 0 ? 1 : 0;

@@ -61,6 +61,16 @@ IN_KINDS = {
 CPL_KINDS = ["gamma_ff", "z_ff", "w_ff", "g_qq", "ggg", "gggg", "wwz", "wwa",
              "wwh", "zzh", "wwhh", "zzhh", "hhh", "hhhh", "hbb", "wwww", "wwzz"]
 CPL = {name: i for i, name in enumerate(CPL_KINDS)}
+# What the library's coupling values fix whatever the SM inputs (its
+# coupling_values; the same facts are checked there at create): every kind is
+# real except the W W H and Z Z H couplings (complex masses in the
+# complex-mass scheme); the fermion kinds with a vector coupling have g1 = g0;
+# the W-fermion coupling is left-handed (g1 = 0), and a boson vertex has no g1.
+# The generated kernels take them as constants, so the compiler drops the
+# arithmetic on the zero parts; the values that remain are used as before.
+CPL_COMPLEX = {"wwh", "zzh"}
+CPL_G1_EQ_G0 = {"gamma_ff", "g_qq", "hbb"}
+CPL_G1_FREE = {"z_ff"}
 
 
 @dataclass(frozen=True)
@@ -189,6 +199,8 @@ class Process:
     # code-generation setting): the amplitudes in this many groups, each
     # evaluated by a device function of its own (1: one piece)
     row_parts: int = 1
+    # the same for the FP32 (mixed-precision) kernel; 0: as row_parts
+    row_parts_mixed: int = 0
 
     def uses_colour_mfma(self):
         """The FP64 colour quadratic form runs on MFMA for ordering templates
@@ -238,6 +250,8 @@ class Process:
             raise ValueError(f"unknown colour form {self.colour_form}")
         if self.division not in DIVISIONS:
             raise ValueError(f"unknown division {self.division}")
+        if self.row_parts < 1 or self.row_parts_mixed < 0:
+            raise ValueError("row_parts >= 1, row_parts_mixed >= 0")
         if self.helicity_schedule not in ("nest", "rows"):
             raise ValueError(f"unknown helicity schedule {self.helicity_schedule}")
         if self.helicity_schedule == "rows" and self.orderings is not None:

@@ -334,11 +334,14 @@ def uu_ttbar_gluons(ng=3, sqrt_s=1000.0, name=None, parts=None):
     > 0.4 (the cut applies to the tops as well).  Phase space: the collision
     decays to t + X, X to tbar + Y, ... in flat two-body steps."""
     calls, n_amps, flows, jamp, colour = _build(ng)
+    parts_mixed = 0
     if parts is None:
-        # the function division: about 40 amplitudes per device function (two
-        # parts for two gluons, where one would do, so that the small process
-        # runs the divided code too)
-        parts = max(2, -(-n_amps // 40)) if ng >= 2 else 1
+        # the function division, measured on MI355X for three gluons: about 20
+        # amplitudes per device function in FP64 (20 parts: 291 ms per 2^18
+        # events; 10 parts: 506 ms), about 40 in FP32 (10 parts: 164 ms; 20:
+        # 184 ms).  Two gluons: two parts, where one would do, so that the small
+        # process runs the divided code too.
+        parts, parts_mixed = (-(-n_amps // 20), -(-n_amps // 40)) if ng >= 3 else (2 if ng == 2 else 1, 0)
     legs = [Leg(F, True, +1, colour=3, name="u"), Leg(F, True, -1, colour=3, name="ubar"),
             Leg(F, False, +1, particle=P_TOP, colour=3, name="t"),
             Leg(F, False, -1, particle=P_TOP, colour=3, name="tbar")]
@@ -357,7 +360,8 @@ def uu_ttbar_gluons(ng=3, sqrt_s=1000.0, name=None, parts=None):
     return Process(name or f"uu_tt{'g' * ng}", legs, cpl, list(calls), n_amps=n_amps, n_flows=len(flows),
                    jamp=jamp, colour=colour, helicities=ir.all_helicities(legs), sqrt_s=sqrt_s,
                    n_a_n_b=9, symmetry=sym, cut_enabled=ng > 0, cut_pt=20.0, cut_dr=0.4, ps_tree=tree,
-                   helicity_schedule="rows" if ng >= 2 else "nest", row_parts=parts).validate()
+                   helicity_schedule="rows" if ng >= 2 else "nest", row_parts=parts,
+                   row_parts_mixed=parts_mixed).validate()
 
 
 def flow_strings(ng):
