@@ -42,9 +42,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "978850fecfaaa50a3f6dc706724da479e05629fa51c68b4d3855e850938012c5",
-                 "fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 8192.0, "write_scale": 1.0,
-                 "flop_per_event": 18297, "flop_per_event_mixed": 15987}
+COUNTERS_FP64 = {"source_digest": "72879baf64830d2d85dcd279033ee36a138f3c58829898569158c9bf06eefa4f",
+                 "fetch_kib": 3225.625, "fetch_scale": 2.0, "write_kib": 98119.375, "write_scale": 1.0,
+                 "flop_per_event": 4437, "flop_per_event_mixed": 2331}
 
 
 # Counter measurements of further kernels, (process, precision) -> figures per
@@ -56,34 +56,38 @@ COUNTERS_FP64 = {"source_digest": "978850fecfaaa50a3f6dc706724da479e05629fa51c68
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "676cc10eb2eadc4dcf18963f2bd83d0df21702cad2a54c5b228360f22767fdd2",
-        "valu_flop_per_event": 7503, "fp64_flop_per_event": 2770, "events": 1 << 21, "kernel_s": 0.481e-3,
+        "source_digest": "c0b67b046512c155af4933daf096de2b063e437899a56457d05e4925ebafeac7",
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2744, "events": 1 << 21, "kernel_s": 0.3625e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "676cc10eb2eadc4dcf18963f2bd83d0df21702cad2a54c5b228360f22767fdd2",
-        "valu_flop_per_event": 10273, "events": 1 << 21, "kernel_s": 0.745e-3,
+        "source_digest": "c0b67b046512c155af4933daf096de2b063e437899a56457d05e4925ebafeac7",
+        "valu_flop_per_event": 5748, "events": 1 << 21, "kernel_s": 0.4755e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
         "source_digest": "014b1dbe93b8a767249ecfa14906abcf8d24a314a1eb90c384a8c2f7dab6ed59",
         "valu_flop_per_event": 26981422, "events": 1 << 18, "kernel_s": 275.4e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
+    ("uu_ttggg", "mixed"): {
+        "source_digest": "014b1dbe93b8a767249ecfa14906abcf8d24a314a1eb90c384a8c2f7dab6ed59",
+        "valu_flop_per_event": 21813632, "fp64_flop_per_event": 1333934, "events": 1 << 18, "kernel_s": 153.3e-3,
+        "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "965f809e37b1dd662ba03e1fd50c641cc574c826fa3bf4ab6e713d2e4dac43a0",
-        "valu_flop_per_event": 3664405, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.8e-3,
+        "source_digest": "c921244ed9794a7f9df1a51c781107d0eab2544702f78a53877c368e62e22402",
+        "valu_flop_per_event": 3648277, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 171.1e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "83651882e11e0714b034447b2debce77d8af645ea7f1811f650fbcc07220d2e6",
-        "valu_flop_per_event": 3608085, "events": 1 << 20, "kernel_s": 96.1e-3,
+        "source_digest": "e95d70cd957b7f66dfdedc31a3f4f9fc08eb7054a95a9b15103445d057146947",
+        "valu_flop_per_event": 3591957, "events": 1 << 20, "kernel_s": 91.7e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "83651882e11e0714b034447b2debce77d8af645ea7f1811f650fbcc07220d2e6",
-        "valu_flop_per_event": 2911487, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 66.1e-3,
+        "source_digest": "e95d70cd957b7f66dfdedc31a3f4f9fc08eb7054a95a9b15103445d057146947",
+        "valu_flop_per_event": 2825855, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 64.2e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "98da5af308d957512950f5b76a1237de33acd541d7000bc48f74d95bda42d4b2",
-        "valu_flop_per_event": 3890815, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 90.8e-3,
+        "source_digest": "d3c99543e74d0ddad5bce00f071fc25402452a6d7989d1156e8ed5dde3019803",
+        "valu_flop_per_event": 3805183, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 88.9e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 
@@ -125,14 +129,15 @@ def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S, seed=SEED):
     return wall, kern, r
 
 
-def settle_clocks(torch, proc, seconds=0.5):
-    """untimed launches of the headline kernel for about half a second before
-    the warm-up steps, so that the GPU has left its idle clocks when timing
-    starts (the first timed steps of a fresh box otherwise run slow)"""
-    out = torch.empty(N_EVENTS, dtype=torch.float64, device="cuda")
+def settle_clocks(torch, proc, seconds=0.5, n=N_EVENTS, sqrt_s=SQRT_S):
+    """untimed launches of the kernel about to be timed for about half a
+    second before the warm-up steps, so that the GPU has left its idle clocks
+    when timing starts (the first timed steps of a fresh box otherwise run
+    slow)"""
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        proc.eval(n=N_EVENTS, seed=SEED, sqrt_s=SQRT_S, me2_out=out)
+        proc.eval(n=n, seed=SEED, sqrt_s=sqrt_s, me2_out=out)
         torch.cuda.synchronize()
 
 
@@ -452,6 +457,7 @@ def main():
         proc = H.Process(pir, precision=args.profile_leg)
         n = {"gg_5g_ddm": 1 << 16, "gg_5g_cf": 1 << 16, "gg_5g_split": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536,
              "uu_ttggg": 1 << 18, "uu_ttggg_cf": 1 << 18}.get(args.profile_proc, N_EVENTS)
+        settle_clocks(torch, proc, n=n, sqrt_s=pir.sqrt_s)
         wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
                "kernel_ms": kern * 1e3, "events_per_launch": n, "events_per_s": n / wall,

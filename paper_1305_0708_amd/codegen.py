@@ -246,7 +246,8 @@ class Gen:
         w("// kernels: one workspace slot per block), or, for a fused launch of the")
         w("// serving engine, the virtual blocks of its batch table")
         w("template <class T>")
-        w(f"__global__ __launch_bounds__(256) void amp_{p.name}(KernelArgs a) {{")
+        lb = f"256, {p.waves_per_simd}" if p.waves_per_simd > 1 else "256"
+        w(f"__global__ __launch_bounds__({lb}) void amp_{p.name}(KernelArgs a) {{")
         if p.uses_colour_mfma():
             w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")
         w("  const BatchTable* bt = a.batch;")
@@ -903,7 +904,8 @@ class Gen:
             if all(rv and lvl >= first_real for lvl, rv in us):
                 cand.append((min(lvl for lvl, _ in us), nm))
         loads, off = {}, 0
-        budget = min(STASH_WORDS, NEST_LDS_WORDS - inner_words) if inner_words else STASH_WORDS
+        cap = min(STASH_WORDS, self.p.stash_words)
+        budget = min(cap, NEST_LDS_WORDS - inner_words) if inner_words else cap
         for lvl, nm in sorted(cand, key=lambda c: (c[0], list(self._kin).index(c[1]))):
             n = _KIN_WORDS[self._kin[nm]]
             if off + n > budget:
@@ -1338,7 +1340,8 @@ class Gen:
             ch = sc.choices[k]
             if ch != (-1, 1):
                 raise NotImplementedError("template nests need two-state positions")
-            w(f"{ind}#pragma unroll 1")
+            unrolled = lvl >= len(sc.order) - p.template_unroll
+            w(f"{ind}#pragma unroll{'' if unrolled else ' 1'}")
             w(f"{ind}for (int c{k} = 0; c{k} < 2; ++c{k}) {{")
             ind += "  "
             w(f"{ind}const int hp{k} = 2 * c{k} - 1;")

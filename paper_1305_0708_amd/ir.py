@@ -186,6 +186,15 @@ class Process:
     # take table entries and the helicities of massless spinors as constants,
     # at the price of code size and registers)
     nest_unroll: int = 8
+    # Waves per SIMD the kernel is compiled for (a code-generation setting: the
+    # compiler keeps the registers within 512 / waves_per_simd per lane), and the
+    # words per lane of the nest's LDS stash of event kinematics (with two waves
+    # per SIMD two blocks must fit the CU's LDS)
+    waves_per_simd: int = 1
+    stash_words: int = 64
+    # Ordering templates: the number of innermost helicity loops of one
+    # ordering's nest that the kernel unrolls (a code-generation setting)
+    template_unroll: int = 0
     # Helicity schedule of the code generator (not part of the structure):
     # "nest" sums the full helicity product as a loop nest over the legs (each
     # call in the innermost loop its inputs need); "rows" evaluates the
@@ -250,6 +259,8 @@ class Process:
             raise ValueError(f"unknown colour form {self.colour_form}")
         if self.division not in DIVISIONS:
             raise ValueError(f"unknown division {self.division}")
+        if self.waves_per_simd not in (1, 2, 3, 4) or not 0 <= self.stash_words <= 64:
+            raise ValueError("waves_per_simd in 1..4, stash_words in 0..64")
         if self.row_parts < 1 or self.row_parts_mixed < 0:
             raise ValueError("row_parts >= 1, row_parts_mixed >= 0")
         if self.helicity_schedule not in ("nest", "rows"):

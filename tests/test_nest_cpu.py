@@ -91,19 +91,26 @@ def test_tables_are_valid(name):
 
 
 def test_c1_tables_and_stash_in_the_generated_kernel():
-    """C1 with its five innermost loops unrolled (its own setting) needs no
-    tables: the gluon states are constants of the unrolled code.  With only the
-    three fermion loops unrolled, the gg -> g* current is tabulated before the
-    loops over both gluon helicities and the top current over gluon 1 inside
-    the b-quark loop; the stash fits its budget and the flop model counts the
-    tables."""
+    """C1 with its whole nest unrolled (its own setting, compiled for two
+    waves per SIMD) needs no tables and no stash: every helicity is a constant
+    of the unrolled code.  With five loops unrolled there are no tables either;
+    with only the three fermion loops unrolled, the gg -> g* current is
+    tabulated before the loops over both gluon helicities and the top current
+    over gluon 1 inside the b-quark loop; the stash fits its budget and the
+    flop model counts the tables."""
     import dataclasses
     from paper_1305_0708_amd import codegen
     c1 = processes.by_name("gg_ttbar_6f")
     sc1 = nest.schedule(c1)
-    assert len(nest.unrolled_levels(sc1)) == 5
-    assert nest.tables(c1, sc1, nest.unrolled_levels(sc1)) == {}
-    assert "t12_" not in codegen.Gen(c1).emit()
+    assert len(nest.unrolled_levels(sc1)) == 8
+    src1 = codegen.Gen(c1).emit()
+    assert "t12_" not in src1 and "stash_put(" not in src1
+    assert "__launch_bounds__(256, 2) void amp_gg_ttbar_6f" in src1
+    c5 = dataclasses.replace(c1, nest_unroll=32)
+    sc5 = nest.schedule(c5)
+    assert len(nest.unrolled_levels(sc5)) == 5
+    assert nest.tables(c5, sc5, nest.unrolled_levels(sc5)) == {}
+    assert "t12_" not in codegen.Gen(c5).emit()
     p = dataclasses.replace(c1, nest_unroll=8)
     src = codegen.Gen(p).emit()
     assert "jvvxxx<T, false>(x0m, Qs0, x1m, Qs1" in src
