@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -861,6 +862,19 @@ heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, i
   return HEGET_OK;
 }
 
+namespace {
+// Wait for the stream: poll it for up to 200 us before a blocking wait.  An
+// integrate step's result is usually that close, and waking from a blocking
+// wait takes longer than the poll.
+hipError_t wait_stream(hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t q;
+  while ((q = hipStreamQuery(st)) == hipErrorNotReady)
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(200)) return hipStreamSynchronize(st);
+  return q;
+}
+}  // namespace
+
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
                              void* stream) {
   g_err.clear();
@@ -893,11 +907,11 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
   a.partials = d_part;
   heget_status rc = launch(p, a, st);
   if (rc == HEGET_OK) {
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, d_part + 3 * nblocks);
+    // the reduction writes its three sums straight into the pinned result
+    // buffer (host memory the device can write): no separate copy back
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, p->h_res);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(p->h_res, d_part + 3 * nblocks, 3 * sizeof(double),
-                                            hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = wait_stream(st);
     if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
   }
   if (rc != HEGET_OK) return rc;

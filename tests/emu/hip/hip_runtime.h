@@ -82,6 +82,7 @@ typedef enum hipError_t {
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
   hipErrorInvalidDevice = 101,
+  hipErrorNotReady = 600,
   hipErrorLaunchFailure = 719
 } hipError_t;
 typedef struct emu_stream* hipStream_t;
@@ -111,6 +112,7 @@ hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k);
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st = nullptr);
 hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t st = nullptr);
 hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipStreamQuery(hipStream_t s);
 hipError_t hipDeviceSynchronize();
 hipError_t hipGetDevice(int* d);
 hipError_t hipGetLastError();

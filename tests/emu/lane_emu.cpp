@@ -340,6 +340,7 @@ hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
   return hipSuccess;
 }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamQuery(hipStream_t) { return hipSuccess; }
 hipError_t hipDeviceSynchronize() { return hipSuccess; }
 hipError_t hipGetDevice(int* d) {
   *d = 0;
