@@ -104,20 +104,40 @@ def measured_traffic(proc_ir):
     return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
-def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S, seed=SEED):
-    """Per step: one heget_integrate (amplitude kernel + reduction).  Also
-    times the amplitude kernel alone with HIP events on the launch stream."""
-    for _ in range(warmup):
-        proc.integrate(n, seed=seed, sqrt_s=sqrt_s)
+def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S, seed=SEED, synchronous_too=False):
+    """Per step: one integrate step of n events (Philox, phase space, the
+    amplitude kernel with its per-block partial sums, the fixed-order
+    reduction) queued with heget_integrate_async, its three sums into a row of
+    a device buffer; the steps run back to back and the host waits once, after
+    the last.  Every step's result is read back and turned into a cross
+    section after the timed region.  With synchronous_too also the
+    heget_integrate call, which waits for each step's result.  Also times the
+    amplitude kernel alone with HIP events on the launch stream.
+    Returns (seconds per step, kernel seconds, last step's result, seconds per
+    synchronous step or None)."""
+    sums = torch.empty((max(steps, warmup, 1), 3), dtype=torch.float64, device="cuda")
+    rows = [sums[k] for k in range(sums.shape[0])]
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        proc.integrate_async(n, rows[k], seed=seed, sqrt_s=sqrt_s, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        r = proc.integrate(n, seed=seed + k, sqrt_s=sqrt_s)
+        proc.integrate_async(n, rows[k], seed=seed + k, sqrt_s=sqrt_s, stream=stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
+    res = [proc.result_from_sums(row, n) for row in sums[:steps].cpu().tolist()]
+    r = res[-1]
+    wall_sync = None
+    if synchronous_too:
+        t0 = time.perf_counter()
+        for k in range(steps):
+            rs = proc.integrate(n, seed=seed + k, sqrt_s=sqrt_s, stream=stream)
+        torch.cuda.synchronize()
+        wall_sync = (time.perf_counter() - t0) / steps
+        assert rs == r, "the synchronous call must give the queued step's result"
     # amplitude kernel alone: eval with |M|^2 written, timed with events on the stream it runs on
     out = torch.empty(n, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     proc.eval(n=n, seed=seed, sqrt_s=sqrt_s, me2_out=out)
     ev0.record(stream)
@@ -126,7 +146,7 @@ def time_path(torch, proc, steps, warmup, n=N_EVENTS, sqrt_s=SQRT_S, seed=SEED):
     ev1.record(stream)
     ev1.synchronize()
     kern = ev0.elapsed_time(ev1) / 1e3 / steps
-    return wall, kern, r
+    return wall, kern, r, wall_sync
 
 
 def settle_clocks(torch, proc, seconds=0.5, n=N_EVENTS, sqrt_s=SQRT_S):
@@ -182,7 +202,7 @@ def resonance_leg(torch, H, processes, steps, warmup, r_rambo):
     against RAMBO's.  The tree's sigma is the rate inside the resonance windows,
     RAMBO's the whole phase space."""
     proc = H.Process(processes.gg_ttbar_6f_bw(), precision="fp64")
-    wall, kern, r = time_path(torch, proc, steps, warmup)
+    wall, kern, r, _ = time_path(torch, proc, steps, warmup)
     return {"workload": "gg->ttbar->6f as configured, events from the resonance tree "
                         "(t, tbar, W+, W- Breit-Wigner mapped) instead of RAMBO",
             "events_per_s": N_EVENTS / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
@@ -238,7 +258,7 @@ def config_leg(torch, H, pir, workload, steps, warmup, n=N_EVENTS, precisions=("
         except H.HegetError as e:
             out[prec] = {"refused": str(e)}
             continue
-        wall, kern, r = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s, seed=seed)
+        wall, kern, r, _ = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s, seed=seed)
         out[prec] = {"events_per_s": n / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
                      "sigma_pb": r["sigma_pb"], "sigma_err_pb": r["err_pb"], "n_accepted": r["n_accepted"]}
         cf = counter_figures(pir, prec, kern, n)
@@ -458,7 +478,7 @@ def main():
         n = {"gg_5g_ddm": 1 << 16, "gg_5g_cf": 1 << 16, "gg_5g_split": 1 << 16, "ud_udhh_4b": 1 << 21, "ee_mumu": 65536,
              "uu_ttggg": 1 << 18, "uu_ttggg_cf": 1 << 18}.get(args.profile_proc, N_EVENTS)
         settle_clocks(torch, proc, n=n, sqrt_s=pir.sqrt_s)
-        wall, kern, r = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
+        wall, kern, r, _ = time_path(torch, proc, args.steps, args.warmup, n=n, sqrt_s=pir.sqrt_s)
         out = {"proc": args.profile_proc, "leg": args.profile_leg, "ms_per_step": wall * 1e3,
                "kernel_ms": kern * 1e3, "events_per_launch": n, "events_per_s": n / wall,
                "n_accepted": r["n_accepted"], "source_digest": codegen.source_digest(pir)}
@@ -477,16 +497,16 @@ def main():
     mixed = H.Process(proc_ir, precision="mixed")
 
     settle_clocks(torch, fp64)
-    wall64, kern64, r64 = time_path(torch, fp64, args.steps, args.warmup)
-    wallmx, kernmx, rmx = time_path(torch, mixed, args.steps, args.warmup)
+    wall64, kern64, r64, sync64 = time_path(torch, fp64, args.steps, args.warmup, synchronous_too=True)
+    wallmx, kernmx, rmx, syncmx = time_path(torch, mixed, args.steps, args.warmup, synchronous_too=True)
 
     # with the exactly-vanishing helicity combinations dropped (4 of 256 survive)
     fp64f = H.Process(proc_ir, precision="fp64")
     nk = fp64f.filter_helicities(n_probe=64, seed=99, sqrt_s=SQRT_S, rel_threshold=1e-20)
     mixedf = H.Process(proc_ir, precision="mixed")
     mixedf.filter_helicities(n_probe=64, seed=99, sqrt_s=SQRT_S, rel_threshold=1e-20)
-    wall64f, kern64f, _ = time_path(torch, fp64f, args.steps, args.warmup)
-    wallmxf, kernmxf, _ = time_path(torch, mixedf, args.steps, args.warmup)
+    wall64f, kern64f, _, _ = time_path(torch, fp64f, args.steps, args.warmup)
+    wallmxf, kernmxf, _, _ = time_path(torch, mixedf, args.steps, args.warmup)
 
     model_flop_event = flops.per_event(proc_ir)
     if counters_valid(proc_ir):
@@ -507,6 +527,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": wall64 * 1e3,
+        "synchronous": {"events_per_s": N_EVENTS / sync64, "ms_per_step": sync64 * 1e3,
+                        "how": "heget_integrate, the host waiting for every step's sigma"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -522,6 +544,7 @@ def main():
                      "flop_per_event": flop_event, "flop_source": flop_source,
                      "model_flop_per_event": model_flop_event},
         "mixed": {"value": N_EVENTS / wallmx, "ms_per_step": wallmx * 1e3, "kernel_ms": kernmx * 1e3,
+                  "synchronous_ms_per_step": syncmx * 1e3,
                   "tflops": mixed_flop_event * N_EVENTS / kernmx / 1e12 if mixed_flop_event else None, "peak": FP32_PEAK_TFLOPS,
                   "flop_per_event": mixed_flop_event, "flop_source": mixed_flop_source,
                   "sigma_pb": rmx["sigma_pb"]},

@@ -304,6 +304,30 @@ heget_status heget_uniforms(uint64_t seed, uint64_t counter_offset, int64_t n, i
 heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
                              void* stream);
 
+/* heget_integrate as one stage of a pipeline: the Monte Carlo event loop of
+ * Sec. 6 with the host queueing batch after batch while the device works.
+ * Enqueues on `stream` the same kernels, counters and fixed-order reduction as
+ * heget_integrate and returns without waiting.  Once the stream has passed the
+ * call, sums_out[0..2] hold sum w, sum w^2 and the accepted count (as a
+ * double), bit for bit the sums heget_integrate reduces;
+ * heget_result_from_sums turns them into the heget_result heget_integrate
+ * fills.  sums_out: 3 doubles of device memory, or of pinned host memory,
+ * owned by the caller and kept until the stream has passed the call.  Calls on
+ * one handle share its per-block partial sums: make them on one stream, which
+ * orders them (calls on two streams at once race).  A call with n above every
+ * earlier call's grows that buffer, after waiting for `stream`.
+ * Errors: HEGET_E_INVALID (null handle or sums_out, n < 2, sqrt_s <= 0),
+ * HEGET_E_OOM, HEGET_E_HIP (a launch failed; the call enqueues nothing more). */
+heget_status heget_integrate_async(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, double* sums_out,
+                                   void* stream);
+
+/* The cross section of n events from the three sums of heget_integrate_async
+ * (host memory): sigma = sum w / n, its Monte Carlo error
+ * sqrt((sum w^2 / n - sigma^2) / (n - 1)), in GeV^-2 and in pb
+ * (hbar c)^2 = 0.3893793721e9 pb GeV^2).  Errors: HEGET_E_INVALID (null
+ * pointer, n < 2). */
+heget_status heget_result_from_sums(const double* sums, int64_t n, heget_result* out);
+
 /* heget_integrate for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * kernels, counters, reduction order and result as heget_integrate (bit for

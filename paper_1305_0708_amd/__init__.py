@@ -81,6 +81,16 @@ def uniforms(n, n_u, seed=0, counter_offset=0, stream=None):
     return out
 
 
+def result_from_sums(sums, n, lib=None):
+    """The heget_integrate result of n events from the three sums (sum w,
+    sum w^2, accepted) that heget_integrate_async writes (heget_result_from_sums)."""
+    L = lib or _lib.load()
+    h = (ctypes.c_double * 3)(*[float(x) for x in list(sums)[:3]])
+    r = _lib.heget_result()
+    check(L.heget_result_from_sums(h, n, ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in r._fields_}
+
+
 class Process:
     """A created process handle (heget_process_create)."""
 
@@ -163,6 +173,24 @@ class Process:
         r = _lib.heget_result()
         check(self._lib.heget_integrate(self._h, n, float(sqrt_s), seed, ctypes.byref(r), self._stream(stream)))
         return {k: getattr(r, k) for k, _ in r._fields_}
+
+    def integrate_async(self, n, sums_out, seed=0, sqrt_s=None, stream=None):
+        """heget_integrate_async: enqueue one integrate step and return at
+        once; sums_out (a float64 CUDA tensor, 3 contiguous values) receives
+        (sum w, sum w^2, accepted) when the stream gets there."""
+        import torch
+        if sums_out.dtype != torch.float64 or not sums_out.is_cuda or not sums_out.is_contiguous() \
+                or sums_out.numel() < 3:
+            raise ValueError("sums_out must be a contiguous float64 CUDA tensor of at least 3 values")
+        sqrt_s = self.ir.sqrt_s if sqrt_s is None else sqrt_s
+        check(self._lib.heget_integrate_async(self._h, n, float(sqrt_s), seed, ctypes.c_void_p(sums_out.data_ptr()),
+                                              self._stream(stream)))
+        return sums_out
+
+    def result_from_sums(self, sums, n):
+        """heget_result_from_sums: the heget_integrate result of n events from
+        the three sums of integrate_async (a sequence of 3 floats)"""
+        return result_from_sums(sums, n, self._lib)
 
     def integrate_noalloc(self, n, seed=0, sqrt_s=None, stream=None):
         """heget_integrate_noalloc: heget_integrate with no allocation in the

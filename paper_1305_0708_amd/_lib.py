@@ -13,6 +13,7 @@ EXPORTED = ["heget_process_create", "heget_process_destroy", "heget_eval", "hege
             "heget_process_n_helicities", "heget_filter_helicities", "heget_last_error", "heget_generate",
             "heget_uniforms",
             "heget_integrate_adaptive", "heget_process_grid_dims", "heget_integrate_noalloc",
+            "heget_integrate_async", "heget_result_from_sums",
             "heget_server_create", "heget_server_submit", "heget_server_poll", "heget_server_stats_get",
             "heget_server_destroy"]
 
@@ -119,6 +120,11 @@ def load(path=None):
     L.heget_integrate_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                           ctypes.POINTER(heget_result), vp]
     L.heget_integrate_noalloc.restype = ctypes.c_int
+    L.heget_integrate_async.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, vp, vp]
+    L.heget_integrate_async.restype = ctypes.c_int
+    L.heget_result_from_sums.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                         ctypes.POINTER(heget_result)]
+    L.heget_result_from_sums.restype = ctypes.c_int
     L.heget_integrate_adaptive.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_uint64, ctypes.POINTER(heget_result),
                                            ctypes.POINTER(heget_result), ctypes.POINTER(ctypes.c_double),

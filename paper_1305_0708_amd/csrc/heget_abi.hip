@@ -875,13 +875,13 @@ hipError_t wait_stream(hipStream_t st) {
 }
 }  // namespace
 
-heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
-                             void* stream) {
-  g_err.clear();
-  if (!p || !out) return fail(HEGET_E_INVALID, "null argument");
-  if (n < 2) return fail(HEGET_E_INVALID, "need n >= 2 events");
-  if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+namespace {
+// One integrate step enqueued on st: the amplitude kernel writes per-block
+// partial sums into the handle's buffer (grown, after a wait for st, when a
+// larger n arrives) and the fixed-order reduction writes its three sums to
+// `sums` (device memory or pinned host memory).  Does not wait for st.
+heget_status enqueue_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, double* sums,
+                               hipStream_t st) {
   const int64_t nblocks = (n + 255) / 256;
   if (p->part_cap < nblocks * 3 + 3) {
     HIP_TRY(hipStreamSynchronize(st));
@@ -892,30 +892,62 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
       return fail(HEGET_E_OOM, "partials allocation failed");
     p->part_cap = nblocks * 3 + 3;
   }
-  if (!p->h_res && hipHostMalloc(reinterpret_cast<void**>(&p->h_res), 3 * sizeof(double), hipHostMallocDefault) !=
-                       hipSuccess) {
-    p->h_res = nullptr;
-    return fail(HEGET_E_OOM, "pinned result allocation failed");
-  }
-  double* d_part = p->d_part;
   KernelArgs a = base_args(p);
   a.n = n;
   a.mom_stride = n;
   a.seed = seed;
   a.sqrt_s = sqrt_s;
   a.weight_factor = heget::detail::weight_factor(p, sqrt_s);
-  a.partials = d_part;
+  a.partials = p->d_part;
   heget_status rc = launch(p, a, st);
-  if (rc == HEGET_OK) {
-    // the reduction writes its three sums straight into the pinned result
-    // buffer (host memory the device can write): no separate copy back
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, d_part, nblocks, p->h_res);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = wait_stream(st);
-    if (e != hipSuccess) rc = fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
-  }
   if (rc != HEGET_OK) return rc;
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, p->d_part, nblocks, sums);
+  HIP_TRY(hipGetLastError());
+  return HEGET_OK;
+}
+
+heget_status check_integrate_args(heget_process_t p, int64_t n, double sqrt_s, const void* out) {
+  if (!p || !out) return fail(HEGET_E_INVALID, "null argument");
+  if (n < 2) return fail(HEGET_E_INVALID, "need n >= 2 events");
+  if (!(sqrt_s > 0)) return fail(HEGET_E_INVALID, "sqrt_s must be > 0");
+  return HEGET_OK;
+}
+}  // namespace
+
+heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, heget_result* out,
+                             void* stream) {
+  g_err.clear();
+  heget_status rc = check_integrate_args(p, n, sqrt_s, out);
+  if (rc != HEGET_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!p->h_res && hipHostMalloc(reinterpret_cast<void**>(&p->h_res), 3 * sizeof(double), hipHostMallocDefault) !=
+                       hipSuccess) {
+    p->h_res = nullptr;
+    return fail(HEGET_E_OOM, "pinned result allocation failed");
+  }
+  // the reduction writes its three sums straight into the pinned result
+  // buffer (host memory the device can write): no separate copy back
+  rc = enqueue_integrate(p, n, sqrt_s, seed, p->h_res, st);
+  if (rc != HEGET_OK) return rc;
+  const hipError_t e = wait_stream(st);
+  if (e != hipSuccess) return fail(HEGET_E_HIP, std::string("integrate: ") + hipGetErrorString(e));
   heget::detail::fill_result(p->h_res, n, out);
+  return HEGET_OK;
+}
+
+heget_status heget_integrate_async(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, double* sums_out,
+                                   void* stream) {
+  g_err.clear();
+  const heget_status rc = check_integrate_args(p, n, sqrt_s, sums_out);
+  if (rc != HEGET_OK) return rc;
+  return enqueue_integrate(p, n, sqrt_s, seed, sums_out, static_cast<hipStream_t>(stream));
+}
+
+heget_status heget_result_from_sums(const double* sums, int64_t n, heget_result* out) {
+  g_err.clear();
+  if (!sums || !out) return fail(HEGET_E_INVALID, "null argument");
+  if (n < 2) return fail(HEGET_E_INVALID, "need n >= 2 events");
+  heget::detail::fill_result(sums, n, out);
   return HEGET_OK;
 }
 

@@ -158,3 +158,27 @@ def test_compressed_form_keeps_mfma_out_of_the_fp32_kernel(name):
     assert "colour_form_resident" in src[b:] or "colour_form_mfma" in src[b:]
     entry = next(l for l in src.splitlines() if l.startswith("static const GenEntry entry"))
     assert entry.endswith(", 0, nullptr, nullptr, nullptr, nullptr};")   # colour_mfma_mixed = 0, fused
+
+
+def test_integrate_async_rejects_bad_arguments(lib):
+    """heget_integrate_async and heget_result_from_sums check their arguments
+    before any device call"""
+    import ctypes
+    from paper_1305_0708_amd import _lib
+    sums = (ctypes.c_double * 3)()
+    r = _lib.heget_result()
+    assert lib.heget_integrate_async(None, 1024, 1000.0, 1, ctypes.cast(sums, ctypes.c_void_p), None) \
+        == _lib.HEGET_E_INVALID
+    assert lib.heget_result_from_sums(None, 1024, ctypes.byref(r)) == _lib.HEGET_E_INVALID
+    assert lib.heget_result_from_sums(sums, 1, ctypes.byref(r)) == _lib.HEGET_E_INVALID
+
+
+def test_result_from_sums_is_the_monte_carlo_estimate():
+    """sigma = sum w / n and its error sqrt((sum w^2 / n - sigma^2) / (n - 1)),
+    worked by hand for w = (1, 2, 3, 4): sigma 2.5, variance 7.5 - 6.25 = 1.25"""
+    import math
+    import paper_1305_0708_amd as H
+    r = H.result_from_sums([10.0, 30.0, 4.0], 4)
+    assert r["sigma_gev2"] == 2.5 and r["n_accepted"] == 4 and r["n_generated"] == 4
+    assert abs(r["err_gev2"] - math.sqrt(1.25 / 3)) < 1e-15
+    assert abs(r["sigma_pb"] / r["sigma_gev2"] - 0.3893793721e9) < 1e-3
