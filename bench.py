@@ -42,9 +42,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "72879baf64830d2d85dcd279033ee36a138f3c58829898569158c9bf06eefa4f",
-                 "fetch_kib": 3225.625, "fetch_scale": 2.0, "write_kib": 98119.375, "write_scale": 1.0,
-                 "flop_per_event": 4437, "flop_per_event_mixed": 2331}
+COUNTERS_FP64 = {"source_digest": "141b6bc739c880cf6df40a41e041508f907ffe5a324db5de8d928ed320b11c7b",
+                 "fetch_kib": 2290.4375, "fetch_scale": 2.0, "write_kib": 92923.125, "write_scale": 1.0,
+                 "flop_per_event": 4275, "flop_per_event_mixed": 2331}
 
 
 # Counter measurements of further kernels, (process, precision) -> figures per
@@ -56,38 +56,38 @@ COUNTERS_FP64 = {"source_digest": "72879baf64830d2d85dcd279033ee36a138f3c5882989
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "c0b67b046512c155af4933daf096de2b063e437899a56457d05e4925ebafeac7",
-        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2744, "events": 1 << 21, "kernel_s": 0.3625e-3,
+        "source_digest": "101336e39a340c0c24ff97a68f8a07bf87aeb5b80e4849f7f748673d34d6b3d2",
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2606, "events": 1 << 21, "kernel_s": 0.2944e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "c0b67b046512c155af4933daf096de2b063e437899a56457d05e4925ebafeac7",
-        "valu_flop_per_event": 5748, "events": 1 << 21, "kernel_s": 0.4755e-3,
+        "source_digest": "101336e39a340c0c24ff97a68f8a07bf87aeb5b80e4849f7f748673d34d6b3d2",
+        "valu_flop_per_event": 5610, "events": 1 << 21, "kernel_s": 0.4083e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
-        "source_digest": "014b1dbe93b8a767249ecfa14906abcf8d24a314a1eb90c384a8c2f7dab6ed59",
-        "valu_flop_per_event": 26981422, "events": 1 << 18, "kernel_s": 275.4e-3,
+        "source_digest": "72c531051cb638d86c200c2ff24fe2f119af53b53d01cd511c9f09e830a99fbd",
+        "valu_flop_per_event": 26797266, "events": 1 << 18, "kernel_s": 272.9e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("uu_ttggg", "mixed"): {
-        "source_digest": "014b1dbe93b8a767249ecfa14906abcf8d24a314a1eb90c384a8c2f7dab6ed59",
-        "valu_flop_per_event": 21813632, "fp64_flop_per_event": 1333934, "events": 1 << 18, "kernel_s": 153.3e-3,
+        "source_digest": "72c531051cb638d86c200c2ff24fe2f119af53b53d01cd511c9f09e830a99fbd",
+        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1334354, "events": 1 << 18, "kernel_s": 152.1e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "c921244ed9794a7f9df1a51c781107d0eab2544702f78a53877c368e62e22402",
-        "valu_flop_per_event": 3648277, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 171.1e-3,
+        "source_digest": "c462279168a761663ae22e4417708415d6f6878410bafd0926f0d24a4064316d",
+        "valu_flop_per_event": 3633029, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 172.1e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "e95d70cd957b7f66dfdedc31a3f4f9fc08eb7054a95a9b15103445d057146947",
-        "valu_flop_per_event": 3591957, "events": 1 << 20, "kernel_s": 91.7e-3,
+        "source_digest": "176d44ae716689b1a14b9fd83f7dd2e1d1f0cee64b2c892191851c35c0e5b42e",
+        "valu_flop_per_event": 3576709, "events": 1 << 20, "kernel_s": 93.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "e95d70cd957b7f66dfdedc31a3f4f9fc08eb7054a95a9b15103445d057146947",
-        "valu_flop_per_event": 2825855, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 64.2e-3,
+        "source_digest": "176d44ae716689b1a14b9fd83f7dd2e1d1f0cee64b2c892191851c35c0e5b42e",
+        "valu_flop_per_event": 2810735, "fp64_flop_per_event": 145238, "events": 1 << 20, "kernel_s": 63.3e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "d3c99543e74d0ddad5bce00f071fc25402452a6d7989d1156e8ed5dde3019803",
-        "valu_flop_per_event": 3805183, "fp64_flop_per_event": 145366, "events": 1 << 20, "kernel_s": 88.9e-3,
+        "source_digest": "95d7f379a8fdc2f1775122b4cbcf492fe0ed70a2d266a031c656fecd4ca5c715",
+        "valu_flop_per_event": 3790063, "fp64_flop_per_event": 145238, "events": 1 << 20, "kernel_s": 87.4e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 
@@ -258,6 +258,7 @@ def config_leg(torch, H, pir, workload, steps, warmup, n=N_EVENTS, precisions=("
         except H.HegetError as e:
             out[prec] = {"refused": str(e)}
             continue
+        settle_clocks(torch, proc, n=n, sqrt_s=pir.sqrt_s)
         wall, kern, r, _ = time_path(torch, proc, steps, warmup, n=n, sqrt_s=pir.sqrt_s, seed=seed)
         out[prec] = {"events_per_s": n / wall, "ms_per_step": wall * 1e3, "kernel_ms": kern * 1e3,
                      "sigma_pb": r["sigma_pb"], "sigma_err_pb": r["err_pb"], "n_accepted": r["n_accepted"]}

@@ -324,15 +324,17 @@ __device__ __forceinline__ wf<T> vxxxxx(vec<T> k, T m, int lam, int nsv) {
   const T pp = sqrt(pt2 + k.z * k.z);
   T ct, st, cp, sp;
   if (pp > T(0)) {
-    ct = k.z / pp;
-    st = pt / pp;
+    const T ipp = T(1) / pp;
+    ct = k.z * ipp;
+    st = pt * ipp;
   } else {
     ct = T(1);
     st = T(0);
   }
   if (pt > T(0)) {
-    cp = k.x / pt;
-    sp = k.y / pt;
+    const T ipt = T(1) / pt;
+    cp = k.x * ipt;
+    sp = k.y * ipt;
   } else {
     cp = T(1);
     sp = T(0);
@@ -371,12 +373,14 @@ __device__ __forceinline__ VPol<T> vpol_pre(mom p) {
   const double pp = sqrt(pt2 + p.z * p.z);
   double ct = 1.0, st = 0.0, cp = 1.0, sp = 0.0;
   if (pp > 0.0) {
-    ct = p.z / pp;
-    st = pt / pp;
+    const double ipp = 1.0 / pp;
+    ct = p.z * ipp;
+    st = pt * ipp;
   }
   if (pt > 0.0) {
-    cp = p.x / pt;
-    sp = p.y / pt;
+    const double ipt = 1.0 / pt;
+    cp = p.x * ipt;
+    sp = p.y * ipt;
   }
   const double h = 0.70710678118654752440;
   return {T(h * ct * cp), T(h * ct * sp), T(h * st), T(h * sp), T(h * cp)};

@@ -19,13 +19,12 @@ namespace heget {
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t a0 = c[0], a2 = c[2];
-    const uint32_t hi0 = __umulhi(0xD2511F53u, a0), lo0 = 0xD2511F53u * a0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, a2), lo1 = 0xCD9E8D57u * a2;
-    c[0] = hi1 ^ c[1] ^ k0;
-    c[1] = lo1;
-    c[2] = hi0 ^ c[3] ^ k1;
-    c[3] = lo0;
+    // each 32 x 32 -> 64-bit product gives both words in one instruction
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c[0], p1 = uint64_t(0xCD9E8D57u) * c[2];
+    c[0] = uint32_t(p1 >> 32) ^ c[1] ^ k0;
+    c[1] = uint32_t(p1);
+    c[2] = uint32_t(p0 >> 32) ^ c[3] ^ k1;
+    c[3] = uint32_t(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -54,7 +53,8 @@ __device__ __forceinline__ void rambo(uint64_t seed, uint64_t event, double sqrt
     const double ct = 2.0 * u[0] - 1.0;
     const double st = sqrt(1.0 - ct * ct);
     double sf, cf;
-    sincos(6.283185307179586476925 * u[1], &sf, &cf);
+    // the azimuth 2 pi u: sincospi reduces its argument exactly
+    sincospi(2.0 * u[1], &sf, &cf);
     const double e = -log(u[2] * u[3]);
     p[k] = {e, e * st * cf, e * st * sf, e * ct};
     Q0 += p[k].e;
@@ -180,7 +180,7 @@ __device__ __forceinline__ double ps_decay(double uc, double uphi, const mom& P,
   const double ct = 2.0 * uc - 1.0;
   const double st = sqrt(1.0 - ct * ct);
   double sf, cf;
-  sincos(2.0 * pi * uphi, &sf, &cf);
+  sincospi(2.0 * uphi, &sf, &cf);
   const double nx = st * cf, ny = st * sf;
   const double e0 = (M * M + m0 * m0 - m1 * m1) / (2.0 * M), e1 = (M * M + m1 * m1 - m0 * m0) / (2.0 * M);
   const mom a = {e0, pst * nx, pst * ny, pst * ct}, b = {e1, -pst * nx, -pst * ny, -pst * ct};
@@ -212,7 +212,7 @@ __device__ __forceinline__ double ps_hadronic(const double* u, double sqrt_S, do
   const double mt0sq = exp(L);
   const double pt = sqrt(fmax(mt0sq - m0 * m0, 0.0));
   double sf, cf;
-  sincos(2.0 * pi * u[2], &sf, &cf);
+  sincospi(2.0 * u[2], &sf, &cf);
   const double px = pt * cf, py = pt * sf;
   const double mt0 = sqrt(mt0sq), mt1 = sqrt(m1 * m1 + pt * pt);
   const double e0 = mt0 * cosh(y0), z0 = mt0 * sinh(y0);

@@ -73,6 +73,12 @@ inline int shfl_xor(int v, int m) { return shfl_xor_i32(v, m); }
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32((a), (b), (c))
 
 inline unsigned __umulhi(unsigned a, unsigned b) { return unsigned((uint64_t(a) * b) >> 32); }
+// sin(pi x) and cos(pi x): x reduced exactly to [-1, 1] by whole periods first
+inline void sincospi(double x, double* s, double* c) {
+  const double r = x - 2.0 * std::nearbyint(0.5 * x);
+  *s = std::sin(3.14159265358979323846 * r);
+  *c = std::cos(3.14159265358979323846 * r);
+}
 using std::max;
 using std::min;
 

@@ -3,6 +3,10 @@ handle through the emulated library's C ABI and evaluate n events, writing
 |M|^2 and the momenta used to an .npz file.
 
     python run_emu.py LIB NAME PRECISION N SEED OUT [MOMENTA.npy]
+    python run_emu.py LIB NAME PRECISION N SEED OUT --integrate
+
+The second form writes the three reduced sums of heget_integrate (twice in a
+row), heget_integrate_async and heget_integrate_noalloc instead.
 
 Run with the sanitizer runtime preloaded (LD_PRELOAD) and ASAN_OPTIONS
 detect_leaks=0; any invalid access aborts the child with a report.
@@ -38,6 +42,8 @@ def main(argv):
     if st != 0:
         print("create:", st, L.heget_last_error().decode(), flush=True)
         return 3
+    if len(argv) > 6 and argv[6] == "--integrate":
+        return integrate(L, h, pir, n, seed, out)
     me2 = np.zeros(n)
     if len(argv) > 6:
         mom = np.ascontiguousarray(np.load(argv[6]), dtype=np.float64)   # [legs][4][n]
@@ -50,6 +56,32 @@ def main(argv):
         print("eval:", st, L.heget_last_error().decode(), flush=True)
         return 4
     np.savez(out, me2=me2, mom=mom_in if mom_in is not None else mom_out)
+    L.heget_process_destroy(h)
+    return 0
+
+
+def integrate(L, h, pir, n, seed, out):
+    from paper_1305_0708_amd import _lib
+    vp = ctypes.c_void_p
+    res = ctypes.POINTER(_lib.heget_result)
+    L.heget_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, res, vp]
+    L.heget_integrate_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, res, vp]
+    L.heget_integrate_async.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, vp, vp]
+    rows = []
+    for fn in (L.heget_integrate, L.heget_integrate, L.heget_integrate_noalloc):
+        r = _lib.heget_result()
+        st = fn(h, n, float(pir.sqrt_s), seed, ctypes.byref(r), None)
+        if st != 0:
+            print("integrate:", st, L.heget_last_error().decode(), flush=True)
+            return 5
+        rows.append([r.sum_w, r.sum_w2, float(r.n_accepted)])
+    sums = np.zeros(3)
+    st = L.heget_integrate_async(h, n, float(pir.sqrt_s), seed, ctypes.c_void_p(sums.ctypes.data), None)
+    if st != 0:
+        print("integrate_async:", st, L.heget_last_error().decode(), flush=True)
+        return 6
+    rows.append(list(sums))
+    np.savez(out, sums=np.array(rows))
     L.heget_process_destroy(h)
     return 0
 

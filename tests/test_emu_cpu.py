@@ -111,3 +111,36 @@ def test_quark_line_kernels(emu_ql, oracle, name, prec):
     err = np.abs(me2[nz] - ref[nz]) / ref[nz]
     print(f"emulated {name} {prec}: max rel err {err.max():.2e}, median {np.median(err):.2e}")
     assert err.max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+# ------------------------------------------------- the integrate entry points
+FR_OUT = os.path.join(EMU, "_build", "integrate")
+
+
+@pytest.fixture(scope="module")
+def emu_int():
+    sys.path.insert(0, EMU)
+    import build_emu
+    if not os.path.exists(build_emu.CXX) or not build_emu.asan_runtime():
+        pytest.skip("host clang++ with the AddressSanitizer runtime not available")
+    lib = build_emu.build(processes=("ee_mumu",), out=FR_OUT)
+    return lib, build_emu.asan_runtime()
+
+
+@pytest.mark.parametrize("n,cus", [(45, 1), (300, 2), (2000, 3)])
+def test_integrate_entry_points_agree(emu_int, n, cus):
+    """heget_integrate (twice in a row), heget_integrate_noalloc (the
+    library's scratch) and heget_integrate_async (sums into caller memory) on
+    ragged launches: the same three sums bit for bit, every event accepted,
+    no invalid access"""
+    lib, asan = emu_int
+    out = os.path.join(FR_OUT, f"sums_{n}_{cus}.npz")
+    env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", EMU_LANE_ORDER="0",
+               EMU_CUS=str(cus))
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_emu.py"), lib, "ee_mumu", "fp64", str(n), "0x2F",
+                        out, "--integrate"], env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, f"emulated integrate n={n}: rc {r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
+    s = np.load(out)["sums"]
+    assert s[0, 2] == n and s[0, 0] > 0
+    for k in (1, 2, 3):
+        assert np.array_equal(s[k], s[0]), (k, s)
