@@ -42,9 +42,9 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "141b6bc739c880cf6df40a41e041508f907ffe5a324db5de8d928ed320b11c7b",
-                 "fetch_kib": 2290.4375, "fetch_scale": 2.0, "write_kib": 92923.125, "write_scale": 1.0,
-                 "flop_per_event": 4275, "flop_per_event_mixed": 2331}
+COUNTERS_FP64 = {"source_digest": "23ad379b6caf19350e01e6215333fed35ce5454affc82953febde9ed88137832",
+                 "fetch_kib": 829.0, "fetch_scale": 2.0, "write_kib": 70460.875, "write_scale": 1.0,
+                 "flop_per_event": 3990, "flop_per_event_mixed": 2331}
 
 
 # Counter measurements of further kernels, (process, precision) -> figures per
@@ -56,38 +56,38 @@ COUNTERS_FP64 = {"source_digest": "141b6bc739c880cf6df40a41e041508f907ffe5a324db
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "101336e39a340c0c24ff97a68f8a07bf87aeb5b80e4849f7f748673d34d6b3d2",
-        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2606, "events": 1 << 21, "kernel_s": 0.2944e-3,
+        "source_digest": "8a9a4985709e0ca58977f599c243700ae6a00aa24a7a99b02bd7603661bbff7d",
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.2549e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "101336e39a340c0c24ff97a68f8a07bf87aeb5b80e4849f7f748673d34d6b3d2",
-        "valu_flop_per_event": 5610, "events": 1 << 21, "kernel_s": 0.4083e-3,
+        "source_digest": "8a9a4985709e0ca58977f599c243700ae6a00aa24a7a99b02bd7603661bbff7d",
+        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.354e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
-        "source_digest": "72c531051cb638d86c200c2ff24fe2f119af53b53d01cd511c9f09e830a99fbd",
-        "valu_flop_per_event": 26797266, "events": 1 << 18, "kernel_s": 272.9e-3,
+        "source_digest": "178a19af4e023fdbc0c8500e1b1b67ab278655cc48d577f2c3b763f09c3e32e5",
+        "valu_flop_per_event": 26558279, "events": 1 << 18, "kernel_s": 270.3e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("uu_ttggg", "mixed"): {
-        "source_digest": "72c531051cb638d86c200c2ff24fe2f119af53b53d01cd511c9f09e830a99fbd",
-        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1334354, "events": 1 << 18, "kernel_s": 152.1e-3,
+        "source_digest": "178a19af4e023fdbc0c8500e1b1b67ab278655cc48d577f2c3b763f09c3e32e5",
+        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1179463, "events": 1 << 18, "kernel_s": 151.8e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "c462279168a761663ae22e4417708415d6f6878410bafd0926f0d24a4064316d",
-        "valu_flop_per_event": 3633029, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 172.1e-3,
+        "source_digest": "b0cebae37be54c558bf9d99eee18afec789365f69755a4e49cb1cd420962a848",
+        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 174.7e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "176d44ae716689b1a14b9fd83f7dd2e1d1f0cee64b2c892191851c35c0e5b42e",
-        "valu_flop_per_event": 3576709, "events": 1 << 20, "kernel_s": 93.6e-3,
+        "source_digest": "7e90b7b969cd46d506c829af0e03d64b4b6abb994aa9f8e6811a1e87dca555fc",
+        "valu_flop_per_event": 3556867, "events": 1 << 20, "kernel_s": 93.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "176d44ae716689b1a14b9fd83f7dd2e1d1f0cee64b2c892191851c35c0e5b42e",
-        "valu_flop_per_event": 2810735, "fp64_flop_per_event": 145238, "events": 1 << 20, "kernel_s": 63.3e-3,
+        "source_digest": "7e90b7b969cd46d506c829af0e03d64b4b6abb994aa9f8e6811a1e87dca555fc",
+        "valu_flop_per_event": 2810735, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 62.6e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "95d7f379a8fdc2f1775122b4cbcf492fe0ed70a2d266a031c656fecd4ca5c715",
-        "valu_flop_per_event": 3790063, "fp64_flop_per_event": 145238, "events": 1 << 20, "kernel_s": 87.4e-3,
+        "source_digest": "646999fb482f30ab6d66dfd6db71060be9a087587e4f3c96c0dd6426a859f3a8",
+        "valu_flop_per_event": 3790063, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 87.7e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }
 

@@ -65,6 +65,41 @@ struct mom {
 };
 __device__ __forceinline__ mom operator+(mom a, mom b) { return {a.e + b.e, a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ mom operator-(mom a) { return {-a.e, -a.x, -a.y, -a.z}; }
+
+// FP64 square root and reciprocal for the kinematics, from the hardware
+// estimates (v_rsq_f64, v_rcp_f64, about 23 bits) refined in FMA: the square
+// root by the coupled Newton iteration for sqrt(x) and 1/(2 sqrt(x)) followed by
+// two residual corrections (Goldschmidt's method as Markstein arranges it, IA-64
+// and Elementary Functions, 2000), the reciprocal by two Newton steps.  Within
+// one unit in the last place; they skip the IEEE library's scaling of tiny and
+// huge arguments, which kinematics never produce.  sqrt_pos returns 0 for x <= 0.
+// The FP32 overloads are the library's.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
+__device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float d) { return 1.0f / d; }
+// a / b: the reciprocal times a, and one correction of the quotient
+__device__ __forceinline__ double quot(double a, double b) {
+  const double r = recip(b);
+  const double q = a * r;
+  return fma(r, fma(-b, q, a), q);
+}
+__device__ __forceinline__ float quot(float a, float b) { return a / b; }
 // The same momentum, opaque to the optimiser: kinematics computed from it
 // inside a loop stay in that loop (recomputed) instead of being hoisted out and
 // held in registers across it.
@@ -132,7 +167,7 @@ __device__ __forceinline__ cx<T> dot(const wf<T>& a, vec<T> q) {
 // 1 / (q^2 - pole) in FP64 for a complex pole (m^2 - i m Gamma, or the complex mass)
 __device__ __forceinline__ cx<double> inv_denominator(mom q, cx<double> pole) {
   const double a = msq(q) - pole.r, b = -pole.i;
-  const double n = 1.0 / (a * a + b * b);
+  const double n = recip(a * a + b * b);
   return {a * n, -b * n};
 }
 
@@ -142,14 +177,14 @@ __device__ __forceinline__ cx<double> inv_denominator(mom q, cx<double> pole) {
 // |p| + p_z without cancellation: for p_z < 0 it equals p_T^2 / (|p| - p_z)
 template <class T>
 __device__ __forceinline__ T pp_plus_pz(vec<T> p, T pp) {
-  return p.z >= T(0) ? pp + p.z : (p.x * p.x + p.y * p.y) / (pp - p.z);
+  return p.z >= T(0) ? pp + p.z : quot(p.x * p.x + p.y * p.y, pp - p.z);
 }
 
 template <class T>
 __device__ __forceinline__ void chi2(vec<T> p, T pp, int lam, cx<T>& a, cx<T>& b) {
   const T s = pp_plus_pz(p, pp);
   if (s > T(0)) {
-    const T n = T(1) / sqrt(T(2) * pp * s);
+    const T n = recip(sqrt_pos(T(2) * pp * s));
     if (lam > 0) {
       a = mk<T>(s * n, T(0));
       b = mk<T>(p.x * n, p.y * n);
@@ -175,10 +210,10 @@ __device__ __forceinline__ void chi2(vec<T> p, T pp, int lam, cx<T>& a, cx<T>& b
 // still defines an exactly massless state.
 template <class T>
 __device__ __forceinline__ void weyl0(vec<T> p, int lam, cx<T>& a, cx<T>& b) {
-  const T pp = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  const T pp = sqrt_pos(p.x * p.x + p.y * p.y + p.z * p.z);
   const T s = pp_plus_pz(p, pp);
   if (s > T(0)) {
-    const T r = sqrt(s), ir = T(1) / r;
+    const T r = sqrt_pos(s), ir = recip(r);
     if (lam > 0) {
       a = mk<T>(r, T(0));
       b = mk<T>(p.x * ir, p.y * ir);
@@ -187,7 +222,7 @@ __device__ __forceinline__ void weyl0(vec<T> p, int lam, cx<T>& a, cx<T>& b) {
       b = mk<T>(r, T(0));
     }
   } else {
-    const T r = sqrt(T(2) * pp);
+    const T r = sqrt_pos(T(2) * pp);
     if (lam > 0) {
       a = mk<T>(T(0), T(0));
       b = mk<T>(r, T(0));
@@ -320,6 +355,8 @@ __device__ __forceinline__ wf<T> vxxxxx(vec<T> k, T m, int lam, int nsv) {
     return v;
   }
   const T pt2 = k.x * k.x + k.y * k.y;
+  // the library's sqrt and division here: the gluon templates form this vector
+  // inside their loops, and the FMA forms moved those kernels' spills into the loops
   const T pt = sqrt(pt2);
   const T pp = sqrt(pt2 + k.z * k.z);
   T ct, st, cp, sp;
@@ -369,16 +406,16 @@ struct VPol {
 template <class T>
 __device__ __forceinline__ VPol<T> vpol_pre(mom p) {
   const double pt2 = p.x * p.x + p.y * p.y;
-  const double pt = sqrt(pt2);
-  const double pp = sqrt(pt2 + p.z * p.z);
+  const double pt = sqrt_pos(pt2);
+  const double pp = sqrt_pos(pt2 + p.z * p.z);
   double ct = 1.0, st = 0.0, cp = 1.0, sp = 0.0;
   if (pp > 0.0) {
-    const double ipp = 1.0 / pp;
+    const double ipp = recip(pp);
     ct = p.z * ipp;
     st = pt * ipp;
   }
   if (pt > 0.0) {
-    const double ipt = 1.0 / pt;
+    const double ipt = recip(pt);
     cp = p.x * ipt;
     sp = p.y * ipt;
   }

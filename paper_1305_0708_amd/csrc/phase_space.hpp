@@ -1,7 +1,9 @@
 // Counter-based uniforms, RAMBO momenta and the gluon generation cut (device).
 //
 // Philox4x32-10 follows its published definition (Salmon et al., SC'11): ten
-// rounds of two 32x32->64-bit products with the Weyl key schedule.  Counter
+// rounds of two 32x32->64-bit products with the Weyl key schedule; each product
+// is one 64-bit multiply and each round's two three-way xors one gfx950
+// three-input bit instruction each.  Counter
 // layout per event i: (i_lo, i_hi, block j, 0), key (seed_lo, seed_hi); each
 // block gives two uniforms u = (floor(x / 2^12) + 1/2) 2^-52 from the 64-bit
 // words x = w0 2^32 + w1 and x = w2 2^32 + w3 (exact in FP64, strictly inside
@@ -21,9 +23,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   for (int r = 0; r < 10; ++r) {
     // each 32 x 32 -> 64-bit product gives both words in one instruction
     const uint64_t p0 = uint64_t(0xD2511F53u) * c[0], p1 = uint64_t(0xCD9E8D57u) * c[2];
-    c[0] = uint32_t(p1 >> 32) ^ c[1] ^ k0;
+    // a ^ b ^ c in one instruction (truth table 0x96)
+    c[0] = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c[1], k0, 0x96);
     c[1] = uint32_t(p1);
-    c[2] = uint32_t(p0 >> 32) ^ c[3] ^ k1;
+    c[2] = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c[3], k1, 0x96);
     c[3] = uint32_t(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -31,8 +34,46 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 }
 
 __device__ __forceinline__ double unit_open(uint32_t hi, uint32_t lo) {
+  // the top 52 bits of x as the mantissa of a double in [1, 2): 1 + floor(x / 2^12) 2^-52;
+  // adding 2^-53 - 1 is exact and gives (floor(x / 2^12) + 1/2) 2^-52
   const uint64_t x = (uint64_t(hi) << 32) | uint64_t(lo);
-  return (double(x >> 12) + 0.5) * 0x1.0p-52;
+  return __builtin_bit_cast(double, (x >> 12) | 0x3FF0000000000000ull) + (0x1.0p-53 - 1.0);
+}
+
+// Natural logarithm of a positive normal x (the RAMBO energies' -log(u u')):
+// x = 2^k m with m in [1/sqrt2, sqrt2), log x = k ln2 + 2 atanh f with
+// f = (m - 1) / (m + 1), |f| <= 0.1716, the range reduction of Cody and Waite
+// (Software Manual for the Elementary Functions, 1980); 2 atanh f = 2f (1 + s/3 +
+// s^2/5 + ... + s^9/19), s = f^2, whose first omitted term is below 2.5e-17 of
+// the sum.  The quotient f takes the hardware reciprocal estimate, two Newton
+// steps and one correction of the quotient.  A few units in the last place.
+__device__ __forceinline__ double log_positive(double x) {
+  int k = __builtin_amdgcn_frexp_exp(x);
+  double m = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    k -= 1;
+  }
+  const double num = m - 1.0, den = m + 1.0;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  double f = num * r;
+  f = fma(r, fma(-den, f, num), f);
+  const double s = f * f;
+  double q = 1.0 / 19.0;
+  q = fma(q, s, 1.0 / 17.0);
+  q = fma(q, s, 1.0 / 15.0);
+  q = fma(q, s, 1.0 / 13.0);
+  q = fma(q, s, 1.0 / 11.0);
+  q = fma(q, s, 1.0 / 9.0);
+  q = fma(q, s, 1.0 / 7.0);
+  q = fma(q, s, 1.0 / 5.0);
+  q = fma(q, s, 1.0 / 3.0);
+  const double t = 2.0 * f;
+  const double lm = fma(t * s, q, t);
+  const double kd = double(k);
+  return fma(kd, 0x1.62e42fefa39efp-1, fma(kd, 0x1.abc9e3b39803fp-56, lm));
 }
 
 // RAMBO for NOUT massless particles; writes the physical momenta p[0..NOUT-1]
@@ -51,22 +92,22 @@ __device__ __forceinline__ void rambo(uint64_t seed, uint64_t event, double sqrt
       u[2 * b + 1] = unit_open(c[2], c[3]);
     }
     const double ct = 2.0 * u[0] - 1.0;
-    const double st = sqrt(1.0 - ct * ct);
+    const double st = sqrt_pos(1.0 - ct * ct);
     double sf, cf;
     // the azimuth 2 pi u: sincospi reduces its argument exactly
     sincospi(2.0 * u[1], &sf, &cf);
-    const double e = -log(u[2] * u[3]);
+    const double e = -log_positive(u[2] * u[3]);
     p[k] = {e, e * st * cf, e * st * sf, e * ct};
     Q0 += p[k].e;
     Q1 += p[k].x;
     Q2 += p[k].y;
     Q3 += p[k].z;
   }
-  const double M = sqrt(Q0 * Q0 - Q1 * Q1 - Q2 * Q2 - Q3 * Q3);
-  const double iM = 1.0 / M;
+  const double M = sqrt_pos(Q0 * Q0 - Q1 * Q1 - Q2 * Q2 - Q3 * Q3);
+  const double iM = recip(M);
   const double b1 = -Q1 * iM, b2 = -Q2 * iM, b3 = -Q3 * iM;
   const double g = Q0 * iM;
-  const double a = 1.0 / (1.0 + g);
+  const double a = recip(1.0 + g);
   const double x = sqrt_s * iM;
 #pragma unroll
   for (int k = 0; k < NOUT; ++k) {
@@ -236,8 +277,8 @@ __device__ __forceinline__ bool pass_pt_dr(const mom* p, double pt_min, double d
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < NOUT; ++k) {
-    const double pt = sqrt(p[k].x * p[k].x + p[k].y * p[k].y);
-    const double pp = sqrt(pt * pt + p[k].z * p[k].z);
+    const double pt = sqrt_pos(p[k].x * p[k].x + p[k].y * p[k].y);
+    const double pp = sqrt_pos(pt * pt + p[k].z * p[k].z);
     ok = ok && (pt > pt_min);
     eta[k] = 0.5 * log((pp + p[k].z) / (pp - p[k].z));
     phi[k] = atan2(p[k].y, p[k].x);

@@ -73,6 +73,32 @@ inline int shfl_xor(int v, int m) { return shfl_xor_i32(v, m); }
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32((a), (b), (c))
 
 inline unsigned __umulhi(unsigned a, unsigned b) { return unsigned((uint64_t(a) * b) >> 32); }
+// gfx950 primitives of the device code: three-input bit function by truth
+// table (bit S0 * 4 + S1 * 2 + S2 of the table gives the result bit), FP64
+// exponent and mantissa, reciprocal and reciprocal square root (exact here; the
+// device's estimates are refined by Newton steps in the code that uses them)
+inline uint32_t emu_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, unsigned table) {
+  uint32_t r = 0;
+  for (int i = 0; i < 32; ++i) {
+    const unsigned idx = (((a >> i) & 1u) << 2) | (((b >> i) & 1u) << 1) | ((c >> i) & 1u);
+    r |= ((table >> idx) & 1u) << i;
+  }
+  return r;
+}
+#define __builtin_amdgcn_bitop3_b32(a, b, c, t) emu_bitop3_b32((a), (b), (c), (t))
+inline int emu_frexp_exp(double x) {
+  int e = 0;
+  std::frexp(x, &e);
+  return e;
+}
+inline double emu_frexp_mant(double x) {
+  int e = 0;
+  return std::frexp(x, &e);
+}
+#define __builtin_amdgcn_frexp_exp(x) emu_frexp_exp(x)
+#define __builtin_amdgcn_frexp_mant(x) emu_frexp_mant(x)
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))
 // sin(pi x) and cos(pi x): x reduced exactly to [-1, 1] by whole periods first
 inline void sincospi(double x, double* s, double* c) {
   const double r = x - 2.0 * std::nearbyint(0.5 * x);
