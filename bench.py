@@ -42,8 +42,8 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "23ad379b6caf19350e01e6215333fed35ce5454affc82953febde9ed88137832",
-                 "fetch_kib": 829.0, "fetch_scale": 2.0, "write_kib": 70460.875, "write_scale": 1.0,
+COUNTERS_FP64 = {"source_digest": "18711b7ee631a6977c777d46b80768076654313406e6ece811f09111c5ae5410",
+                 "fetch_kib": 927.9375, "fetch_scale": 2.0, "write_kib": 63269.375, "write_scale": 1.0,
                  "flop_per_event": 3990, "flop_per_event_mixed": 2331}
 
 
@@ -56,37 +56,37 @@ COUNTERS_FP64 = {"source_digest": "23ad379b6caf19350e01e6215333fed35ce5454affc82
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "8a9a4985709e0ca58977f599c243700ae6a00aa24a7a99b02bd7603661bbff7d",
-        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.2549e-3,
+        "source_digest": "a2d5d2cf17581d8182a5eefae35bb65bdef2008ed43ca1c5bd7e87741a59863e",
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.256e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "8a9a4985709e0ca58977f599c243700ae6a00aa24a7a99b02bd7603661bbff7d",
-        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.354e-3,
+        "source_digest": "a2d5d2cf17581d8182a5eefae35bb65bdef2008ed43ca1c5bd7e87741a59863e",
+        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.3523e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
-        "source_digest": "178a19af4e023fdbc0c8500e1b1b67ab278655cc48d577f2c3b763f09c3e32e5",
-        "valu_flop_per_event": 26558279, "events": 1 << 18, "kernel_s": 270.3e-3,
+        "source_digest": "ce584a9312e8f2e5edac704a60b3a23c4368bc848b750abc87cd58f439f1be8c",
+        "valu_flop_per_event": 26558279, "events": 1 << 18, "kernel_s": 269.8e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("uu_ttggg", "mixed"): {
-        "source_digest": "178a19af4e023fdbc0c8500e1b1b67ab278655cc48d577f2c3b763f09c3e32e5",
-        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1179463, "events": 1 << 18, "kernel_s": 151.8e-3,
+        "source_digest": "ce584a9312e8f2e5edac704a60b3a23c4368bc848b750abc87cd58f439f1be8c",
+        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1179463, "events": 1 << 18, "kernel_s": 151.7e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "b0cebae37be54c558bf9d99eee18afec789365f69755a4e49cb1cd420962a848",
-        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 174.7e-3,
+        "source_digest": "be014d4effe6349265820fc2456c56e6766b723ea61de0b9605cc6f54fac6a4f",
+        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.3e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "7e90b7b969cd46d506c829af0e03d64b4b6abb994aa9f8e6811a1e87dca555fc",
+        "source_digest": "9af26d68c4f6fc2dd5e43f3245bc929626959d764781376c99b53edabe924d98",
         "valu_flop_per_event": 3556867, "events": 1 << 20, "kernel_s": 93.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "7e90b7b969cd46d506c829af0e03d64b4b6abb994aa9f8e6811a1e87dca555fc",
+        "source_digest": "9af26d68c4f6fc2dd5e43f3245bc929626959d764781376c99b53edabe924d98",
         "valu_flop_per_event": 2810735, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 62.6e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "646999fb482f30ab6d66dfd6db71060be9a087587e4f3c96c0dd6426a859f3a8",
+        "source_digest": "7fc4c3d9df488902a29ef8622898683d4a06fcf249b73852ed2f3dc2ab90eb74",
         "valu_flop_per_event": 3790063, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 87.7e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }

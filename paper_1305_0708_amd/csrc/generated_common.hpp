@@ -92,18 +92,40 @@ __device__ __forceinline__ V stash_get(T (*s)[256], int off) {
   return v;
 }
 
+// A 64-bit value moved by a DPP row shift of N lanes: lane l of each row of 16
+// reads lane l - N of its row, or 0 where that lane is outside the row.
+template <int N>
+__device__ __forceinline__ double row_shr(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), 0x110 + N, 0xF, 0xF, true));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), 0x110 + N, 0xF, 0xF, true));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+// The value of one lane, read by every lane
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), lane));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), lane));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+// Sum over the 64 lanes of a wavefront in a fixed order, in registers: an
+// inclusive scan inside each row of 16 lanes by DPP row shifts of 1, 2, 4 and 8
+// lanes, then the rows' last lanes added in row order.  Every lane of the wave
+// must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += row_shr<1>(v);
+  v += row_shr<2>(v);
+  v += row_shr<4>(v);
+  v += row_shr<8>(v);
+  return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
+}
+
 // Deterministic per-block partial sums (w, w^2, accepted) for the cross
-// section: a fixed butterfly inside each 64-lane wavefront, then the waves in
+// section: a fixed-order sum inside each 64-lane wavefront, then the waves in
 // order.  Every thread of the block must call it; blk is the block's index
 // within its request.
 __device__ __forceinline__ void block_partials(const KernelArgs& a, int64_t blk, double wgt, bool acc) {
-  double s = wgt, s2 = wgt * wgt, c = acc ? 1.0 : 0.0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s += __shfl_xor(s, off, 64);
-    s2 += __shfl_xor(s2, off, 64);
-    c += __shfl_xor(c, off, 64);
-  }
+  const double s = wave_sum(wgt), s2 = wave_sum(wgt * wgt), c = wave_sum(acc ? 1.0 : 0.0);
   __shared__ double red[3][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {

@@ -47,6 +47,8 @@ double shfl_xor_f64(double v, int mask);
 float shfl_xor_f32(float v, int mask);
 int shfl_xor_i32(int v, int mask);
 int readfirstlane(int v);
+int update_dpp(int old, int src, int ctrl);
+int readlane(int v, int lane);
 emu_d4 mfma_f64(double a, double b, emu_d4 c);
 emu_f4 mfma_f32(float a, float b, emu_f4 c);
 void run_grid(dim3 grid, dim3 block, void (*entry)(void*), void* ctx);
@@ -67,6 +69,8 @@ inline int shfl_xor(int v, int m) { return shfl_xor_i32(v, m); }
 #define __any(x) emu::any(x)
 #define __shfl_xor(v, m, w) emu::shfl_xor((v), (m))
 #define __builtin_amdgcn_readfirstlane(x) emu::readfirstlane(x)
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu::update_dpp((old), (src), (ctrl))
+#define __builtin_amdgcn_readlane(v, l) emu::readlane((v), (l))
 #define __builtin_amdgcn_wave_barrier() emu::wave_barrier()
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64((a), (b), (c))

@@ -74,7 +74,7 @@ struct Fiber {
   uint64_t wait_gen = 0;
 };
 
-enum Kind { K_NONE, K_WAVE_BARRIER, K_ANY, K_SHFL_D, K_SHFL_F, K_SHFL_I, K_RFL, K_MFMA_D, K_MFMA_F, K_BLOCK };
+enum Kind { K_NONE, K_WAVE_BARRIER, K_ANY, K_SHFL_D, K_SHFL_F, K_SHFL_I, K_RFL, K_DPP, K_RL, K_MFMA_D, K_MFMA_F, K_BLOCK };
 
 struct WaveState {
   int arrived = 0;
@@ -215,6 +215,30 @@ int readfirstlane(int v) {
   WaveState& w = wave_op(K_RFL, [&](WaveState& s, int l) { s.in_i[l] = v; },
                          [](WaveState& s) {
                            for (int l = 0; l < kWave; ++l) s.out_i[l] = s.in_i[0];
+                         });
+  return w.out_i[lane];
+}
+
+// DPP move with a row shift right by N = ctrl - 0x110 lanes (the only control
+// the device code uses): lane l of each row of 16 reads lane l - N of its row;
+// lanes with no source in the row get 0 (bound_ctrl).
+int update_dpp(int old, int src, int ctrl) {
+  if (ctrl < 0x111 || ctrl > 0x11F) die("unsupported DPP control");
+  (void)old;
+  const int lane = int(g_cur->tid) % kWave;
+  WaveState& w = wave_op(K_DPP, [&](WaveState& s, int l) { s.in_i[l] = src; s.mask = ctrl - 0x110; },
+                         [](WaveState& s) {
+                           for (int l = 0; l < kWave; ++l)
+                             s.out_i[l] = (l % 16) >= s.mask ? s.in_i[l - s.mask] : 0;
+                         });
+  return w.out_i[lane];
+}
+
+int readlane(int v, int src_lane) {
+  const int lane = int(g_cur->tid) % kWave;
+  WaveState& w = wave_op(K_RL, [&](WaveState& s, int l) { s.in_i[l] = v; s.mask = src_lane; },
+                         [](WaveState& s) {
+                           for (int l = 0; l < kWave; ++l) s.out_i[l] = s.in_i[s.mask & (kWave - 1)];
                          });
   return w.out_i[lane];
 }
