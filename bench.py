@@ -42,8 +42,8 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "18711b7ee631a6977c777d46b80768076654313406e6ece811f09111c5ae5410",
-                 "fetch_kib": 927.9375, "fetch_scale": 2.0, "write_kib": 63269.375, "write_scale": 1.0,
+COUNTERS_FP64 = {"source_digest": "5e09ede578ce62faa308cfaed196634fbce329d7ad866377def333e956d41923",
+                 "fetch_kib": 850.625, "fetch_scale": 2.0, "write_kib": 63215.0, "write_scale": 1.0,
                  "flop_per_event": 3990, "flop_per_event_mixed": 2331}
 
 
@@ -56,37 +56,37 @@ COUNTERS_FP64 = {"source_digest": "18711b7ee631a6977c777d46b80768076654313406e6e
 KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
-        "source_digest": "a2d5d2cf17581d8182a5eefae35bb65bdef2008ed43ca1c5bd7e87741a59863e",
-        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.256e-3,
+        "source_digest": "b9b1fce845d836bd1039eff40ff5ebbfd9d44327065d42117192dcaadc27c0c8",
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.2576e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
-        "source_digest": "a2d5d2cf17581d8182a5eefae35bb65bdef2008ed43ca1c5bd7e87741a59863e",
-        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.3523e-3,
+        "source_digest": "b9b1fce845d836bd1039eff40ff5ebbfd9d44327065d42117192dcaadc27c0c8",
+        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.3551e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
-        "source_digest": "ce584a9312e8f2e5edac704a60b3a23c4368bc848b750abc87cd58f439f1be8c",
-        "valu_flop_per_event": 26558279, "events": 1 << 18, "kernel_s": 269.8e-3,
+        "source_digest": "b1f2e1a70a1d49c1dadd4c06833b6e8505d56f7fc784d3b793533866e5ec79ca",
+        "valu_flop_per_event": 26558279, "events": 1 << 18, "kernel_s": 270.7e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("uu_ttggg", "mixed"): {
-        "source_digest": "ce584a9312e8f2e5edac704a60b3a23c4368bc848b750abc87cd58f439f1be8c",
-        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1179463, "events": 1 << 18, "kernel_s": 151.7e-3,
+        "source_digest": "b1f2e1a70a1d49c1dadd4c06833b6e8505d56f7fc784d3b793533866e5ec79ca",
+        "valu_flop_per_event": 21721472, "fp64_flop_per_event": 1179463, "events": 1 << 18, "kernel_s": 151.8e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
-        "source_digest": "be014d4effe6349265820fc2456c56e6766b723ea61de0b9605cc6f54fac6a4f",
-        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.3e-3,
+        "source_digest": "5b85ba6f8532ce81d46e3714da91ba4bec0c80b05b387f10be4666f477c1b3bd",
+        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 173.2e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
-        "source_digest": "9af26d68c4f6fc2dd5e43f3245bc929626959d764781376c99b53edabe924d98",
+        "source_digest": "24d9abe3bc7ecc28d42dbbe3825031185b1e9827b5ad7a5d64b8ce331e623c95",
         "valu_flop_per_event": 3556867, "events": 1 << 20, "kernel_s": 93.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("gg_4g_ddm", "mixed"): {
-        "source_digest": "9af26d68c4f6fc2dd5e43f3245bc929626959d764781376c99b53edabe924d98",
+        "source_digest": "24d9abe3bc7ecc28d42dbbe3825031185b1e9827b5ad7a5d64b8ce331e623c95",
         "valu_flop_per_event": 2810735, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 62.6e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
     ("gg_4g_cf", "mixed"): {
-        "source_digest": "7fc4c3d9df488902a29ef8622898683d4a06fcf249b73852ed2f3dc2ab90eb74",
+        "source_digest": "b22b89d2ceeced9ef238bf79b940b1d4c77e76fdb346325a6d7b8b5c41311eec",
         "valu_flop_per_event": 3790063, "fp64_flop_per_event": 125396, "events": 1 << 20, "kernel_s": 87.7e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 kinematics beside)"},
 }

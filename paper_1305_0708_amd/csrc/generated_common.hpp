@@ -148,62 +148,4 @@ __device__ __forceinline__ void block_partials(const KernelArgs& a, int64_t blk,
   }
 }
 
-// Fixed-order reduction of per-block partial triples with Neumaier
-// compensation, by one block of 256 threads: thread t sums blocks t, t + 256,
-// ... in order, then a pairwise tree (t with t + 128, then t + 64, ...) combines
-// the 256 compensated sums.  Used by the single-request reduction and by the
-// serving engine's batched one, so both give the same bits.
-__device__ inline void reduce_triples(const double* partials, int64_t nblocks, double* out) {
-  __shared__ double sm[3][256];
-  __shared__ double cm[3][256];
-  const int t = threadIdx.x;
-  double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
-  int64_t b = t;
-  // four blocks' loads in flight at a time, added in block order
-  for (; b + 3 * 256 < nblocks; b += 4 * 256) {
-    double x[4][3];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) x[q][k] = partials[3 * (b + q * 256) + k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double u = s[k] + x[q][k];
-        c[k] += (fabs(s[k]) >= fabs(x[q][k])) ? ((s[k] - u) + x[q][k]) : ((x[q][k] - u) + s[k]);
-        s[k] = u;
-      }
-  }
-  for (; b < nblocks; b += 256) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double x = partials[3 * b + k];
-      const double u = s[k] + x;
-      c[k] += (fabs(s[k]) >= fabs(x)) ? ((s[k] - u) + x) : ((x - u) + s[k]);
-      s[k] = u;
-    }
-  }
-  for (int k = 0; k < 3; ++k) {
-    sm[k][t] = s[k];
-    cm[k][t] = c[k];
-  }
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double a = sm[k][t], x = sm[k][t + h];
-        const double u = a + x;
-        cm[k][t] += ((fabs(a) >= fabs(x)) ? ((a - u) + x) : ((x - u) + a)) + cm[k][t + h];
-        sm[k][t] = u;
-      }
-    }
-    __syncthreads();
-  }
-  if (t == 0)
-    for (int k = 0; k < 3; ++k) out[k] = sm[k][0] + cm[k][0];
-  __syncthreads();
-}
-
 }  // namespace heget

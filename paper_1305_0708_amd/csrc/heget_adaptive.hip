@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "generated_common.hpp"
+#include "reduce.hpp"
 #include "heget.h"
 #include "heget_internal.hpp"
 

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "heget_internal.hpp"
+#include "reduce.hpp"
 
 using heget::BatchTable;
 using heget::KernelArgs;
