@@ -316,8 +316,9 @@ heget_status heget_integrate(heget_process_t p, int64_t n, double sqrt_s, uint64
  * one handle share its per-block partial sums: make them on one stream, which
  * orders them (calls on two streams at once race).  A call with n above every
  * earlier call's grows that buffer, after waiting for `stream`.
- * Errors: HEGET_E_INVALID (null handle or sums_out, n < 2, sqrt_s <= 0),
- * HEGET_E_OOM, HEGET_E_HIP (a launch failed; the call enqueues nothing more). */
+ * Errors: HEGET_E_INVALID (null handle or sums_out, n < 2, sqrt_s <= 0,
+ * sums_out in pageable host memory, i.e. not known to HIP), HEGET_E_OOM,
+ * HEGET_E_HIP (a launch failed; the call enqueues nothing more). */
 heget_status heget_integrate_async(heget_process_t p, int64_t n, double sqrt_s, uint64_t seed, double* sums_out,
                                    void* stream);
 

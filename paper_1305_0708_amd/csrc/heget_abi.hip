@@ -941,6 +941,13 @@ heget_status heget_integrate_async(heget_process_t p, int64_t n, double sqrt_s, 
   g_err.clear();
   const heget_status rc = check_integrate_args(p, n, sqrt_s, sums_out);
   if (rc != HEGET_OK) return rc;
+  // the reduction writes sums_out from the device: refuse pageable host memory
+  // (unregistered with HIP) before anything is launched
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, sums_out) != hipSuccess || attr.type == hipMemoryTypeUnregistered) {
+    (void)hipGetLastError();
+    return fail(HEGET_E_INVALID, "sums_out must be device memory or pinned host memory");
+  }
   return enqueue_integrate(p, n, sqrt_s, seed, sums_out, static_cast<hipStream_t>(stream));
 }
 

@@ -336,12 +336,13 @@ def uu_ttbar_gluons(ng=3, sqrt_s=1000.0, name=None, parts=None):
     calls, n_amps, flows, jamp, colour = _build(ng)
     parts_mixed = 0
     if parts is None:
-        # the function division, measured on MI355X for three gluons: about 20
-        # amplitudes per device function in FP64 (20 parts: 291 ms per 2^18
-        # events; 10 parts: 506 ms), about 40 in FP32 (10 parts: 164 ms; 20:
-        # 184 ms).  Two gluons: two parts, where one would do, so that the small
-        # process runs the divided code too.
-        parts, parts_mixed = (-(-n_amps // 20), -(-n_amps // 40)) if ng >= 3 else (2 if ng == 2 else 1, 0)
+        # the function division, measured on MI355X for three gluons (393
+        # amplitudes, ms per 2^18 events): about 15 amplitudes per device
+        # function in FP64 (27 parts: 240 ms; 24: 245; 20: 270; 10: 506), about
+        # 57 in FP32 (7 parts: 146 ms; 6: 149; 8: 148; 10: 152; 5: 155).  Two
+        # gluons: two parts, where one would do, so that the small process runs
+        # the divided code too.
+        parts, parts_mixed = (-(-n_amps // 15), -(-n_amps // 57)) if ng >= 3 else (2 if ng == 2 else 1, 0)
     legs = [Leg(F, True, +1, colour=3, name="u"), Leg(F, True, -1, colour=3, name="ubar"),
             Leg(F, False, +1, particle=P_TOP, colour=3, name="t"),
             Leg(F, False, -1, particle=P_TOP, colour=3, name="tbar")]

@@ -147,6 +147,17 @@ hipError_t hipHostFree(void* p);
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k);
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st = nullptr);
 hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t st = nullptr);
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2 };
+struct hipPointerAttribute_t {
+  hipMemoryType type;
+  int device;
+  void* devicePointer;
+  void* hostPointer;
+  int isManaged;
+  unsigned allocationFlags;
+};
+// every pointer is device memory to the emulator (its device memory is host memory)
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p);
 hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipStreamQuery(hipStream_t s);
 hipError_t hipDeviceSynchronize();

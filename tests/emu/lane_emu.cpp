@@ -363,6 +363,15 @@ hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
   memset(d, v, n);
   return hipSuccess;
 }
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
+  a->type = hipMemoryTypeDevice;
+  a->device = 0;
+  a->devicePointer = const_cast<void*>(p);
+  a->hostPointer = const_cast<void*>(p);
+  a->isManaged = 0;
+  a->allocationFlags = 0;
+  return hipSuccess;
+}
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamQuery(hipStream_t) { return hipSuccess; }
 hipError_t hipDeviceSynchronize() { return hipSuccess; }

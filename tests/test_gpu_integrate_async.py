@@ -23,3 +23,38 @@ def test_queued_steps_equal_synchronous_ones(name, prec):
         ref = p.integrate(n, seed=seed)
         assert got[k] == [ref["sum_w"], ref["sum_w2"], float(ref["n_accepted"])], (k, n, seed)
         assert p.result_from_sums(got[k], n) == ref
+
+
+def test_pageable_host_sums_are_refused():
+    """sums_out in pageable host memory is refused with HEGET_E_INVALID before
+    any launch.  The test asks HIP itself first and calls the library only when
+    HIP reports the pointer unregistered, the case the library refuses, so no
+    kernel can be launched at pageable memory."""
+    import ctypes
+    import numpy as np
+    import torch
+    import paper_1305_0708_amd as H
+    from paper_1305_0708_amd import _lib, processes
+
+    class Attr(ctypes.Structure):
+        _fields_ = [("type", ctypes.c_int), ("device", ctypes.c_int), ("devicePointer", ctypes.c_void_p),
+                    ("hostPointer", ctypes.c_void_p), ("isManaged", ctypes.c_int), ("allocationFlags", ctypes.c_uint)]
+    print("integrate_async pageable sums", flush=True)
+    p = H.Process(processes.by_name("ee_mumu"), precision="fp64")
+    host = np.zeros(3)
+    hip = ctypes.CDLL("libamdhip64.so")
+    a = Attr()
+    st = hip.hipPointerGetAttributes(ctypes.byref(a), ctypes.c_void_p(host.ctypes.data))
+    hip.hipGetLastError()
+    if st == 0 and a.type != 0:
+        pytest.skip(f"HIP reports this host array as memory type {a.type}")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = p._lib.heget_integrate_async(p._h, 4096, 200.0, 1, ctypes.c_void_p(host.ctypes.data), stream)
+    assert rc == _lib.HEGET_E_INVALID
+    # pinned host memory is accepted, and gives the same sums as device memory
+    pinned = torch.zeros(3, dtype=torch.float64, pin_memory=True)
+    dev = torch.zeros(3, dtype=torch.float64, device="cuda")
+    assert p._lib.heget_integrate_async(p._h, 4096, 200.0, 1, ctypes.c_void_p(pinned.data_ptr()), stream) == 0
+    p.integrate_async(4096, dev, seed=1, sqrt_s=200.0)
+    torch.cuda.synchronize()
+    assert pinned.tolist() == dev.cpu().tolist() and pinned[2].item() == 4096
