@@ -93,8 +93,8 @@ def gg_ttbar_6f_bw(sqrt_s=1000.0):
             (P_W, BW, 3, 4),                   # W+ -> e+ nu_e
             (P_W, BW, 6, 7)]                   # W- -> mu- nu_mu~
     # with the resonance tree's phase space in the kernel: the whole nest unrolled
-    # at one wave per SIMD (per 2^20 events, FP64 / mixed: 0.213 / 0.160 ms; two
-    # waves 0.226 / 0.162 ms)
+    # at one wave per SIMD (per 2^20 events, FP64 / mixed: 0.189 / 0.148 ms; two
+    # waves 0.201 / 0.148 ms)
     return dataclasses.replace(gg_ttbar_6f(sqrt_s), name="gg_ttbar_6f_bw", ps_tree=tree,
                                ps_window=20.0, nest_unroll=256, waves_per_simd=1, stash_words=64).validate()
 
