@@ -246,7 +246,12 @@ class Gen:
         w("// kernels: one workspace slot per block), or, for a fused launch of the")
         w("// serving engine, the virtual blocks of its batch table")
         w("template <class T>")
-        lb = f"256, {p.waves_per_simd}" if p.waves_per_simd > 1 else "256"
+        w64, w32 = p.waves_per_simd, p.waves_per_simd_mixed or p.waves_per_simd
+        if w64 != w32:
+            # the FP64 and the FP32 kernel compiled for different occupancies
+            lb = f"256, sizeof(T) == 8 ? {w64} : {w32}"
+        else:
+            lb = f"256, {w64}" if w64 > 1 else "256"
         w(f"__global__ __launch_bounds__({lb}) void amp_{p.name}(KernelArgs a) {{")
         if p.uses_colour_mfma():
             w(f"  colour_stage<T, {(p.n_flows + 3) // 4}, {(p.n_flows + 15) // 16}, {self.cterm_cap()}>(a);")

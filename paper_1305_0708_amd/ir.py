@@ -192,6 +192,9 @@ class Process:
     # per SIMD two blocks must fit the CU's LDS)
     waves_per_simd: int = 1
     stash_words: int = 64
+    # Waves per SIMD of the mixed-precision (FP32 chain) kernel when it differs
+    # from the FP64 kernel's (0: the same); its registers are half as wide
+    waves_per_simd_mixed: int = 0
     # Ordering templates: the number of innermost helicity loops of one
     # ordering's nest that the kernel unrolls (a code-generation setting)
     template_unroll: int = 0
@@ -261,6 +264,8 @@ class Process:
             raise ValueError(f"unknown division {self.division}")
         if self.waves_per_simd not in (1, 2, 3, 4) or not 0 <= self.stash_words <= 64:
             raise ValueError("waves_per_simd in 1..4, stash_words in 0..64")
+        if self.waves_per_simd_mixed not in (0, 1, 2, 3, 4):
+            raise ValueError("waves_per_simd_mixed in 0..4")
         if self.row_parts < 1 or self.row_parts_mixed < 0:
             raise ValueError("row_parts >= 1, row_parts_mixed >= 0")
         if self.helicity_schedule not in ("nest", "rows"):
