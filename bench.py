@@ -436,8 +436,9 @@ def serve_leg(n_requests, rate=200.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    # 50 steps of C1 time about 6 ms: long enough that one host stall does not move the average
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests in the serving replay (0: skip it)")
@@ -606,17 +607,19 @@ def main():
                                           extended=True)
     c2 = processes.by_name("gg_4g")
     c2d = processes.by_name("gg_4g_ddm")
+    # C2 launches take 60-180 ms each: at most 10 timed steps per leg
+    c2_steps, c2_warmup = min(args.steps, 10), min(args.warmup, 2)
     legs["c2"] = config_leg(
         torch, H, c2, "g g -> g g g g, sqrt_s_hat = 1 TeV, pT > 20 GeV and Delta R > 0.4 by rejection, 2^20 RAMBO "
         "events per step, 64 helicity combinations, 120 trace-basis flows, dense 120 x 120 colour form on MFMA",
-        args.steps, args.warmup, seed=0x48454747)
+        c2_steps, c2_warmup, seed=0x48454747)
     legs["c2"]["compressed"] = config_leg(
         torch, H, processes.by_name("gg_4g_cf"), f"the same events through the same 120 trace-basis flows, "
         f"{compression_text(processes.by_name('gg_4g_cf'))}; mixed precision runs it on VALU, FP64 keeps the dense "
-        "MFMA form", args.steps, args.warmup, precisions=("mixed",), seed=0x48454747)
+        "MFMA form", c2_steps, c2_warmup, precisions=("mixed",), seed=0x48454747)
     legs["c2"]["ddm_basis"] = config_leg(
         torch, H, c2d, "the same events and |M|^2 through the 24-flow DDM basis, colour form on VALU",
-        args.steps, args.warmup, seed=0x48454747)
+        c2_steps, c2_warmup, seed=0x48454747)
     if not args.no_cpu_baseline:
         legs["c2"]["oracle"] = oracle_leg(torch, H, O, c2, "GG_4G", {}, 4, 0x48454747, cut=(20.0, 0.4))
         legs["c2"]["ddm_basis"]["oracle"] = oracle_leg(torch, H, O, c2d, "GG_4G", {}, 4, 0x48454747,
