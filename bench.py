@@ -42,8 +42,8 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 #    model still counts; the same from SQ_INSTS_VALU_*_F32 for the mixed kernel.
 # All were re-taken on the kernel with the bra sums accumulated bra by bra
 # (the same values as on the kernel before it).
-COUNTERS_FP64 = {"source_digest": "5e09ede578ce62faa308cfaed196634fbce329d7ad866377def333e956d41923",
-                 "fetch_kib": 878.1875, "fetch_scale": 2.0, "write_kib": 62103.625, "write_scale": 1.0,
+COUNTERS_FP64 = {"source_digest": "a6d472db08ef9e1a5f8d879906a6034d4bcf3e5b4b04639feffeaf8ecf2bc8bf",
+                 "fetch_kib": 832.5625, "fetch_scale": 2.0, "write_kib": 63189.25, "write_scale": 1.0,
                  "flop_per_event": 3990, "flop_per_event_mixed": 2331}
 
 
@@ -57,11 +57,11 @@ KERNEL_COUNTERS = {
     # u d -> u d H H -> 4b, 2^21 events per launch (profiles/amp_ud_udhh_4b_2p21ev.md)
     ("ud_udhh_4b", "mixed"): {
         "source_digest": "b9b1fce845d836bd1039eff40ff5ebbfd9d44327065d42117192dcaadc27c0c8",
-        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.2552e-3,
+        "valu_flop_per_event": 3004, "fp64_flop_per_event": 2219, "events": 1 << 21, "kernel_s": 0.2567e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 denominators and reductions beside)"},
     ("ud_udhh_4b", "fp64"): {
         "source_digest": "b9b1fce845d836bd1039eff40ff5ebbfd9d44327065d42117192dcaadc27c0c8",
-        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.3526e-3,
+        "valu_flop_per_event": 5223, "events": 1 << 21, "kernel_s": 0.3522e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     # u ubar -> t tbar g g g, 2^18 events per launch (profiles/amp_uu_ttggg_2p18ev.md)
     ("uu_ttggg", "fp64"): {
@@ -70,12 +70,12 @@ KERNEL_COUNTERS = {
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64"},
     ("uu_ttggg", "mixed"): {
         "source_digest": "403c91b4612e1d795cd305f62fcab31dc1c0cf2a6a88f44eeb8ce20437242777",
-        "valu_flop_per_event": 20706944, "fp64_flop_per_event": 909127, "events": 1 << 18, "kernel_s": 146.1e-3,
+        "valu_flop_per_event": 20706944, "fp64_flop_per_event": 909127, "events": 1 << 18, "kernel_s": 145.6e-3,
         "source": "executed FP32 flops from SQ_INSTS_VALU_*_F32 (FP64 momenta and denominators beside)"},
     # g g -> g g g g, 2^20 events per launch (profiles/amp_gg_4g_mfma_2p20ev.md)
     ("gg_4g", "fp64"): {
         "source_digest": "5b85ba6f8532ce81d46e3714da91ba4bec0c80b05b387f10be4666f477c1b3bd",
-        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 172.7e-3,
+        "valu_flop_per_event": 3613187, "mfma_flop_per_event": 2097152, "events": 1 << 20, "kernel_s": 174.6e-3,
         "source": "executed FP64 flops from SQ_INSTS_VALU_*_F64; MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_F64"},
     ("gg_4g_ddm", "fp64"): {
         "source_digest": "24d9abe3bc7ecc28d42dbbe3825031185b1e9827b5ad7a5d64b8ce331e623c95",

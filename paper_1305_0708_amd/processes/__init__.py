@@ -74,10 +74,11 @@ def gg_ttbar_6f(sqrt_s=1000.0):
     # drops the arithmetic on the structural zeros), compiled for two waves per
     # SIMD; measured on MI355X per 2^20 events (FP64 / mixed): 32 combinations
     # 0.481 / 0.316 ms, 128 0.229 / 0.150 ms, 256 0.170 / 0.138 ms, 256 at two
-    # waves per SIMD 0.142 / 0.138 ms
+    # waves per SIMD 0.142 / 0.138 ms; on the current kernels the FP32 kernel at
+    # three waves (168 registers, 11 spilled) 0.1001 ms against 0.1024 at two
     return Process("gg_ttbar_6f", legs, cpl, calls, n_amps=3, n_flows=2, jamp=jamp, colour=colour,
                    helicities=ir.all_helicities(legs), sqrt_s=sqrt_s, n_a_n_b=64, symmetry=1,
-                   nest_unroll=256, waves_per_simd=2, stash_words=36).validate()
+                   nest_unroll=256, waves_per_simd=2, stash_words=36, waves_per_simd_mixed=3).validate()
 
 
 def gg_ttbar_6f_bw(sqrt_s=1000.0):
@@ -96,7 +97,8 @@ def gg_ttbar_6f_bw(sqrt_s=1000.0):
     # at one wave per SIMD (per 2^20 events, FP64 / mixed: 0.189 / 0.148 ms; two
     # waves 0.201 / 0.148 ms)
     return dataclasses.replace(gg_ttbar_6f(sqrt_s), name="gg_ttbar_6f_bw", ps_tree=tree,
-                               ps_window=20.0, nest_unroll=256, waves_per_simd=1, stash_words=64).validate()
+                               ps_window=20.0, nest_unroll=256, waves_per_simd=1, stash_words=64,
+                               waves_per_simd_mixed=0).validate()
 
 
 def ud_udhh_4b(sqrt_s=2000.0):

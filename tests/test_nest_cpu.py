@@ -105,7 +105,10 @@ def test_c1_tables_and_stash_in_the_generated_kernel():
     assert len(nest.unrolled_levels(sc1)) == 8
     src1 = codegen.Gen(c1).emit()
     assert "t12_" not in src1 and "stash_put(" not in src1
-    assert "__launch_bounds__(256, 2) void amp_gg_ttbar_6f" in src1
+    # two waves per SIMD for the FP64 kernel, three for the FP32 one
+    assert "__launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void amp_gg_ttbar_6f" in src1
+    bw = codegen.Gen(processes.by_name("gg_ttbar_6f_bw")).emit()
+    assert "__launch_bounds__(256) void amp_gg_ttbar_6f_bw" in bw
     c5 = dataclasses.replace(c1, nest_unroll=32)
     sc5 = nest.schedule(c5)
     assert len(nest.unrolled_levels(sc5)) == 5
